@@ -1,0 +1,409 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage it checks.  None of them re-types the oracle's own
+formula: they check moments, closed forms, special cases, symmetries and the
+paper's own statements (e.g. a_v = 1/dx on a flat wall, Sec. 2.2.3).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import diagnostics as odiag
+from oracle import lattice as lat
+from oracle import model as om
+from tests.helpers import oracle_for
+
+LATTICES = [lat.D2Q9, lat.D3Q19]
+
+
+# ---------------------------------------------------------------- P1 lattice
+@pytest.mark.parametrize("L", LATTICES, ids=lambda L: L.name)
+def test_lattice_moments(L):
+    """Sec. 2.1.2 weights: isotropy up to fourth order with c_s^2 = 1/3."""
+    c = L.c.astype(float)
+    D = L.D
+    assert abs(L.w.sum() - 1.0) < 1e-15
+    assert np.abs(L.w @ c).max() < 1e-15
+    assert np.abs(np.einsum("q,qa,qb->ab", L.w, c, c) - np.eye(D) / 3).max() < 1e-15
+    assert np.abs(np.einsum("q,qa,qb,qc->abc", L.w, c, c, c)).max() < 1e-15
+    d = np.eye(D)
+    iso = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+           + np.einsum("ad,bc->abcd", d, d)) / 9
+    assert np.abs(np.einsum("q,qa,qb,qc,qd->abcd", L.w, c, c, c, c) - iso).max() < 1e-15
+    # opposite table is an involution reversing the vector
+    assert np.array_equal(L.c[L.opp], -L.c)
+    assert np.array_equal(L.opp[L.opp], np.arange(L.Q))
+    # distinct vectors, |c|^2 in {0,1,2}
+    assert len({tuple(v) for v in L.c}) == L.Q
+    assert set((L.c ** 2).sum(axis=1)) == {0, 1, 2}
+
+
+def test_lattice_paper_d2q9_order():
+    """Eq. (ci) as printed: i = 1..4 at angles (i-2) pi/2, i.e. (0,-1), (1,0), (0,1), (-1,0)."""
+    assert [tuple(v) for v in lat.D2Q9.c[1:5]] == [(0, -1), (1, 0), (0, 1), (-1, 0)]
+    assert [tuple(v) for v in lat.D2Q9.c[5:9]] == [(1, 1), (-1, 1), (-1, -1), (1, -1)]
+
+
+@pytest.mark.parametrize("L,expect", [(lat.D2Q9, {0: -2.0, 1: -0.5, 2: 1.0}),
+                                      (lat.D3Q19, {0: -2.5, 1: -1.0, 2: 0.5})],
+                         ids=["D2Q9", "D3Q19"])
+def test_source_coefficients(L, expect):
+    """Eq. (F_i) bracket, evaluated by hand per speed class |c|^2."""
+    c2 = (L.c ** 2).sum(axis=1)
+    for i in range(L.Q):
+        assert abs(L.k[i] - expect[int(c2[i])]) < 1e-15
+
+
+# ---------------------------------------------------------------- P2-P4 local physics
+def _rand_state(L, n=7, seed=0):
+    rng = np.random.default_rng(seed)
+    u = rng.normal(0, 0.05, (L.D, n))
+    rho = rng.uniform(1, 10, n)
+    p = rng.normal(0, 1e-3, n)
+    return u, rho, p, rng
+
+
+@pytest.mark.parametrize("L", LATTICES, ids=lambda L: L.name)
+def test_f_equilibrium_moments(L):
+    """Eq. (feq_i): sum f_eq = 0, sum c f_eq = rho u, sum c c f_eq = p I + rho u u."""
+    u, rho, p, _ = _rand_state(L)
+    feq = om.f_equilibrium(L, p, rho, u)
+    c = L.c.astype(float)
+    assert np.abs(feq.sum(axis=0)).max() < 1e-15
+    assert np.abs(np.einsum("qa,qn->an", c, feq) - rho * u).max() < 1e-15
+    P2 = np.einsum("qa,qb,qn->abn", c, c, feq)
+    want = p[None, None, :] * np.eye(L.D)[:, :, None] + rho * np.einsum("an,bn->abn", u, u)
+    assert np.abs(P2 - want).max() < 1e-15
+
+
+@pytest.mark.parametrize("L", LATTICES, ids=lambda L: L.name)
+def test_g_equilibrium_moments(L):
+    """Eq. (H_i): sum g_eq = phi, sum c g_eq = 0, sum c c g_eq = alpha mu c_s^2 I."""
+    rng = np.random.default_rng(1)
+    phi = rng.uniform(0, 1, 5)
+    mu = rng.normal(0, 1e-3, 5)
+    geq = om.g_equilibrium(L, phi, 1.7, mu)
+    c = L.c.astype(float)
+    assert np.abs(geq.sum(axis=0) - phi).max() < 1e-15
+    assert np.abs(np.einsum("qa,qn->an", c, geq)).max() < 1e-18
+    want = 1.7 * mu / 3.0
+    got = np.einsum("qa,qb,qn->abn", c, c, geq)
+    for a in range(L.D):
+        assert np.abs(got[a, a] - want).max() < 1e-17
+    assert np.abs(got - got * np.eye(L.D)[:, :, None]).max() < 1e-18
+
+
+@pytest.mark.parametrize("L", LATTICES, ids=lambda L: L.name)
+def test_phase_source_moments(L):
+    """Eq. (F_i): sum G_i = -u.grad(phi); first and second moments vanish."""
+    s = np.array([0.3, -1.2, 2e-4])
+    G = om.phase_source(L, s)
+    c = L.c.astype(float)
+    assert np.abs(G.sum(axis=0) + s).max() < 1e-15
+    assert np.abs(np.einsum("qa,qn->an", c, G)).max() < 1e-16
+    assert np.abs(np.einsum("qa,qb,qn->abn", c, c, G)).max() < 1e-15
+
+
+@pytest.mark.parametrize("L", LATTICES, ids=lambda L: L.name)
+def test_forcing_moments(L):
+    """Eq. (GGi) as read: sum F_i = (1 - 1/2tau) u.grad rho (the half of it appears in
+    the pressure of Sec. 2.1.2); sum c F_i = (1 - 1/2tau) F; sum c c F_i =
+    (1 - 1/2tau) c_s^2 (u.grad rho I + u grad rho + grad rho u)."""
+    u, rho, p, rng = _rand_state(L, 6, 2)
+    grho = rng.normal(0, 0.3, (L.D, 6))
+    F = rng.normal(0, 1e-3, (L.D, 6))
+    tau = rng.uniform(0.6, 1.5, 6)
+    Fi = om.force_distribution(L, tau, u, grho, F)
+    c = L.c.astype(float)
+    pre = 1 - 0.5 / tau
+    ug = (u * grho).sum(axis=0)
+    assert np.abs(Fi.sum(axis=0) - pre * ug).max() < 1e-15
+    assert np.abs(np.einsum("qa,qn->an", c, Fi) - pre * F).max() < 1e-16
+    want = (ug[None, None] * np.eye(L.D)[:, :, None] + np.einsum("an,bn->abn", u, grho)
+            + np.einsum("an,bn->abn", grho, u)) / 3 * pre
+    assert np.abs(np.einsum("qa,qb,qn->abn", c, c, Fi) - want).max() < 1e-15
+
+
+# ---------------------------------------------------------------- P5 stencils
+@pytest.mark.parametrize("D", [2, 3])
+def test_stencils_exact_on_polynomials(D):
+    """Eq. (gradient) is exact on quadratics and Eq. (Laplace) on cubics."""
+    L = lat.D2Q9 if D == 2 else lat.D3Q19
+    shape = (9, 8) if D == 2 else (7, 6, 5)
+    grid = om.Grid(shape, (False,) * D)
+    X = [grid.coords[d].astype(float) for d in range(D)]
+    rng = np.random.default_rng(3)
+    a = rng.normal(size=(D, D))
+    b = rng.normal(size=D)
+    quad = sum(b[i] * X[i] for i in range(D)) + sum(a[i, j] * X[i] * X[j]
+                                                     for i in range(D) for j in range(D))
+    grad = om.gradient(grid, L, quad)
+    want = [b[i] + sum((a[i, j] + a[j, i]) * X[j] for j in range(D)) for i in range(D)]
+    cubic = X[0] ** 3 + 2 * X[0] * X[1] ** 2 - X[1] ** 3 + (X[2] ** 3 * X[0] if D == 3 else 0)
+    lap = om.laplacian(grid, L, cubic)
+    lwant = 6 * X[0] + 4 * X[0] - 6 * X[1] + (6 * X[2] * X[0] if D == 3 else 0)
+    interior = np.ones(grid.N, bool)
+    for d in range(D):
+        interior &= (grid.coords[d] >= 1) & (grid.coords[d] < grid.P[d] - 1)
+    for i in range(D):
+        assert np.abs(grad[i] - want[i])[interior].max() < 1e-11
+    assert np.abs(lap - lwant)[interior].max() < 1e-10
+
+
+# ---------------------------------------------------------------- P6, P7 wall treatment
+def test_effective_area_flat_wall():
+    """Sec. 2.2.3: a_v = 1/dx on a flat wall, split 0.5 + 0.5 over the boundary
+    layer and the first fluid layer (the two-layer structure)."""
+    c = workloads.flat_droplet_case(16, 12, 3.0, 60.0)
+    o = oracle_for(c)
+    av = o.domain(o.a_v)
+    assert np.allclose(av[0], 0.5, atol=1e-15) and np.allclose(av[1], 0.5, atol=1e-15)
+    assert np.allclose(av[-1], 0.5, atol=1e-15) and np.allclose(av[-2], 0.5, atol=1e-15)
+    assert np.abs(av[2:-2]).max() == 0.0
+    assert np.allclose(av.sum(axis=0), 2.0)       # two walls of one unit each per column
+
+
+def test_node_classes_flat_and_staircase():
+    c = workloads.flat_droplet_case(16, 12, 3.0, 60.0)
+    o = oracle_for(c)
+    zeta, ghost = o.domain(o.zeta), o.domain(o.ghost)
+    assert zeta.all()                              # solid rows are boundary nodes
+    assert np.array_equal(o.domain(o.boundary)[[0, -1]], np.ones((2, 16), bool))
+    g = o.grid.to_domain  # ghosts live in the padding rows just outside
+    full_ghost = o.ghost.reshape(o.grid.P[::-1])
+    assert full_ghost[1].all() and full_ghost[-2].all() and not ghost.any()
+    # 45 degree staircase: every ghost has a zeta = 1 lattice neighbour, boundary
+    # nodes are mask-solid, fluid nodes are not
+    m = workloads.inclined_plane((20, 20), (10.0, 10.0), 45.0)
+    c2 = dict(c, shape=(20, 20), mask=m, phi0=np.zeros((20, 20)))
+    o2 = oracle_for(c2)
+    b = o2.domain(o2.boundary)
+    assert np.all(m[b] == 1) and np.all(m[o2.domain(o2.eps) > 0] == 0)
+
+
+def test_ghost_mean_flat_wall():
+    """Sec. 2.2.2 ghost mean: on a flat wall each ghost averages the three boundary
+    nodes below/above it (2D, b = 9 offsets, zeta = 1 only)."""
+    c = workloads.flat_droplet_case(16, 10, 3.0, 60.0)
+    o = oracle_for(c)
+    rng = np.random.default_rng(5)
+    phi = np.where(o.zeta, rng.uniform(0, 1, o.grid.N), 0.0)
+    full = om.ghost_fill(o.grid, phi, o.zeta, o.ghost).reshape(o.grid.P[::-1])
+    ph = phi.reshape(o.grid.P[::-1])
+    row_b = ph[2]                                   # boundary row y = 0 (padded row 2)
+    want = (np.roll(row_b, 1) + row_b + np.roll(row_b, -1)) / 3.0
+    assert np.abs(full[1] - want).max() < 1e-15
+
+
+def test_ghost_mean_3d_uses_27_block():
+    c = workloads.inclined_droplet_case_3d(n=10, radius=3.0, width=3.0)
+    o = oracle_for(c)
+    rng = np.random.default_rng(6)
+    phi = np.where(o.zeta, rng.uniform(0, 1, o.grid.N), 0.0)
+    full = om.ghost_fill(o.grid, phi, o.zeta, o.ghost)
+    gidx = np.flatnonzero(o.ghost)[:20]
+    for n in gidx:                                   # brute force over the 3x3x3 block
+        num = den = 0.0
+        for off in itertools.product((-1, 0, 1), repeat=3):
+            q = [o.grid.coords[d][n] + off[d] for d in range(3)]
+            if any(q[d] < 0 or q[d] >= o.grid.P[d] for d in range(3)):
+                continue
+            m = q[0] + o.grid.P[0] * (q[1] + o.grid.P[1] * q[2])
+            if o.zeta[m]:
+                num += phi[m]
+                den += 1
+        assert abs(full[n] - num / den) < 1e-15
+
+
+# ---------------------------------------------------------------- P8-P12 invariants
+@pytest.mark.parametrize("value", [0.0, 1.0])
+def test_uniform_phase_fixed_point(value):
+    """phi uniform at a minimum of the double well, walls present: mu = 0, F = 0,
+    u = 0, and the populations are a fixed point of the step."""
+    c = workloads.flat_droplet_case(24, 12, 3.0, 45.0)
+    c["phi0"] = np.full_like(c["phi0"], value)
+    o = oracle_for(c)
+    g0, f0 = o.g.copy(), o.f.copy()
+    o.step(20)
+    assert np.array_equal(o.g, g0) and np.array_equal(o.f, f0)
+
+
+def test_mass_budget_identity():
+    """Collision keeps sum g_eq = phi and streaming with bounce-back permutes
+    populations, so M(t+1) - M(t) = -sum (1.5 s(t) - 0.5 s(t-1))."""
+    c = workloads.flat_droplet_case(48, 24, 8.0, 50.0)
+    o = oracle_for(c)
+    for _ in range(30):
+        m0 = o.mass()
+        o.step()
+        assert abs(o.mass() - m0 + o.source_sum()) < 1e-12 * m0
+
+
+def test_mass_exact_without_flow():
+    """u = 0 everywhere (uniform density, no force): s = 0, so mass is exact."""
+    c = workloads.flat_droplet_case(32, 16, 6.0, 60.0)
+    c["phi0"] = np.full_like(c["phi0"], 0.37)   # uniform: grad phi = 0 except at walls
+    c["theta_deg"] = 90.0
+    o = oracle_for(c)
+    m0 = o.mass()
+    o.step(50)
+    assert abs(o.mass() - m0) < 1e-12 * m0
+
+
+def test_phase_inversion_symmetry():
+    """With rho_l = rho_g, (phi0, theta) -> (1 - phi0, 180 - theta) maps phi to 1 - phi
+    and leaves u, p unchanged (the double well, the wall term and G_i are odd)."""
+    c = workloads.flat_droplet_case(40, 20, 7.0, 65.0)
+    a = oracle_for(c, rho_l=2.0, rho_g=2.0)
+    c2 = dict(c, phi0=1.0 - c["phi0"], theta_deg=180.0 - 65.0)
+    b = oracle_for(c2, rho_l=2.0, rho_g=2.0)
+    a.step(60)
+    b.step(60)
+    fa, fb = a.fields(), b.fields()
+    z = a.domain(a.zeta)
+    assert np.abs(fa["phi"] + fb["phi"] - 1.0)[z].max() < 1e-12
+    assert np.abs(fa["u"] - fb["u"]).max() < 1e-15
+    assert np.abs(fa["p"] - fb["p"]).max() < 1e-15
+    assert np.abs(fa["mu"] + fb["mu"])[z].max() < 1e-15
+
+
+def test_translation_invariance():
+    c = workloads.flat_droplet_case(40, 20, 7.0, 65.0)
+    a = oracle_for(c)
+    b = oracle_for(dict(c, phi0=np.roll(c["phi0"], 11, axis=1)))
+    a.step(40)
+    b.step(40)
+    assert np.array_equal(np.roll(a.fields()["phi"], 11, axis=1), b.fields()["phi"])
+
+
+def test_mirror_symmetry():
+    """Reflection x -> -x about the droplet axis."""
+    c = workloads.flat_droplet_case(41, 20, 7.0, 65.0)
+    c["phi0"] = workloads.droplet((41, 20), (20.0, 0.5), 7.0, 4.0)
+    o = oracle_for(c)
+    o.step(60)
+    f = o.fields()
+    assert np.abs(f["phi"] - f["phi"][:, ::-1]).max() < 1e-12
+    assert np.abs(f["u"][0] + f["u"][0][:, ::-1]).max() < 1e-15
+    assert np.abs(f["u"][1] - f["u"][1][:, ::-1]).max() < 1e-15
+
+
+# ---------------------------------------------------------------- P13-P15 closed forms
+def _slab_case(W, phi0, ny):
+    return dict(lattice="D2Q9", shape=(4, ny), periodic=(True, True),
+                mask=np.zeros((ny, 4), np.uint8), phi0=phi0, sigma=1e-2, width=W,
+                theta_deg=90.0)
+
+
+def test_tanh_profile_is_equilibrium():
+    """The planar profile 0.5 + 0.5 tanh(2x/W) (Eq. initialphi) makes the bulk and
+    gradient terms of mu (Eq. chemical_potencial2) cancel exactly in the continuum
+    when W = sqrt(8 kappa / beta).  On the lattice the residual is the stencil's
+    O(W^-2) error: small against beta and falling ~4x when W doubles.  A profile of
+    the wrong width leaves an O(beta) chemical potential."""
+    res = {}
+    for W in (4.0, 8.0, 6.0 * 1.5):
+        Wc = 4.0 if W == 9.0 else W               # 9.0: a 1.5x too wide profile at W = 6
+        Wc = 6.0 if W == 9.0 else Wc
+        ny = int(24 * W)
+        y = np.arange(ny)
+        a, b = ny // 4, 3 * ny // 4
+        prof = np.where(y < ny // 2, 0.5 + 0.5 * np.tanh(2 * (y - a) / W),
+                        0.5 - 0.5 * np.tanh(2 * (y - b) / W))
+        o = oracle_for(_slab_case(Wc, prof[:, None] * np.ones((1, 4)), ny))
+        beta = om.beta_kappa(1e-2, Wc)[0]
+        res[W] = np.abs(o.fields()["mu"]).max() / beta
+    assert res[4.0] < 0.05
+    assert res[8.0] < 0.3 * res[4.0]
+    assert res[9.0] > 20 * res[8.0]
+    # and the profile stays put under the full dynamics
+    W, ny = 4.0, 96
+    y = np.arange(ny)
+    prof = np.where(y < 48, 0.5 + 0.5 * np.tanh(2 * (y - 24) / W),
+                    0.5 - 0.5 * np.tanh(2 * (y - 72) / W))
+    o = oracle_for(_slab_case(W, prof[:, None] * np.ones((1, 4)), ny))
+    o.step(1500)
+    # the discrete equilibrium differs from the continuum tanh by O(W^-2)
+    assert np.abs(o.fields()["phi"][:, 0] - prof).max() < 1e-2
+
+
+def test_contact_angle_ninety_keeps_semicircle():
+    """cos(theta) = 0 switches the wall term off (Eq. chemical_potencial2): the
+    semicircle on a flat wall stays at 90 degrees."""
+    c = workloads.flat_droplet_case(96, 48, 15.0, 90.0)
+    o = oracle_for(c)
+    o.step(1500)
+    f = o.fields()
+    th, centre, R, n = odiag.contact_angle(f["phi"], o.domain(o.zeta), c["wall"], 4.0)
+    assert abs(th - 90.0) < 0.5
+    assert abs(R - 15.0) < 0.5
+
+
+def test_contact_angle_estimator_on_exact_cap():
+    """The estimator on the paper's analytic equilibrium field phi_r (Sec. 3.1)."""
+    nx, ny, W = 160, 80, 4.0
+    for th in (40.0, 75.0, 120.0, 150.0):
+        Rr = 25.0
+        yc = 0.5 - Rr * math.cos(math.radians(th))
+        phi = workloads.droplet((nx, ny), (80.0, yc), Rr, W)
+        zeta = np.ones_like(phi, bool)
+        wall = dict(kind="plane", point=(0.0, 0.5), normal=(0.0, 1.0))
+        got, centre, R, n = odiag.contact_angle(phi, zeta, wall, W)
+        assert abs(got - th) < 0.3, (th, got)
+    # curved wall: circle of radius Rs centred below, cap meeting it at theta
+    Rs, R, th = 30.0, 20.0, 70.0
+    d = math.sqrt(R * R + Rs * Rs - 2 * R * Rs * math.cos(math.radians(th)))
+    phi = workloads.droplet((nx, ny), (80.0, 5.0 + d), R, W)
+    wall = dict(kind="circle", center=(80.0, 5.0), radius=Rs)
+    got = odiag.contact_angle(phi, np.ones_like(phi, bool), wall, W)[0]
+    assert abs(got - th) < 0.3
+
+
+def test_laplace_law_free_droplet():
+    """Laplace's law for a free 2D droplet: p_in - p_out = sigma / R with the model's
+    sigma = sqrt(2 kappa beta) / 6 and F_s = mu grad phi.  The pressure difference
+    is averaged over the tail of the run to remove the acoustic ringing; R is the
+    fitted phi = 1/2 radius."""
+    sigma, W, n = 1e-2, 4.0, 56
+    X, Y = np.meshgrid(np.arange(n), np.arange(n))
+    r = np.hypot(X - n / 2, Y - n / 2)
+    for R in (9.0, 12.0, 15.0):
+        phi0 = workloads.droplet((n, n), (n / 2, n / 2), R, W)
+        c = dict(lattice="D2Q9", shape=(n, n), periodic=(True, True),
+                 mask=np.zeros((n, n), np.uint8), phi0=phi0, sigma=sigma, width=W,
+                 theta_deg=90.0)
+        o = oracle_for(c)
+        o.step(2500)
+        samples, radii = [], []
+        for k in range(8):
+            o.step(125)
+            f = o.fields()
+            samples.append(f["p"][r < R - 2 * W].mean() - f["p"][r > R + 2 * W].mean())
+            radii.append(odiag.kasa_fit(odiag.interface_points(f["phi"], np.ones((n, n), bool)))[1])
+        ratio = np.mean(samples) * np.mean(radii) / sigma
+        assert abs(ratio - 1.0) < 0.03, (R, ratio)
+
+
+def test_cap_radius_closed_forms():
+    """theta = 90 deg keeps the initial radius; the 2D cap area and 3D cap volume
+    formulas reproduce the semicircle / hemisphere they start from."""
+    assert abs(odiag.cap_radius_2d(20.0, 90.0) - 20.0) < 1e-12
+    assert abs(odiag.cap_radius_3d(20.0, 90.0) - 20.0) < 1e-12
+    for th in (30.0, 60.0, 120.0, 150.0):
+        t = math.radians(th)
+        R = odiag.cap_radius_2d(20.0, th)
+        assert abs(R * R * (t - math.sin(t) * math.cos(t)) - math.pi * 400 / 2) < 1e-9
+        R3 = odiag.cap_radius_3d(20.0, th)
+        h = R3 * (1 - math.cos(t))
+        assert abs(math.pi * h * h * (3 * R3 - h) / 3 - 2 * math.pi * 8000 / 3) < 1e-6
+
+
+def test_beta_kappa_from_sigma_width():
+    """beta, kappa give back W = sqrt(8 kappa / beta) and sigma = sqrt(2 kappa beta) / 6."""
+    for sigma, W in ((1e-3, 4.0), (5e-3, 5.0), (0.02, 8.0)):
+        b, k = om.beta_kappa(sigma, W)
+        assert abs(math.sqrt(8 * k / b) - W) < 1e-12
+        assert abs(math.sqrt(2 * k * b) / 6 - sigma) < 1e-15

@@ -1,0 +1,208 @@
+"""Seeded synthetic inputs: solid masks, initial order-parameter fields and case
+samplers.  Shared by the tests, the benchmark and the smoke check; holds none of
+the solver's arithmetic.
+
+Arrays use numpy shape (ny, nx) in 2D and (nz, ny, nx) in 3D, i.e. x is the
+fastest index once flattened.  A mask entry is 1 on geometric solid nodes.
+
+The geometries follow the paper's test problems (Sec. 3): a droplet resting on a
+flat wall (Sec. 3.1), on an inclined wall built as a staircase (Sec. 3.2) and on
+a cylinder or sphere (Sec. 3.3); the initial field is the tanh droplet of Eq.
+(initialphi).  Each case also records the wall it rests on (a plane, or a circle
+or sphere), which the contact-angle estimators need.
+"""
+import math
+
+import numpy as np
+
+
+# ---------------------------------------------------------------- geometry
+
+def _grid(shape):
+    """Coordinate arrays (x, y[, z]) over numpy shape reversed(shape)."""
+    axes = [np.arange(n, dtype=np.float64) for n in shape]
+    mesh = np.meshgrid(*axes[::-1], indexing="ij")
+    return mesh[::-1]
+
+
+def flat_walls(shape, bottom=True, top=True):
+    """Solid rows at the lowest (y, or z in 3D) index and/or the highest."""
+    mask = np.zeros(shape[::-1], dtype=np.uint8)
+    if len(shape) == 2:
+        if bottom:
+            mask[0, :] = 1
+        if top:
+            mask[-1, :] = 1
+    else:
+        if bottom:
+            mask[0, :, :] = 1
+        if top:
+            mask[-1, :, :] = 1
+    return mask
+
+
+def inclined_plane(shape, point, angle_deg):
+    """Staircase solid below a plane tilted by angle_deg about the y axis
+    (3D: solid where (z - zp) cos a - (x - xp) sin a < 0) or, in 2D, below the line
+    through point with slope tan(a) (solid where (y - yp) cos a - (x - xp) sin a < 0)."""
+    a = math.radians(angle_deg)
+    X = _grid(shape)
+    up = X[-1] if len(shape) == 3 else X[1]
+    level = (up - point[1]) * math.cos(a) - (X[0] - point[0]) * math.sin(a)
+    return (level < 0).astype(np.uint8)
+
+
+def ball(shape, center, radius):
+    """Solid disc (2D) or sphere (3D): nodes strictly inside the radius."""
+    X = _grid(shape)
+    r2 = sum((X[d] - center[d]) ** 2 for d in range(len(shape)))
+    return (r2 < radius * radius).astype(np.uint8)
+
+
+def droplet(shape, center, radius, width):
+    """Eq. (initialphi): 0.5 + 0.5 tanh(2 (R - |x - x0|) / W)."""
+    X = _grid(shape)
+    r = np.sqrt(sum((X[d] - center[d]) ** 2 for d in range(len(shape))))
+    return 0.5 + 0.5 * np.tanh(2.0 * (radius - r) / width)
+
+
+# ---------------------------------------------------------------- cases
+
+def _case(lattice, shape, periodic, mask, phi0, theta, sigma, width, wall, **kw):
+    d = dict(lattice=lattice, shape=tuple(shape), periodic=tuple(periodic),
+             mask=np.ascontiguousarray(mask, dtype=np.uint8),
+             phi0=np.ascontiguousarray(phi0, dtype=np.float64),
+             theta_deg=float(theta), sigma=float(sigma), width=float(width),
+             tau=0.8, mobility=0.1, rho_l=10.0, rho_g=1.0, wall=wall)
+    d.update(kw)
+    return d
+
+
+def flat_droplet_case(nx=128, ny=64, radius=20.0, theta=60.0, width=4.0,
+                      sigma=1e-3, lattice="D2Q9"):
+    """Droplet centred on the wetting plane of a flat bottom wall; walls at the
+    bottom and top rows; periodic in x.  The wetting plane of a one-row solid is
+    y = 0.5, half-way between the solid row and the first fluid row."""
+    shape = (nx, ny)
+    mask = flat_walls(shape)
+    phi0 = droplet(shape, (nx / 2, 0.5), radius, width)
+    wall = dict(kind="plane", point=(0.0, 0.5), normal=(0.0, 1.0))
+    return _case(lattice, shape, (True, False), mask, phi0, theta, sigma, width, wall)
+
+
+def config0():
+    """128 x 64 D2Q9, FP64, R = 20, theta = 60 deg, W = 4, sigma = 1e-3, 5000 steps."""
+    c = flat_droplet_case(128, 64, 20.0, 60.0, 4.0)
+    c.update(storage="f64", steps=5000, name="flat-128x64-fp64")
+    return c
+
+
+def config1(theta=60.0, nx=1024, ny=512):
+    """1024 x 512 D2Q9, FP32, R = 80 on a flat wall, W = 5; 50k steps."""
+    c = flat_droplet_case(nx, ny, 80.0 * nx / 1024, theta, 5.0)
+    c.update(storage="f32", steps=50000, name=f"flat-{nx}x{ny}-fp32-theta{int(theta)}")
+    return c
+
+
+def inclined_droplet_case_3d(n=256, radius=40.0, theta=45.0, angle=30.0, width=5.0,
+                             sigma=1e-3, storage="f32"):
+    """n^3 D3Q19, non-periodic; staircase solid below a plane tilted by `angle`
+    through (n/2, n/4) in the x-z plane; droplet centred on that plane."""
+    shape = (n, n, n)
+    xp, zp = n / 2.0, n / 4.0
+    mask = inclined_plane(shape, (xp, zp), angle)
+    phi0 = droplet(shape, (xp, n / 2.0, zp), radius, width)
+    a = math.radians(angle)
+    wall = dict(kind="plane", point=(xp, n / 2.0, zp), normal=(-math.sin(a), 0.0, math.cos(a)))
+    return _case("D3Q19", shape, (False, False, False), mask, phi0, theta, sigma, width,
+                 wall, storage=storage, steps=20000,
+                 name=f"inclined-{n}^3-{storage}")
+
+
+def config2(storage="f32", n=256):
+    return inclined_droplet_case_3d(n=n, radius=40.0 * n / 256, storage=storage)
+
+
+def cylinder_case(nx, ny, rc_frac, theta, width=4.0, sigma=1e-3, drop_frac=0.3):
+    """Solid cylinder of radius rc_frac*ny near the bottom, droplet of radius
+    drop_frac*R_c centred on its top; walls at the bottom and top rows."""
+    rc = rc_frac * ny
+    center = (nx / 2.0, rc + 0.05 * ny)
+    mask = np.maximum(ball((nx, ny), center, rc), flat_walls((nx, ny)))
+    rd = drop_frac * rc
+    phi0 = droplet((nx, ny), (center[0], center[1] + rc), rd, width)
+    wall = dict(kind="circle", center=center, radius=rc)
+    return _case("D2Q9", (nx, ny), (True, False), mask, phi0, theta, sigma, width, wall,
+                 storage="f32", name=f"cyl-{nx}x{ny}")
+
+
+def config3(seed=3, n_cases=64):
+    """64 D2Q9 cylinder cases, sizes U{128..768 step 16} x half, R_c ~ U[0.2, 0.4] Ny,
+    droplet 0.3 R_c, theta ~ U[30, 150] deg, W = 4, FP32."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_cases):
+        nx = int(rng.integers(0, (768 - 128) // 16 + 1)) * 16 + 128
+        ny = nx // 2
+        rcf = float(rng.uniform(0.2, 0.4))
+        th = float(rng.uniform(30.0, 150.0))
+        c = cylinder_case(nx, ny, rcf, th)
+        c["name"] = f"c3-{k:02d}-{nx}x{ny}"
+        out.append(c)
+    return out
+
+
+def serving_request(rng, idx):
+    """One request of the serving workload: 2D (256x128 .. 1024x512) or 3D
+    (64^3 .. 192^3), geometry flat / inclined / curved, theta ~ U[30, 150]."""
+    th = float(rng.uniform(30.0, 150.0))
+    geom = ["flat", "inclined", "curved"][int(rng.integers(0, 3))]
+    if rng.uniform() < 0.5:
+        nx = int(rng.integers(0, (1024 - 256) // 32 + 1)) * 32 + 256
+        ny = nx // 2
+        R = 0.2 * ny
+        if geom == "flat":
+            c = flat_droplet_case(nx, ny, R, th, 5.0)
+        elif geom == "inclined":
+            a = 30.0
+            xp, yp = nx / 2.0, ny / 4.0
+            mask = np.maximum(inclined_plane((nx, ny), (xp, yp), a), flat_walls((nx, ny)))
+            phi0 = droplet((nx, ny), (xp, yp), R, 5.0)
+            r = math.radians(a)
+            wall = dict(kind="plane", point=(xp, yp), normal=(-math.sin(r), math.cos(r)))
+            c = _case("D2Q9", (nx, ny), (True, False), mask, phi0, th, 1e-3, 5.0, wall)
+        else:
+            c = cylinder_case(nx, ny, 0.3, th, width=5.0, drop_frac=R / (0.3 * ny))
+    else:
+        n = int(rng.integers(0, (192 - 64) // 16 + 1)) * 16 + 64
+        R = 0.2 * n
+        shape = (n, n, n)
+        if geom == "flat":
+            mask = flat_walls(shape, bottom=True, top=False)
+            phi0 = droplet(shape, (n / 2, n / 2, 0.5), R, 5.0)
+            wall = dict(kind="plane", point=(0.0, 0.0, 0.5), normal=(0.0, 0.0, 1.0))
+        elif geom == "inclined":
+            c = inclined_droplet_case_3d(n=n, radius=R, theta=th)
+            mask, phi0, wall = c["mask"], c["phi0"], c["wall"]
+        else:
+            rs = 0.3 * n
+            center = (n / 2, n / 2, rs + 0.05 * n)
+            mask = ball(shape, center, rs)
+            phi0 = droplet(shape, (n / 2, n / 2, center[2] + rs), R, 5.0)
+            wall = dict(kind="circle", center=center, radius=rs)
+        c = _case("D3Q19", shape, (False, False, False), mask, phi0, th, 1e-3, 5.0, wall)
+    c.update(storage="f32", geometry=geom, name=f"req-{idx:03d}-{geom}-{c['lattice']}")
+    return c
+
+
+def config4(seed=4, n_requests=200, rate=20.0):
+    """Poisson arrivals (mean `rate` per second) of mixed serving requests."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(n_requests):
+        t += float(rng.exponential(1.0 / rate))
+        c = serving_request(rng, k)
+        c["arrival_s"] = t
+        out.append(c)
+    return out
