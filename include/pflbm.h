@@ -1,0 +1,199 @@
+/*
+ * pflbm.h - C interface of the MI355X (gfx950) phase-field lattice Boltzmann
+ * library with wetting folded into the chemical potential (arXiv:2312.00369).
+ *
+ * The problem statement follows the paper: a grid with a solid mask
+ * (Sec. 2.2.2), a contact angle theta (Eq. chemical_potencial2), the fluid
+ * parameters rho_l, rho_g, nu, sigma (through beta and kappa), M and W
+ * (Sec. 3.1), an initial order parameter (Eq. initialphi), and the lattice
+ * (D2Q9, or D3Q19 for both distribution sets in 3D, Sec. 3).  The outputs are
+ * the order parameter, pressure, velocity and chemical potential fields and
+ * the contact angle.
+ *
+ * Conventions shared by every call
+ *  - Host arrays are dense nx*ny*nz arrays with x fastest (index x + nx*(y +
+ *    ny*z)); nz = 1 in 2D.  The library copies what it needs: the caller keeps
+ *    ownership of every array it passes.
+ *  - Lattice units: dx = dt = 1.
+ *  - Every call returns PFLBM_OK (0) or a negative error code.  No C++
+ *    exception crosses this interface.  pflbm_last_error() returns a
+ *    thread-local text for the last failure in the calling thread.
+ *  - Handles are not thread-safe; a handle's device work is ordered on the HIP
+ *    stream given at creation (0 = the null stream), which must outlive it.
+ *  - Calls marked (async) enqueue work and return; calls marked (sync) wait
+ *    for the handle's stream before returning.
+ */
+#ifndef PFLBM_H
+#define PFLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+#define PFLBM_OK            0
+#define PFLBM_EINVAL       (-1) /* bad argument: tau <= 1/2, M <= 0, dims <= 0, theta
+                                   outside (0,180), null required pointer, struct_size
+                                   mismatch, buffer too small                         */
+#define PFLBM_ENOMEM       (-2) /* device or host allocation failed                   */
+#define PFLBM_EDEVICE      (-3) /* a HIP call failed; the message is kept             */
+#define PFLBM_ENONFINITE   (-4) /* the case produced a NaN or infinity                 */
+#define PFLBM_ESTATE       (-5) /* call not valid in the object's state               */
+#define PFLBM_EUNSUPPORTED (-6) /* lattice / storage combination not provided          */
+
+/* ---------------------------------------------------------------- enums */
+enum { PFLBM_D2Q9 = 0, PFLBM_D3Q19 = 1 };                 /* Sec. 2.1.2, Eq. ci / 3ci */
+enum { PFLBM_FP64 = 0, PFLBM_FP32 = 1, PFLBM_FP16_DEV = 2 }; /* distribution storage   */
+enum { PFLBM_WALL_NONE = 0, PFLBM_WALL_PLANE = 1, PFLBM_WALL_BALL = 2 };
+
+/* Case parameters (POD, FP64 on the host whatever the storage).
+ *  tau            hydrodynamic relaxation time tau_f (nu = c_s^2 (tau_f - 1/2),
+ *                 Sec. 2.1.2); used when nu_l = nu_g = 0
+ *  tau_phi        relaxation time tau_g of the phase-field LBE (Eq. BGK); 0 = tau
+ *  mobility       M; alpha = M / (c_s^2 (tau_g - 1/2)) (Eq. mobility)
+ *  beta, kappa    free-energy coefficients (Eq. free-energy, bulk_energy)
+ *  rho_l, rho_g   densities at phi = 1 and phi = 0 (Sec. 2.1.1)
+ *  nu_l, nu_g     viscosities at phi = 1 and 0; both 0 = uniform tau
+ *  theta_deg      contact angle in degrees, in (0, 180)
+ *  body_force     F_b (Sec. 2.1.1); components beyond the dimension are ignored
+ *  storage        PFLBM_FP64: FP64 storage and arithmetic; PFLBM_FP32: FP32
+ *                 storage and arithmetic; PFLBM_FP16_DEV: FP16 deviations with a
+ *                 per-case power-of-two scale (g_0 and s in FP32), FP32 arithmetic
+ *  wall_*, diag_width
+ *                 the wall the contact-angle estimator measures against: a plane
+ *                 (point + normal pointing into the fluid) or a circle / sphere
+ *                 (centre + radius); interface points closer than diag_width to
+ *                 it are left out of the fit
+ *  steady_tol     max |phi(t) - phi(t_prev_diag)| below which a case is steady
+ */
+typedef struct pflbm_params {
+  uint32_t struct_size;          /* = sizeof(pflbm_params) */
+  int32_t lattice;               /* PFLBM_D2Q9 or PFLBM_D3Q19 */
+  int32_t storage;               /* PFLBM_FP64 / FP32 / FP16_DEV */
+  int32_t nx, ny, nz;            /* nz = 1 for D2Q9 */
+  int32_t periodic[3];           /* nonzero = periodic axis; others get bounce-back walls */
+  double tau, tau_phi, mobility, beta, kappa, rho_l, rho_g, nu_l, nu_g, theta_deg;
+  double body_force[3];
+  int32_t wall_kind;             /* PFLBM_WALL_* */
+  double wall_point[3], wall_normal[3], wall_radius, diag_width;
+  double steady_tol;
+} pflbm_params;
+
+/* Diagnostics record (all reductions in FP64 over zeta = 1 nodes). */
+typedef struct pflbm_diag {
+  int64_t step;            /* time steps taken so far                                  */
+  double mass;             /* sum of phi                                               */
+  double s_sum;            /* sum of s = u . grad(phi) of the last step; the step's mass
+                              change is -(1.5 s_sum(t) - 0.5 s_sum(t-1))                */
+  double steady_residual;  /* max |phi - phi at the previous diagnostics call|          */
+  double theta_deg;        /* contact angle from the circle / sphere fit (NaN if none)  */
+  double centre[3], radius;/* fitted interface circle / sphere                          */
+  int64_t n_points;        /* interface points used by the fit                          */
+  int32_t nonfinite;       /* nonzero if phi held a NaN or infinity                     */
+  int32_t steady;          /* steady_residual <= steady_tol (and not the first call)    */
+} pflbm_diag;
+
+typedef struct pflbm_case_s* pflbm_handle;
+typedef struct pflbm_group_s* pflbm_group;
+
+/* ---------------------------------------------------------------- host-only helpers */
+
+/* Node classes of Sec. 2.2.2 for a mask, computed on the host without a
+ * device: classes[n] gets bit 0 zeta, bit 1 fluid (epsilon = 1), bit 2 ghost,
+ * for each of the nx*ny*nz domain nodes.  (no device work) */
+int pflbm_classify(const pflbm_params* prm, const uint8_t* solid_mask, uint8_t* classes);
+
+/* Velocity set of a lattice as used by the kernels: c[3*i + a], w[i], opp[i]
+ * and the phase-source coefficient k[i] (any pointer may be NULL).  Returns Q
+ * (9 or 19) or a negative error code.  (no device work) */
+int pflbm_lattice_table(int32_t lattice, int32_t* c, double* w, int32_t* opp, double* k);
+
+/* ---------------------------------------------------------------- single case */
+
+/* Device bytes a case with these parameters needs (sync-free, host only). */
+int pflbm_footprint(const pflbm_params* prm, size_t* bytes);
+
+/* Create a case.  solid_mask: nx*ny*nz bytes, nonzero = geometric solid node
+ * (Sec. 2.2.2 node marks are derived from it).  phi0: nx*ny*nz initial order
+ * parameter (Eq. initialphi), read on fluid and boundary nodes only.
+ * The library allocates its device memory itself (hipMalloc).  hip_stream is
+ * borrowed (a hipStream_t, or NULL).  (sync: returns with the case initialised) */
+int pflbm_create(const pflbm_params* prm, const uint8_t* solid_mask, const double* phi0,
+                 void* hip_stream, pflbm_handle* out);
+
+/* As pflbm_create, but the case lives in caller-owned device memory of at least
+ * pflbm_footprint bytes, which must stay allocated until pflbm_destroy. */
+int pflbm_create_in(const pflbm_params* prm, const uint8_t* solid_mask, const double* phi0,
+                    void* hip_stream, void* dev_workspace, size_t ws_bytes, pflbm_handle* out);
+
+/* Advance nsteps >= 0 time steps (Sec. 2.1.2 Eq. BGK-NS and 2.1.3 Eq. BGK, with
+ * the wall term of Eq. chemical_potencial2).  With a graph chunk set, full
+ * chunks replay a captured HIP graph.  (async) */
+int pflbm_step(pflbm_handle h, int64_t nsteps);
+
+/* Steps per captured HIP graph (0 = launch kernels directly).  Default 64. */
+int pflbm_set_graph_chunk(pflbm_handle h, int32_t steps);
+
+/* Launch shape of the stencil and collide kernels: threads along x, y, z of one
+ * workgroup (tx a multiple of 64, tx*ty*tz <= 1024).  Results do not depend on it.
+ * Drops any captured graph. */
+int pflbm_set_tile(pflbm_handle h, int32_t tx, int32_t ty, int32_t tz);
+
+/* Current fields as FP64 host arrays of nx*ny*nz (u: D arrays, component-major).
+ * Any pointer may be NULL.  phi holds the ghost value on ghost nodes and 0 on
+ * other solid nodes; p, u and mu are 0 on zeta = 0 nodes.  (sync) */
+int pflbm_fields(pflbm_handle h, double* phi, double* p, double* u, double* mu);
+
+/* Node classes as nx*ny*nz bytes: bit 0 zeta (fluid or boundary), bit 1 fluid
+ * (epsilon = 1), bit 2 ghost.  (host copy, sync-free) */
+int pflbm_node_classes(pflbm_handle h, uint8_t* classes);
+
+/* Run the reductions now and fill *d.  Also refreshes the steady-state
+ * reference field.  (sync) */
+int pflbm_diagnostics(pflbm_handle h, pflbm_diag* d);
+
+/* Checkpoint: raw device state (populations, s, step count, scales).
+ * pflbm_state_size gives the byte count; set_state accepts only a blob from a
+ * case with identical parameters.  Resuming is bit-identical.  (sync) */
+int pflbm_state_size(pflbm_handle h, size_t* bytes);
+int pflbm_get_state(pflbm_handle h, void* host, size_t bytes);
+int pflbm_set_state(pflbm_handle h, const void* host, size_t bytes);
+
+/* Time nsteps eager steps with HIP events around every kernel launch on the
+ * case's stream; avg_ms[k] receives the mean duration in milliseconds of kernel
+ * kind k for k < nkinds (0: phi sum, 1: mu stencil, 2: collide-stream; kinds
+ * the library does not have read 0).  The steps count as real steps.  (sync) */
+int pflbm_profile(pflbm_handle h, int64_t nsteps, double* avg_ms, int32_t nkinds);
+
+/* Time steps taken so far (-1 for a NULL handle). */
+int64_t pflbm_step_count(pflbm_handle h);
+void pflbm_destroy(pflbm_handle h);
+
+/* ---------------------------------------------------------------- groups (batched) */
+
+/* A group advances many cases of the same lattice and storage together: one
+ * persistent launch per kernel walks a device tile -> case table.  Members are
+ * non-owning references; destroying a member removes it. */
+int pflbm_group_create(void* hip_stream, pflbm_group* out);
+int pflbm_group_add(pflbm_group g, pflbm_handle h);
+int pflbm_group_remove(pflbm_group g, pflbm_handle h);
+int pflbm_group_size(pflbm_group g);
+/* Advance every member nsteps (async). */
+int pflbm_group_step(pflbm_group g, int64_t nsteps);
+/* Reductions for every member (one batched launch); d[k] for member k in
+ * insertion order, flags[k] = bit 0 steady, bit 1 nonfinite.  (sync) */
+int pflbm_group_poll(pflbm_group g, pflbm_diag* d, int32_t* flags, int32_t capacity);
+int pflbm_group_set_tile(pflbm_group g, int32_t tx, int32_t ty, int32_t tz, int32_t blocks_per_cu);
+void pflbm_group_destroy(pflbm_group g);
+
+/* ---------------------------------------------------------------- errors */
+const char* pflbm_strerror(int code);
+const char* pflbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFLBM_H */

@@ -1,0 +1,93 @@
+// Internal host-side definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pflbm.h"
+#include "kernels.h"
+
+namespace pflbm {
+
+// Thread-local error text; set_error returns its code so call sites can
+// `return set_error(...)`.
+int set_error(int code, const char* fmt, ...);
+void clear_error();
+
+#define PFLBM_HIP(call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return ::pflbm::set_error(PFLBM_EDEVICE, "%s failed: %s (%s:%d)", #call,       \
+                                hipGetErrorString(e_), __FILE__, __LINE__);          \
+  } while (0)
+
+struct Layout {
+  size_t nodes, f[2], g[2], s, phi, mu, snap, partial, rec, total;
+  size_t f_bytes, g_bytes;   // one f buffer, one g buffer
+  size_t c_bytes;     // one compute-type field
+  long long nparts;   // reduction partial records
+};
+
+// Geometry, physics constants and node classes derived on the host.
+struct Derived {
+  int D, Q;
+  Geo geo;
+  Phys phys;
+  Wall wall;
+  long long N;        // SX * PY * PZ
+};
+
+int validate_and_derive(const pflbm_params* prm, Derived* d);
+Layout make_layout(const Derived& d, int storage, dim3 tile);
+// Node words on the padded grid; also fills `classes` (nx*ny*nz bytes) if non-null.
+void classify_nodes(const Derived& d, const uint8_t* mask, std::vector<uint32_t>& words,
+                    uint8_t* classes);
+dim3 default_tile(int D);
+
+}  // namespace pflbm
+
+struct pflbm_group_s;
+
+struct pflbm_case_s {
+  pflbm_params prm;
+  pflbm::Derived dv;
+  pflbm::Layout lay;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  bool owns = false;
+  unsigned char* base = nullptr;
+  uint32_t* nodes = nullptr;
+  void* f[2] = {nullptr, nullptr};
+  void* g[2] = {nullptr, nullptr};
+  void* s = nullptr;
+  void* phi = nullptr;
+  void* mu = nullptr;
+  void* snap = nullptr;
+  double* partial = nullptr;
+  double* rec = nullptr;
+  std::vector<uint8_t> classes;   // host copy of the domain classes
+  int cur = 0;                    // buffer holding the current post-collision state
+  int64_t step = 0;
+  bool snap_valid = false;
+  dim3 tile;
+  int graph_chunk = 64;
+  hipGraphExec_t gexec = nullptr;
+  int gexec_steps = 0;
+  pflbm_group_s* group = nullptr;
+};
+
+namespace pflbm {
+// Per-(lattice, storage) launchers; defined in engine.hip.
+int run_phi(pflbm_case_s* h);
+int run_mu(pflbm_case_s* h);
+int run_collide(pflbm_case_s* h, int mode, void* out_p, void* out_u);
+int run_init_g(pflbm_case_s* h);
+int run_reduce(pflbm_case_s* h, int update_snap, double* host_rec);
+int run_step_eager(pflbm_case_s* h);
+}  // namespace pflbm

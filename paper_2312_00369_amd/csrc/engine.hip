@@ -1,0 +1,136 @@
+// Kernel launchers for one case, dispatched on (lattice, storage).
+#include "case.h"
+
+namespace pflbm {
+
+namespace {
+
+dim3 grid_of(const Geo& G, dim3 t) {
+  return dim3((G.PX + t.x - 1) / t.x, (G.PY + t.y - 1) / t.y, (G.PZ + t.z - 1) / t.z);
+}
+
+template <class L, int S>
+struct Engine {
+  using C = ComputeT<S>;
+
+  static int phi(pflbm_case_s* h) {
+    const Geo& G = h->dv.geo;
+    hipLaunchKernelGGL((k_phi<L, S>), grid_of(G, h->tile), h->tile, 0, h->stream, h->nodes,
+                       h->g[h->cur], static_cast<C*>(h->phi), G, h->dv.phys);
+    PFLBM_HIP(hipGetLastError());
+    return PFLBM_OK;
+  }
+
+  static size_t mu_lds(dim3 t) {
+    const size_t lz = (L::D == 3) ? t.z + 4 : 1;
+    return (size_t)(t.x + 4) * (t.y + 4) * lz * (sizeof(C) + sizeof(uint32_t));
+  }
+
+  static int mu(pflbm_case_s* h) {
+    const Geo& G = h->dv.geo;
+    hipLaunchKernelGGL((k_mu<L, C>), grid_of(G, h->tile), h->tile, mu_lds(h->tile), h->stream,
+                       h->nodes, static_cast<C*>(h->phi), static_cast<C*>(h->mu), G, h->dv.phys);
+    PFLBM_HIP(hipGetLastError());
+    return PFLBM_OK;
+  }
+
+  static int collide(pflbm_case_s* h, int mode, void* out_p, void* out_u) {
+    const Geo& G = h->dv.geo;
+    const int c = h->cur;
+    auto args = [&](auto kern) {
+      hipLaunchKernelGGL(kern, grid_of(G, h->tile), h->tile, 0, h->stream, h->nodes, h->f[c],
+                         h->g[c], h->f[1 - c], h->g[1 - c], static_cast<const C*>(h->phi),
+                         static_cast<const C*>(h->mu), static_cast<C*>(h->s),
+                         static_cast<C*>(out_p), static_cast<C*>(out_u), G, h->dv.phys);
+    };
+    if (mode == 0)
+      args(k_collide<L, S, 0>);
+    else if (mode == 1)
+      args(k_collide<L, S, 1>);
+    else
+      args(k_collide<L, S, 2>);
+    PFLBM_HIP(hipGetLastError());
+    return PFLBM_OK;
+  }
+
+  static int init_g(pflbm_case_s* h) {
+    const Geo& G = h->dv.geo;
+    hipLaunchKernelGGL((k_init_g<L, S>), grid_of(G, h->tile), h->tile, 0, h->stream, h->nodes,
+                       h->g[h->cur], static_cast<const C*>(h->phi), static_cast<const C*>(h->mu),
+                       G, h->dv.phys);
+    PFLBM_HIP(hipGetLastError());
+    return PFLBM_OK;
+  }
+
+  static int reduce(pflbm_case_s* h, int update_snap) {
+    const Geo& G = h->dv.geo;
+    const dim3 t = h->tile;
+    const dim3 gr = grid_of(G, t);
+    hipLaunchKernelGGL((k_reduce_partial<L, C>), gr, t, 0, h->stream, h->nodes,
+                       static_cast<const C*>(h->phi), static_cast<const C*>(h->s),
+                       static_cast<C*>(h->snap), h->partial, G, h->dv.wall, update_snap);
+    PFLBM_HIP(hipGetLastError());
+    const long long nparts = (long long)gr.x * gr.y * gr.z;
+    hipLaunchKernelGGL(k_reduce_final<kRecN>, dim3(1), dim3(256), 0, h->stream, h->partial, nparts,
+                       h->rec);
+    PFLBM_HIP(hipGetLastError());
+    return PFLBM_OK;
+  }
+};
+
+template <template <class, int> class Fn, class... A>
+int dispatch(pflbm_case_s* h, A... a) {
+  const int lat = h->prm.lattice, st = h->prm.storage;
+  if (lat == PFLBM_D2Q9) {
+    if (st == PFLBM_FP64) return Fn<D2Q9, kF64>::go(h, a...);
+    if (st == PFLBM_FP32) return Fn<D2Q9, kF32>::go(h, a...);
+    if (st == PFLBM_FP16_DEV) return Fn<D2Q9, kF16Dev>::go(h, a...);
+  } else {
+    if (st == PFLBM_FP64) return Fn<D3Q19, kF64>::go(h, a...);
+    if (st == PFLBM_FP32) return Fn<D3Q19, kF32>::go(h, a...);
+    if (st == PFLBM_FP16_DEV) return Fn<D3Q19, kF16Dev>::go(h, a...);
+  }
+  return set_error(PFLBM_EUNSUPPORTED, "unsupported lattice/storage %d/%d", lat, st);
+}
+
+template <class L, int S> struct DoPhi { static int go(pflbm_case_s* h) { return Engine<L, S>::phi(h); } };
+template <class L, int S> struct DoMu { static int go(pflbm_case_s* h) { return Engine<L, S>::mu(h); } };
+template <class L, int S> struct DoCollide {
+  static int go(pflbm_case_s* h, int m, void* p, void* u) { return Engine<L, S>::collide(h, m, p, u); }
+};
+template <class L, int S> struct DoInit { static int go(pflbm_case_s* h) { return Engine<L, S>::init_g(h); } };
+template <class L, int S> struct DoReduce {
+  static int go(pflbm_case_s* h, int up) { return Engine<L, S>::reduce(h, up); }
+};
+
+}  // namespace
+
+int run_phi(pflbm_case_s* h) { return dispatch<DoPhi>(h); }
+int run_mu(pflbm_case_s* h) { return dispatch<DoMu>(h); }
+int run_collide(pflbm_case_s* h, int mode, void* out_p, void* out_u) {
+  return dispatch<DoCollide>(h, mode, out_p, out_u);
+}
+int run_init_g(pflbm_case_s* h) { return dispatch<DoInit>(h); }
+
+int run_reduce(pflbm_case_s* h, int update_snap, double* host_rec) {
+  int rc = dispatch<DoReduce>(h, update_snap);
+  if (rc) return rc;
+  if (host_rec) {
+    PFLBM_HIP(hipMemcpyAsync(host_rec, h->rec, kRecN * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream));
+    PFLBM_HIP(hipStreamSynchronize(h->stream));
+  }
+  return PFLBM_OK;
+}
+
+int run_step_eager(pflbm_case_s* h) {
+  int rc;
+  if ((rc = run_phi(h))) return rc;
+  if ((rc = run_mu(h))) return rc;
+  if ((rc = run_collide(h, 0, nullptr, nullptr))) return rc;
+  h->cur ^= 1;
+  h->step += 1;
+  return PFLBM_OK;
+}
+
+}  // namespace pflbm

@@ -1,0 +1,549 @@
+// Device kernels of one time step (templated on lattice and storage).
+//
+// State kept between steps: post-collision populations f*, g* (ping-pong
+// buffers, structure of arrays: population i of node n at i*NQ + n) and
+// s = u . grad(phi) of the previous step.  One step is
+//   k_phi      phi(x) = sum_i g_i(x), with g_i pulled from x - c_i     Eq. (order-parameter)
+//   k_mu       LDS tile with a two-node halo: ghost phi (Sec. 2.2.2), the isotropic
+//              Laplacian (Eq. Laplace), a_v = |grad eps| (Eq. avvv) and
+//              mu (Eq. chemical_potencial2); writes mu and the ghost phi values
+//   k_collide  pulls f and g, forms grad phi (Eq. gradient), rho, F = mu grad phi + F_b,
+//              u, p (Sec. 2.1.2), s, and collides both sets: Eq. (BGK-NS) with
+//              f_eq of Eq. (feq_i) and F_i of Eq. (GGi); Eq. (BGK) with g_eq of
+//              Eq. (H_i) and G_i of Eq. (F_i) plus half its time derivative
+// Pulling f_i at x from a zeta = 0 node x - c_i takes f*_opp(i) of x itself
+// (bounce-back half-way along the link, Sec. 2.2.2).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "lattice.h"
+
+namespace pflbm {
+
+enum Storage { kF64 = 0, kF32 = 1, kF16Dev = 2 };
+
+// ------------------------------------------------------------------ geometry
+struct Geo {
+  int PX, PY, PZ;    // padded extents: periodic axes as given, others + 2
+  int SX;            // x stride (>= PX); nodes x >= PX are dead
+  int per[3];        // periodic flags
+  int pad[3];        // 0 periodic, 1 otherwise: domain x = padded x - pad
+  long long NQ;      // stride between populations (>= SX*PY*PZ)
+  __host__ __device__ long long idx(int x, int y, int z) const {
+    return x + (long long)SX * (y + (long long)PY * z);
+  }
+};
+
+struct Phys {
+  double tau, inv_tau_g, alpha, beta, kappa, wet, rho_l, rho_g, nu_l, nu_g;
+  double Fb[3];
+  int visc_var;
+  float scale_f, scale_g;  // FP16 codec: stored = value * scale (power of two)
+};
+
+// ------------------------------------------------------------------ storage codec
+// One distribution set (f or g) in one buffer: the rest population (i = 0) in
+// the first NQ slots, then populations 1..Q-1, each NQ slots.  The rest
+// population of g carries phi (g_0 ~ phi - (1 - w_0) alpha mu) and changes by
+// far less than an FP32 ulp of 1 per step in bulk liquid, so it is always
+// stored in FP64; every other population is small and is stored in the case's
+// storage type.  FP16-deviation storage keeps value * scale (a power of two)
+// in FP16: the rest equilibrium of every FP16 population is 0 (f at p = 0,
+// u = 0; g_i, i > 0, at mu = 0), so these are deviations from it.
+//   storage   f rest / moving      g rest / moving     compute
+//   kF64      f64 / f64            f64 / f64           f64
+//   kF32      f32 / f32            f64 / f32           f32
+//   kF16Dev   f32 / f16*scale      f64 / f16*scale     f32
+template <int S> struct ComputeOf { using T = float; };
+template <> struct ComputeOf<kF64> { using T = double; };
+template <int S> using ComputeT = typename ComputeOf<S>::T;
+
+template <int S, bool G>
+struct Set {
+  using C = ComputeT<S>;
+  using R = typename std::conditional<G || S == kF64, double, float>::type;   // rest
+  static constexpr bool kHalf = (S == kF16Dev);
+  using M = typename std::conditional<S == kF64, double,
+            typename std::conditional<kHalf, __half, float>::type>::type;   // moving
+  __host__ __device__ static size_t bytes(long long NQ, int Q) {
+    return (size_t)NQ * sizeof(R) + (size_t)(Q - 1) * (size_t)NQ * sizeof(M);
+  }
+  __device__ static R load_rest(const void* b, long long n) { return static_cast<const R*>(b)[n]; }
+  __device__ static void store_rest(void* b, long long n, R v) { static_cast<R*>(b)[n] = v; }
+  __device__ static const M* moving(const void* b, long long NQ) {
+    return reinterpret_cast<const M*>(static_cast<const unsigned char*>(b) + NQ * sizeof(R));
+  }
+  __device__ static M* moving(void* b, long long NQ) {
+    return reinterpret_cast<M*>(static_cast<unsigned char*>(b) + NQ * sizeof(R));
+  }
+  // population i >= 1
+  __device__ static C load(const void* b, int i, long long n, long long NQ, float scale) {
+    const M v = moving(b, NQ)[(i - 1) * NQ + n];
+    if constexpr (kHalf) return __half2float(v) * (1.0f / scale);
+    else return C(v);
+  }
+  __device__ static void store(void* b, int i, long long n, long long NQ, C v, float scale) {
+    if constexpr (kHalf) moving(b, NQ)[(i - 1) * NQ + n] = __float2half_rn(v * scale);
+    else moving(b, NQ)[(i - 1) * NQ + n] = M(v);
+  }
+};
+
+// ------------------------------------------------------------------ indexing
+__device__ inline int wrap1(int q, int P, int per) {
+  if (per) {
+    q += (q < 0) ? P : 0;
+    q -= (q >= P) ? P : 0;
+  }
+  return q;
+}
+
+// Flat indices of x + c_i for all i, for a zeta = 1 node (interior along
+// non-periodic axes, so only periodic axes can wrap).
+template <class L>
+__device__ inline void neighbours(const Geo& G, int x, int y, int z, long long nb[L::Q]) {
+  const int xs[3] = {wrap1(x - 1, G.PX, G.per[0]), x, wrap1(x + 1, G.PX, G.per[0])};
+  const int ys[3] = {wrap1(y - 1, G.PY, G.per[1]), y, wrap1(y + 1, G.PY, G.per[1])};
+  int zs[3] = {z, z, z};
+  if (L::D == 3) {
+    zs[0] = wrap1(z - 1, G.PZ, G.per[2]);
+    zs[2] = wrap1(z + 1, G.PZ, G.per[2]);
+  }
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i)
+    nb[i] = G.idx(xs[1 + L::cx(i)], ys[1 + L::cy(i)], zs[1 + L::cz(i)]);
+}
+
+// Pull moving population i >= 1 of node n from x - c_i, or take the opposite
+// population of n itself when x - c_i is a zeta = 0 node (bounce-back).  The
+// rest population never moves.
+template <class L, class SetT>
+__device__ inline typename SetT::C pull(const void* buf, int i, long long n,
+                                        const long long nb[L::Q], uint32_t word, long long NQ,
+                                        float scale) {
+  const bool bb = (word >> (kLinkShift + i)) & 1u;
+  const long long src = bb ? n : nb[L::opp(i)];
+  const int dir = bb ? L::opp(i) : i;
+  return SetT::load(buf, dir, src, NQ, scale);
+}
+
+__device__ inline bool node_coords(const Geo& G, int& x, int& y, int& z) {
+  x = blockIdx.x * blockDim.x + threadIdx.x;
+  y = blockIdx.y * blockDim.y + threadIdx.y;
+  z = blockIdx.z * blockDim.z + threadIdx.z;
+  return x < G.PX && y < G.PY && z < G.PZ;
+}
+
+// ------------------------------------------------------------------ k_phi
+template <class L, int S>
+__global__ void k_phi(const uint32_t* __restrict__ nodes, const void* __restrict__ gsrc,
+                      ComputeT<S>* __restrict__ phi, Geo G, Phys P) {
+  using C = ComputeT<S>;
+  int x, y, z;
+  if (!node_coords(G, x, y, z)) return;
+  const long long n = G.idx(x, y, z);
+  const uint32_t word = nodes[n];
+  if (!(word & kZeta)) return;
+  long long nb[L::Q];
+  neighbours<L>(G, x, y, z, nb);
+  using GS = Set<S, true>;
+  // g_0 carries phi; the moving populations are small.  Summing them first and
+  // adding g_0 last rounds once, instead of dropping sub-ulp terms one by one.
+  C small = C(0);
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) small += pull<L, GS>(gsrc, i, n, nb, word, G.NQ, P.scale_g);
+  phi[n] = C(GS::load_rest(gsrc, n) + (double)small);
+}
+
+// ------------------------------------------------------------------ k_mu
+// Workgroup = one tile of blockDim nodes; LDS holds phi and node words of the
+// tile plus two halo layers (ghost nodes of the first halo layer need their own
+// neighbours).  Dynamic LDS bytes: (TX+4)(TY+4)(TZ+4 or 1) * (sizeof(C) + 4).
+template <class L, class C>
+__global__ void k_mu(const uint32_t* __restrict__ nodes, C* __restrict__ phi,
+                     C* __restrict__ mu, Geo G, Phys P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int H = 2;
+  constexpr int HZ = (L::D == 3) ? H : 0;
+  const int TX = blockDim.x, TY = blockDim.y, TZ = blockDim.z;
+  const int LX = TX + 2 * H, LY = TY + 2 * H, LZ = TZ + 2 * HZ;
+  const int NL = LX * LY * LZ;
+  C* sphi = reinterpret_cast<C*>(smem);
+  uint32_t* sw = reinterpret_cast<uint32_t*>(sphi + NL);
+  const int ox = blockIdx.x * TX - H, oy = blockIdx.y * TY - H, oz = blockIdx.z * TZ - HZ;
+  const int tid = threadIdx.x + TX * (threadIdx.y + TY * threadIdx.z);
+  const int nthr = TX * TY * TZ;
+
+  for (int t = tid; t < NL; t += nthr) {
+    const int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
+    int q[3] = {ox + lx, oy + ly, oz + lz};
+    const int P3[3] = {G.PX, G.PY, G.PZ};
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (G.per[d]) {
+        q[d] %= P3[d];
+        if (q[d] < 0) q[d] += P3[d];
+      } else {
+        ok = ok && q[d] >= 0 && q[d] < P3[d];
+      }
+    }
+    uint32_t w = 0;
+    C v = C(0);
+    if (ok) {
+      const long long n = G.idx(q[0], q[1], q[2]);
+      w = nodes[n];
+      if (w & kZeta) v = phi[n];
+    }
+    sw[t] = w;
+    sphi[t] = v;
+  }
+  __syncthreads();
+
+  // Ghost mean over the 3^D block: only zeta = 1 entries are read, so filling in
+  // place is order-independent.
+  for (int t = tid; t < NL; t += nthr) {
+    const int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
+    const bool inner = lx >= 1 && lx < LX - 1 && ly >= 1 && ly < LY - 1 &&
+                       (L::D == 2 || (lz >= 1 && lz < LZ - 1));
+    if (!inner || !(sw[t] & kGhost)) continue;
+    C num = C(0);
+    int den = 0;
+    const int z0 = (L::D == 3) ? -1 : 0, z1 = (L::D == 3) ? 1 : 0;
+    for (int dz = z0; dz <= z1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int t2 = t + dx + LX * (dy + LY * dz);
+          if (sw[t2] & kZeta) {
+            num += sphi[t2];
+            ++den;
+          }
+        }
+    if (den > 0) sphi[t] = num / C(den);
+  }
+  __syncthreads();
+
+  int x, y, z;
+  if (!node_coords(G, x, y, z)) return;
+  const int t = (threadIdx.x + H) + LX * ((threadIdx.y + H) + LY * (threadIdx.z + HZ));
+  const uint32_t w = sw[t];
+  const long long n = G.idx(x, y, z);
+  if (w & kZeta) {
+    const C ph = sphi[t];
+    C lap = C(0), ex = C(0), ey = C(0), ez = C(0);
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+      const int t2 = t + L::cx(i) + LX * (L::cy(i) + LY * L::cz(i));
+      const C wi = C(L::w(i));
+      lap += C(2) * wi * (sphi[t2] - ph);
+      const C e = (sw[t2] & kFluid) ? C(1) : C(0);
+      ex += wi * C(L::cx(i)) * e;
+      ey += wi * C(L::cy(i)) * e;
+      ez += wi * C(L::cz(i)) * e;
+    }
+    const C inv_cs2 = C(3);
+    lap *= inv_cs2;
+    ex *= inv_cs2;
+    ey *= inv_cs2;
+    ez *= inv_cs2;
+    const C av = sqrt(ex * ex + ey * ey + ez * ez);
+    const C m = C(4) * C(P.beta) * ph * (ph - C(1)) * (ph - C(0.5)) - C(P.kappa) * lap -
+                av * C(P.wet) * (ph - ph * ph);
+    mu[n] = m;
+  } else if (w & kGhost) {
+    phi[n] = sphi[t];
+  }
+}
+
+// ------------------------------------------------------------------ node update
+// MODE 0: collide and write f*, g*, s.  MODE 1: write p and u only (fields).
+// MODE 2: write s only (initial s of the time-derivative term).
+template <class L, int S, int MODE>
+__global__ void k_collide(const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
+                          const void* __restrict__ gsrc, void* __restrict__ fdst,
+                          void* __restrict__ gdst, const ComputeT<S>* __restrict__ phi,
+                          const ComputeT<S>* __restrict__ mu, ComputeT<S>* __restrict__ sprev,
+                          ComputeT<S>* __restrict__ out_p, ComputeT<S>* __restrict__ out_u,
+                          Geo G, Phys P) {
+  using C = ComputeT<S>;
+  constexpr int Q = L::Q;
+  int x, y, z;
+  if (!node_coords(G, x, y, z)) return;
+  const long long n = G.idx(x, y, z);
+  const uint32_t word = nodes[n];
+  if (!(word & kZeta)) return;
+  long long nb[Q];
+  neighbours<L>(G, x, y, z, nb);
+
+  using FS = Set<S, false>;
+  using GS = Set<S, true>;
+  C f[Q], g[Q];
+  f[0] = C(FS::load_rest(fsrc, n));
+  const double g0 = GS::load_rest(gsrc, n);
+  g[0] = C(0);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    f[i] = pull<L, FS>(fsrc, i, n, nb, word, G.NQ, P.scale_f);
+    g[i] = pull<L, GS>(gsrc, i, n, nb, word, G.NQ, P.scale_g);
+  }
+  const C ph = phi[n];
+  const C m = mu[n];
+  const C inv_cs2 = C(3);
+  C gx = C(0), gy = C(0), gz = C(0);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const C v = C(L::w(i)) * phi[nb[i]];
+    gx += C(L::cx(i)) * v;
+    gy += C(L::cy(i)) * v;
+    gz += C(L::cz(i)) * v;
+  }
+  gx *= inv_cs2;
+  gy *= inv_cs2;
+  gz *= inv_cs2;
+  const C drho = C(P.rho_l - P.rho_g);
+  const C rho = C(P.rho_g) + ph * drho;
+  const C rx = drho * gx, ry = drho * gy, rz = drho * gz;           // grad rho
+  const C Fx = m * gx + C(P.Fb[0]), Fy = m * gy + C(P.Fb[1]),
+          Fz = (L::D == 3) ? m * gz + C(P.Fb[2]) : C(0);
+  C mx = C(0), my = C(0), mz = C(0), sumf = C(0);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    mx += C(L::cx(i)) * f[i];
+    my += C(L::cy(i)) * f[i];
+    mz += C(L::cz(i)) * f[i];
+    sumf += f[i];
+  }
+  const C inv_rho = C(1) / rho;
+  const C ux = (mx + C(0.5) * Fx) * inv_rho;
+  const C uy = (my + C(0.5) * Fy) * inv_rho;
+  const C uz = (mz + C(0.5) * Fz) * inv_rho;
+  const C uu = ux * ux + uy * uy + uz * uz;
+  const C ugr = ux * rx + uy * ry + uz * rz;                          // u . grad rho
+  const C w0 = C(L::w(0));
+  const C s0 = -w0 * uu * C(0.5) * inv_cs2;
+  const C p = (sumf + C(0.5) * ugr + rho * s0) / (inv_cs2 * (C(1) - w0));
+  const C s = ux * gx + uy * gy + uz * gz;                            // u . grad phi
+
+  if (MODE == 1) {
+    out_p[n] = p;
+    out_u[n] = ux;
+    out_u[G.NQ + n] = uy;
+    if (L::D == 3) out_u[2 * G.NQ + n] = uz;
+    return;
+  }
+  if (MODE == 2) {
+    sprev[n] = s;
+    return;
+  }
+
+  // phase-field collision: Eq. (BGK) with the time derivative of G_i as a
+  // backward difference of s, G_i + dG_i/2 = w_i k_i (1.5 s - 0.5 s_prev)
+  const C sp = sprev[n];
+  const C srcf = C(1.5) * s - C(0.5) * sp;
+  const C itg = C(P.inv_tau_g);
+  const C am = C(P.alpha) * m;
+  // g_0 - g_0^eq = g_0 - phi + (1 - w_0) alpha mu = (1 - w_0) alpha mu - sum_{i>0} g_i,
+  // formed from small terms only so that g_0 (about phi) is rounded once.
+  C gsmall = C(0);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) gsmall += g[i];
+  {
+    const C d0 = (C(1) - w0) * am - gsmall;
+    const C inc = w0 * C(L::k(0)) * srcf - d0 * itg;
+    GS::store_rest(gdst, n, g0 + (double)inc);
+  }
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const C wi = C(L::w(i));
+    const C gp = g[i] - (g[i] - wi * am) * itg + wi * C(L::k(i)) * srcf;
+    GS::store(gdst, i, n, G.NQ, gp, P.scale_g);
+  }
+  // hydrodynamic collision
+  C tau = C(P.tau);
+  if (P.visc_var) tau = (ph * C(P.nu_l - P.nu_g) + C(P.nu_g)) * inv_cs2 + C(0.5);
+  const C itau = C(1) / tau;
+  const C ffac = C(1) - C(0.5) * itau;
+  const C pc = p * inv_cs2;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const C wi = C(L::w(i));
+    const C cx = C(L::cx(i)), cy = C(L::cy(i)), cz = C(L::cz(i));
+    const C cu = cx * ux + cy * uy + cz * uz;
+    const C cF = cx * Fx + cy * Fy + cz * Fz;
+    const C cr = cx * rx + cy * ry + cz * rz;
+    const C si = wi * (cu * inv_cs2 + C(0.5) * cu * cu * inv_cs2 * inv_cs2 - C(0.5) * uu * inv_cs2);
+    const C feq = pc * (i == 0 ? wi - C(1) : wi) + rho * si;
+    // Eq. (GGi): u.grad rho + c.F/cs2 + [(c.u)(c.grad rho) - cs2 u.grad rho]/cs2
+    const C Fi = ffac * wi * (ugr + cF * inv_cs2 + (cu * cr - ugr * C(kCs2)) * inv_cs2);
+    const C fp = f[i] - (f[i] - feq) * itau + Fi;
+    if (i == 0) FS::store_rest(fdst, n, typename FS::R(fp));
+    else FS::store(fdst, i, n, G.NQ, fp, P.scale_f);
+  }
+  sprev[n] = s;
+}
+
+// ------------------------------------------------------------------ init
+// g at t = 0 is g_eq(phi0, mu0) after streaming; store it where the first pull
+// will find it (the inverse of the pull map).  f = 0 is set by a memset.
+template <class L, int S>
+__global__ void k_init_g(const uint32_t* __restrict__ nodes, void* __restrict__ gdst,
+                         const ComputeT<S>* __restrict__ phi, const ComputeT<S>* __restrict__ mu,
+                         Geo G, Phys P) {
+  using C = ComputeT<S>;
+  int x, y, z;
+  if (!node_coords(G, x, y, z)) return;
+  const long long n = G.idx(x, y, z);
+  const uint32_t word = nodes[n];
+  if (!(word & kZeta)) return;
+  long long nb[L::Q];
+  neighbours<L>(G, x, y, z, nb);
+  using GS = Set<S, true>;
+  const C am = C(P.alpha) * mu[n];
+  GS::store_rest(gdst, n, (double)phi[n] - (1.0 - L::w(0)) * (double)am);
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    const C geq = C(L::w(i)) * am;
+    const bool bb = (word >> (kLinkShift + i)) & 1u;
+    if (bb)
+      GS::store(gdst, L::opp(i), n, G.NQ, geq, P.scale_g);
+    else
+      GS::store(gdst, i, nb[L::opp(i)], G.NQ, geq, P.scale_g);
+  }
+}
+
+// ------------------------------------------------------------------ reductions
+// Record layout (doubles): see kRec* below.
+enum {
+  kRecMass = 0, kRecS, kRecResid, kRecNonfinite, kRecCount,
+  kRecX, kRecY, kRecZ, kRecXX, kRecXY, kRecXZ, kRecYY, kRecYZ, kRecZZ,
+  kRecXR, kRecYR, kRecZR, kRecRR, kRecAbsMax, kRecN
+};
+
+struct Wall {
+  int kind;          // 0 none, 1 plane, 2 ball
+  double p[3], nrm[3], radius, width;
+  double ref[3];     // coordinates are taken relative to this point
+};
+
+__device__ inline double wall_dist(const Wall& W, double x, double y, double z) {
+  if (W.kind == 1)
+    return (x - W.p[0]) * W.nrm[0] + (y - W.p[1]) * W.nrm[1] + (z - W.p[2]) * W.nrm[2];
+  const double dx = x - W.p[0], dy = y - W.p[1], dz = z - W.p[2];
+  return sqrt(dx * dx + dy * dy + dz * dz) - W.radius;
+}
+
+template <class C>
+__device__ inline void add_point(double* acc, const Wall& W, double x, double y, double z) {
+  if (W.kind == 0 || wall_dist(W, x, y, z) < W.width) return;
+  const double X = x - W.ref[0], Y = y - W.ref[1], Z = z - W.ref[2];
+  const double r2 = X * X + Y * Y + Z * Z;
+  acc[kRecCount] += 1.0;
+  acc[kRecX] += X; acc[kRecY] += Y; acc[kRecZ] += Z;
+  acc[kRecXX] += X * X; acc[kRecXY] += X * Y; acc[kRecXZ] += X * Z;
+  acc[kRecYY] += Y * Y; acc[kRecYZ] += Y * Z; acc[kRecZZ] += Z * Z;
+  acc[kRecXR] += X * r2; acc[kRecYR] += Y * r2; acc[kRecZR] += Z * r2; acc[kRecRR] += r2;
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// One partial record per workgroup; blockDim must be a multiple of 64 (<= 1024).
+// Interface points lie on edges (x, x + e_a) inside the domain between two
+// zeta = 1 nodes where exactly one phi is below 1/2 (no periodic seam).
+template <class L, class C>
+__global__ void k_reduce_partial(const uint32_t* __restrict__ nodes, const C* __restrict__ phi,
+                                 const C* __restrict__ s, C* __restrict__ snap,
+                                 double* __restrict__ partial, Geo G, Wall W, int update_snap) {
+  __shared__ double red[16][kRecN];
+  double acc[kRecN];
+#pragma unroll
+  for (int k = 0; k < kRecN; ++k) acc[k] = 0.0;
+  int x, y, z;
+  if (node_coords(G, x, y, z)) {
+    const long long n = G.idx(x, y, z);
+    const uint32_t w = nodes[n];
+    if (w & kZeta) {
+      const double ph = (double)phi[n];
+      acc[kRecMass] = ph;
+      acc[kRecS] = (double)s[n];
+      const double sn = (double)snap[n];
+      acc[kRecResid] = fabs(ph - sn);
+      acc[kRecAbsMax] = fabs(ph);
+      if (!isfinite(ph) || !isfinite(acc[kRecS])) acc[kRecNonfinite] = 1.0;
+      if (update_snap) snap[n] = phi[n];
+      const double X = x - G.pad[0], Y = y - G.pad[1], Z = (L::D == 3) ? z - G.pad[2] : 0;
+      const int P3[3] = {G.PX, G.PY, G.PZ};
+      const int c3[3] = {x, y, z};
+#pragma unroll
+      for (int a = 0; a < L::D; ++a) {
+        if (c3[a] + 1 >= P3[a]) continue;
+        const long long n2 = n + (a == 0 ? 1LL : a == 1 ? (long long)G.SX : (long long)G.SX * G.PY);
+        if (!(nodes[n2] & kZeta)) continue;
+        const double p2 = (double)phi[n2];
+        if ((ph < 0.5) == (p2 < 0.5)) continue;
+        const double t = (0.5 - ph) / (p2 - ph);
+        add_point<C>(acc, W, X + (a == 0 ? t : 0.0), Y + (a == 1 ? t : 0.0), Z + (a == 2 ? t : 0.0));
+      }
+    }
+  }
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  const int lane = tid & 63, wv = tid >> 6;
+  const int nw = (blockDim.x * blockDim.y * blockDim.z + 63) / 64;
+#pragma unroll
+  for (int k = 0; k < kRecN; ++k) {
+    const double v = (k == kRecResid || k == kRecAbsMax) ? wave_max(acc[k]) : wave_sum(acc[k]);
+    if (lane == 0) red[wv][k] = v;
+  }
+  __syncthreads();
+  if (tid < kRecN) {
+    double v = red[0][tid];
+    for (int j = 1; j < nw; ++j)
+      v = (tid == kRecResid || tid == kRecAbsMax) ? fmax(v, red[j][tid]) : v + red[j][tid];
+    const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+    partial[b * kRecN + tid] = v;
+  }
+}
+
+// Sums nparts partial records in a fixed order (deterministic); one workgroup of 256.
+template <int NR>
+__global__ void k_reduce_final(const double* __restrict__ partial, long long nparts,
+                               double* __restrict__ out) {
+  static_assert(NR == kRecN, "record size");
+  __shared__ double red[4][kRecN];
+  double acc[kRecN];
+#pragma unroll
+  for (int k = 0; k < kRecN; ++k) acc[k] = 0.0;
+  for (long long b = threadIdx.x; b < nparts; b += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < kRecN; ++k) {
+      const double v = partial[b * kRecN + k];
+      acc[k] = (k == kRecResid || k == kRecAbsMax) ? fmax(acc[k], v) : acc[k] + v;
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kRecN; ++k) {
+    const double v = (k == kRecResid || k == kRecAbsMax) ? wave_max(acc[k]) : wave_sum(acc[k]);
+    if (lane == 0) red[wv][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kRecN) {
+    const int k = threadIdx.x;
+    double v = red[0][k];
+    for (int j = 1; j < (int)(blockDim.x / 64); ++j)
+      v = (k == kRecResid || k == kRecAbsMax) ? fmax(v, red[j][k]) : v + red[j][k];
+    out[k] = v;
+  }
+}
+
+}  // namespace pflbm

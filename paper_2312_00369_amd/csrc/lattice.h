@@ -1,0 +1,74 @@
+// Velocity sets used by the kernels and the host classifier.
+//
+// D2Q9 (Sec. 2.1.2, Eq. ci): rest, four axis and four diagonal vectors,
+// weights 4/9, 1/9, 1/36.  D3Q19 (Eq. 3ci): rest, six axis and twelve edge
+// vectors, weights 1/3, 1/18, 1/36.  c_s^2 = 1/3 for both.
+// k_i is the bracket of the phase source G_i (Eq. F_i):
+//   k_i = -1 + (|c_i|^2 - D c_s^2) / (2 c_s^2)
+// which is -2, -1/2, 1 for D2Q9 and -5/2, -1, 1/2 for D3Q19.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pflbm {
+
+struct D2Q9 {
+  static constexpr int D = 2;
+  static constexpr int Q = 9;
+  __host__ __device__ static constexpr int cx(int i) {
+    constexpr int v[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    return v[i];
+  }
+  __host__ __device__ static constexpr int cy(int i) {
+    constexpr int v[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    return v[i];
+  }
+  __host__ __device__ static constexpr int cz(int) { return 0; }
+  __host__ __device__ static constexpr int opp(int i) {
+    constexpr int v[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    return v[i];
+  }
+  __host__ __device__ static constexpr double w(int i) {
+    return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+  }
+  __host__ __device__ static constexpr double k(int i) {
+    return i == 0 ? -2.0 : (i < 5 ? -0.5 : 1.0);
+  }
+};
+
+struct D3Q19 {
+  static constexpr int D = 3;
+  static constexpr int Q = 19;
+  __host__ __device__ static constexpr int cx(int i) {
+    constexpr int v[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return v[i];
+  }
+  __host__ __device__ static constexpr int cy(int i) {
+    constexpr int v[19] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return v[i];
+  }
+  __host__ __device__ static constexpr int cz(int i) {
+    constexpr int v[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+    return v[i];
+  }
+  __host__ __device__ static constexpr int opp(int i) {
+    constexpr int v[19] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
+    return v[i];
+  }
+  __host__ __device__ static constexpr double w(int i) {
+    return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+  }
+  __host__ __device__ static constexpr double k(int i) {
+    return i == 0 ? -2.5 : (i < 7 ? -1.0 : 0.5);
+  }
+};
+
+constexpr double kCs2 = 1.0 / 3.0;
+
+// Node word bits (one uint32 per padded node).
+constexpr unsigned kZeta = 1u;        // fluid or boundary node: carries f and g
+constexpr unsigned kFluid = 2u;       // epsilon = 1
+constexpr unsigned kGhost = 4u;       // zeta = 0 node one link from a zeta = 1 node
+constexpr int kLinkShift = 8;         // bit kLinkShift + i: node - c_i is zeta = 0
+
+}  // namespace pflbm

@@ -1,0 +1,206 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded inputs.
+
+Tolerances: FP64 storage |dphi|_inf <= 1e-10 (rounding order only); FP32 storage
+|dphi|_inf <= 1e-5 against the FP64 oracle; contact angle within 0.5 degrees.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from tests.helpers import maxdiff, oracle_for, oracle_theta
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _zeta(case):
+    return (case.classes() & 1).astype(bool)
+
+
+def _compare(gf, of, zeta, tol_phi, tol_other):
+    assert maxdiff(gf["phi"], of["phi"], zeta) <= tol_phi, maxdiff(gf["phi"], of["phi"], zeta)
+    assert maxdiff(gf["mu"], of["mu"], zeta) <= tol_other
+    assert maxdiff(gf["p"], of["p"], zeta) <= tol_other
+    for d in range(gf["u"].shape[0]):
+        assert maxdiff(gf["u"][d], of["u"][d], zeta) <= tol_other
+
+
+def test_init_fields_fp64(P):
+    c = workloads.config0()
+    g = P.Case.from_case(c, "f64")
+    o = oracle_for(c)
+    zeta = _zeta(g)
+    assert np.array_equal(zeta, o.domain(o.zeta))
+    _compare(g.fields(), o.fields(), zeta, 1e-13, 1e-13)
+    # ghost values (phi on ghost nodes is reported too)
+    ghost = (g.classes() & 4).astype(bool)
+    assert maxdiff(g.fields()["phi"], o.fields()["phi"], ghost) <= 1e-13
+
+
+@pytest.mark.parametrize("shape,periodic", [((128, 64), (True, False)), ((67, 37), (True, False)),
+                                            ((61, 45), (False, False)), ((5, 33), (True, False))])
+def test_parity_fp64_short(P, shape, periodic):
+    """200 steps on several shapes, including ragged tiles and a 5-wide periodic domain."""
+    nx, ny = shape
+    c = workloads.flat_droplet_case(nx, ny, min(20.0, 0.3 * ny), 60.0, 4.0)
+    c["periodic"] = periodic
+    g = P.Case.from_case(c, "f64")
+    o = oracle_for(c)
+    zeta = _zeta(g)
+    for k in range(4):
+        g.step(50)
+        o.step(50)
+        _compare(g.fields(), o.fields(), zeta, 1e-12, 1e-12)
+        assert abs(g.diagnostics()["mass"] - o.mass()) <= 1e-11 * o.mass()
+
+
+def test_parity_fp64_config0_golden(P):
+    """configs[0]: 128x64 FP64, 5000 steps; fields and mass trajectory against the
+    stored oracle run (tests/golden/make_golden.py)."""
+    gold = np.load(os.path.join(GOLDEN, "config0_fp64.npz"), allow_pickle=False)
+    c = workloads.config0()
+    g = P.Case.from_case(c, "f64")
+    zeta = _zeta(g)
+    every = int(gold["mass_every"])
+    masses = []
+    for k in range(len(gold["mass"])):
+        masses.append(g.diagnostics()["mass"])
+        if k + 1 < len(gold["mass"]):
+            g.step(every)
+    assert g.steps == int(gold["steps"])
+    rel = np.abs(np.array(masses) - gold["mass"]) / gold["mass"]
+    assert rel.max() <= 1e-10, rel.max()
+    f = g.fields()
+    assert maxdiff(f["phi"], gold["phi"], zeta) <= 1e-10
+    assert maxdiff(f["p"], gold["p"], zeta) <= 1e-10
+    d = g.diagnostics()
+    assert abs(d["theta_deg"] - float(gold["theta"])) <= 0.5
+
+
+def test_parity_fp32_config0_golden(P):
+    gold = np.load(os.path.join(GOLDEN, "config0_fp64.npz"), allow_pickle=False)
+    c = workloads.config0()
+    g = P.Case.from_case(c, "f32")
+    zeta = _zeta(g)
+    g.step(int(gold["steps"]))
+    f = g.fields()
+    err = maxdiff(f["phi"], gold["phi"], zeta)
+    print(f"FP32 |dphi|_inf after {int(gold['steps'])} steps: {err:.3e}")
+    assert err <= 1e-5
+    d = g.diagnostics()
+    assert abs(d["theta_deg"] - float(gold["theta"])) <= 0.5
+    rel_mass = abs(d["mass"] - float(gold["mass"][-1])) / float(gold["mass"][-1])
+    print(f"FP32 relative mass difference: {rel_mass:.3e}")
+
+
+def test_parity_d3q19_fp64(P):
+    """D3Q19 for both sets, staircase inclined wall, all faces walls: 40 steps."""
+    c = workloads.inclined_droplet_case_3d(n=24, radius=7.0, theta=45.0, width=4.0)
+    g = P.Case.from_case(c, "f64")
+    o = oracle_for(c)
+    zeta = _zeta(g)
+    assert np.array_equal(zeta, o.domain(o.zeta))
+    _compare(g.fields(), o.fields(), zeta, 1e-13, 1e-13)
+    for k in range(2):
+        g.step(20)
+        o.step(20)
+        _compare(g.fields(), o.fields(), zeta, 1e-12, 1e-12)
+
+
+def test_parity_d3q19_periodic_fp32(P):
+    c = workloads.inclined_droplet_case_3d(n=20, radius=6.0, theta=120.0, width=4.0)
+    c["periodic"] = (False, True, False)
+    g = P.Case.from_case(c, "f32")
+    o = oracle_for(c)
+    zeta = _zeta(g)
+    g.step(30)
+    o.step(30)
+    _compare(g.fields(), o.fields(), zeta, 1e-5, 1e-5)
+
+
+def test_mass_budget_identity(P):
+    """M(t+1) - M(t) = -(1.5 S(t) - 0.5 S(t-1)) with S the sum of s over zeta = 1."""
+    c = workloads.config0()
+    g = P.Case.from_case(c, "f64")
+    g.step(100)
+    d0 = g.diagnostics()
+    g.step(1)
+    d1 = g.diagnostics()
+    resid = d1["mass"] - d0["mass"] + 1.5 * d1["s_sum"] - 0.5 * d0["s_sum"]
+    assert abs(resid) <= 1e-12 * d0["mass"], resid
+
+
+def test_graph_equals_eager_bitwise(P):
+    c = workloads.flat_droplet_case(96, 48, 14.0, 120.0, 4.0)
+    a = P.Case.from_case(c, "f32")
+    b = P.Case.from_case(c, "f32")
+    a.set_graph_chunk(0)
+    b.set_graph_chunk(16)
+    a.step(101)
+    b.step(101)
+    fa, fb = a.fields(), b.fields()
+    assert np.array_equal(fa["phi"], fb["phi"]) and np.array_equal(fa["u"], fb["u"])
+
+
+def test_tile_shape_invariance_bitwise(P):
+    c = workloads.flat_droplet_case(150, 70, 20.0, 45.0, 4.0)
+    ref = None
+    for tile in [(64, 4, 1), (128, 2, 1), (64, 1, 1), (256, 4, 1)]:
+        g = P.Case.from_case(c, "f32")
+        g.set_tile(*tile)
+        g.step(60)
+        f = g.fields()
+        if ref is None:
+            ref = f
+        else:
+            assert np.array_equal(ref["phi"], f["phi"]) and np.array_equal(ref["p"], f["p"])
+
+
+def test_translation_bitwise(P):
+    """Shifting the initial field along the periodic axis shifts the result exactly."""
+    c = workloads.flat_droplet_case(128, 48, 14.0, 70.0, 4.0)
+    c2 = dict(c)
+    c2["phi0"] = np.roll(c["phi0"], 37, axis=1)
+    a = P.Case.from_case(c, "f32")
+    b = P.Case.from_case(c2, "f32")
+    a.step(80)
+    b.step(80)
+    assert np.array_equal(np.roll(a.fields()["phi"], 37, axis=1), b.fields()["phi"])
+
+
+def test_checkpoint_resume_bitwise(P):
+    c = workloads.flat_droplet_case(96, 48, 14.0, 60.0, 4.0)
+    a = P.Case.from_case(c, "f32")
+    a.step(30)
+    blob = a.get_state()
+    a.step(40)
+    b = P.Case.from_case(c, "f32")
+    b.set_state(blob)
+    assert b.steps == 30
+    b.step(40)
+    assert np.array_equal(a.fields()["phi"], b.fields()["phi"])
+
+
+def test_workspace_create_matches(P):
+    c = workloads.flat_droplet_case(96, 48, 14.0, 60.0, 4.0)
+    a = P.Case.from_case(c, "f32")
+    b = P.Case.from_case(c, "f32", workspace=True)
+    a.step(25)
+    b.step(25)
+    assert np.array_equal(a.fields()["phi"], b.fields()["phi"])
+
+
+def test_uniform_phase_is_fixed_point(P):
+    """phi = 1 everywhere with walls: mu = 0, F = 0, u = 0; populations do not move."""
+    c = workloads.flat_droplet_case(64, 32, 10.0, 60.0, 4.0)
+    c["phi0"] = np.ones_like(c["phi0"])
+    c["theta_deg"] = 90.0   # cos(theta) = 0: no wall term at phi = 1 either way
+    g = P.Case.from_case(c, "f64")
+    f0 = g.fields()
+    g.step(50)
+    f1 = g.fields()
+    assert np.array_equal(f0["phi"], f1["phi"])
+    assert np.abs(f1["u"]).max() == 0.0

@@ -1,0 +1,130 @@
+"""CPU tests of the C interface: the library loads, exports every declared
+symbol, and its host-side pieces (lattice tables, node classification,
+parameter checks, footprint) agree with the oracle and the paper.  No device
+work is started here."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import lattice as olat
+from tests.helpers import oracle_for
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pflbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pflbm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(P):
+    lib = ct.CDLL(P.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding wraps every one of them under the same name
+    assert set(names) <= set(P.EXPORTED), set(names) - set(P.EXPORTED)
+
+
+@pytest.mark.parametrize("name,L", [("D2Q9", olat.D2Q9), ("D3Q19", olat.D3Q19)])
+def test_library_lattice_tables(P, name, L):
+    t = P.lattice_table(name)
+    D = L.D
+    c = t["c"][:, :D].astype(float)
+    w = t["w"]
+    assert abs(w.sum() - 1) < 1e-15
+    assert np.abs(np.einsum("q,qa,qb->ab", w, c, c) - np.eye(D) / 3).max() < 1e-15
+    assert np.array_equal(t["c"][t["opp"]], -t["c"])
+    # same velocity set and weights as the oracle (built from the paper's formulas)
+    lib_set = {tuple(v[:D]): (wi, ki) for v, wi, ki in zip(t["c"], w, t["k"])}
+    for v, wi, ki in zip(L.c, L.w, L.k):
+        wl, kl = lib_set[tuple(int(a) for a in v)]
+        assert abs(wl - wi) < 1e-16 and abs(kl - ki) < 1e-15
+    if D == 2:
+        assert np.all(t["c"][:, 2] == 0)
+
+
+def _classes_from_oracle(c):
+    o = oracle_for(c)
+    z = o.domain(o.zeta)
+    e = o.domain(o.eps) > 0
+    g = o.domain(o.ghost)
+    return z.astype(np.uint8) | (e.astype(np.uint8) << 1) | (g.astype(np.uint8) << 2)
+
+
+CASES = {
+    "flat": lambda: workloads.flat_droplet_case(37, 21, 6.0, 60.0),
+    "flat_closed": lambda: dict(workloads.flat_droplet_case(37, 21, 6.0, 60.0),
+                                periodic=(False, False)),
+    "cylinder": lambda: workloads.cylinder_case(64, 32, 0.3, 100.0),
+    "incline2d": lambda: dict(workloads.flat_droplet_case(40, 30, 6.0, 60.0),
+                              mask=workloads.inclined_plane((40, 30), (20.0, 10.0), 26.0)),
+    "incline3d": lambda: workloads.inclined_droplet_case_3d(n=14, radius=4.0, width=3.0),
+    "sphere3d": lambda: dict(workloads.inclined_droplet_case_3d(n=12, radius=3.0, width=3.0),
+                             mask=workloads.ball((12, 12, 12), (6.0, 6.0, 3.0), 3.5),
+                             periodic=(True, False, True)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_host_classification_matches_oracle(P, name):
+    """Node marks of Sec. 2.2.2 from the library's host code equal the oracle's
+    (written separately); ghost nodes inside the domain included."""
+    c = CASES[name]()
+    prm = P.params_from_case(c, "f32")
+    got = P.classify(prm, c["mask"])
+    want = _classes_from_oracle(c)
+    assert np.array_equal(got, want)
+
+
+def _params(P, **kw):
+    c = workloads.flat_droplet_case(32, 16, 5.0, 60.0)
+    return P.params_from_case(c, "f32", **kw)
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("tau", 0.5, -1), ("mobility", 0.0, -1), ("theta_deg", 0.0, -1),
+    ("theta_deg", 180.0, -1), ("beta", -1.0, -1), ("rho_g", 0.0, -1),
+    ("lattice", 7, -6), ("storage", 9, -6), ("nx", 0, -1), ("nz", 3, -1),
+    ("struct_size", 8, -1), ("tau_phi", 0.4, -1), ("wall_kind", 5, -1)])
+def test_parameter_validation(P, field, value, code):
+    prm = _params(P)
+    setattr(prm, field, value)
+    n = ct.c_size_t(0)
+    rc = P.lib.pflbm_footprint(ct.byref(prm), ct.byref(n))
+    assert rc == code
+    assert len(P.lib.pflbm_last_error()) > 0
+
+
+def test_null_arguments(P):
+    prm = _params(P)
+    assert P.lib.pflbm_footprint(None, None) == -1
+    assert P.lib.pflbm_footprint(ct.byref(prm), None) == -1
+    out = ct.c_void_p()
+    assert P.lib.pflbm_create(ct.byref(prm), None, None, None, ct.byref(out)) == -1
+    assert P.lib.pflbm_step(None, 1) == -1
+    assert P.lib.pflbm_fields(None, None, None, None, None) == -1
+    assert P.lib.pflbm_group_step(None, 1) == -1
+    assert P.lib.pflbm_step_count(None) == -1
+    P.lib.pflbm_destroy(None)            # no-op
+    P.lib.pflbm_group_destroy(None)      # no-op
+    assert P.lib.pflbm_strerror(-4) == b"non-finite values"
+
+
+def test_footprint_scales_with_storage(P):
+    """Bytes per node: FP64 > FP32 > FP16-deviation, and linear in the node count."""
+    c = workloads.flat_droplet_case(256, 128, 20.0, 60.0)
+    b = {s: P.footprint(P.params_from_case(c, s)) / (256 * 130) for s in ("f64", "f32", "f16dev")}
+    assert b["f64"] > b["f32"] > b["f16dev"]
+    # D2Q9 FP32: f 9x4 B and g 8x4 + 8 B per buffer, two buffers each, plus 5 fields
+    assert 2 * (36 + 40) + 4 * 4 + 4 < b["f32"] < 2 * (36 + 40) + 4 * 4 + 4 + 8
+    c2 = workloads.flat_droplet_case(512, 256, 20.0, 60.0)
+    r = P.footprint(P.params_from_case(c2, "f32")) / P.footprint(P.params_from_case(c, "f32"))
+    assert 3.9 < r < 4.1
