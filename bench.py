@@ -1,0 +1,162 @@
+"""Benchmark of the plain solver: MLUPS and % of HBM roofline on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Workload: D2Q9 phase-field LBM in FP32 storage on a 1024 x 512 grid, droplet
+R = 80 on a flat wall, theta = 60 deg, rho_l / rho_g = 10, W = 5 (walls top and
+bottom, periodic in x).  Inputs are built on the host, the case is created once
+(all state resident in HBM), then W warm-up steps and K timed steps run,
+bracketed by device synchronisation and timed with HIP events on the stream
+the library launches on.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic bytes per node update (persistent state read once and written
+# once plus one class byte): D2Q9 FP32 153, D3Q19 FP32 313, D3Q19 FP16-dev 165.
+ALG_BYTES = {("D2Q9", "f32"): 153, ("D2Q9", "f64"): 305, ("D3Q19", "f32"): 313,
+             ("D3Q19", "f16dev"): 165}
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50000)
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--theta", type=float, default=60.0)
+    ap.add_argument("--chunk", type=int, default=100, help="steps per captured HIP graph")
+    ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--variant", type=int, default=1, help="fused step tile variant")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the DRAM-bound twin")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for counter scaling)")
+    return ap.parse_args()
+
+
+def time_steps(torch, case, steps, warmup):
+    case.step(warmup)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    case.step(steps)
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1)
+
+
+def cpu_baseline(c, budget_s=15.0):
+    """The FP64 oracle, unmodified, on a bounded sample of the same workload."""
+    import numpy as np
+    from oracle.model import Oracle, Params, beta_kappa
+    beta, kappa = beta_kappa(c["sigma"], c["width"])
+    o = Oracle(Params(lattice=c["lattice"], shape=c["shape"], periodic=c["periodic"], tau=0.8,
+                      mobility=0.1, beta=beta, kappa=kappa, theta_deg=c["theta_deg"]),
+               c["mask"], c["phi0"])
+    nodes = int(o.zeta.sum())
+    o.step(1)
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        o.step(1)
+        steps += 1
+    dt = time.perf_counter() - t0
+    return dict(value=round(nodes * steps / dt / 1e6, 4), unit="MLUPS", cores=1, kind="oracle",
+                sample=f"{c['shape'][0]}x{c['shape'][1]} D2Q9 FP64 NumPy oracle, {steps} steps "
+                       f"after one untimed step ({dt:.1f} s, single-threaded NumPy)")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2312_00369_amd as P
+    import workloads
+
+    torch.cuda.init()
+    stream = torch.cuda.Stream()          # default priority; the library launches on it
+    with torch.cuda.stream(stream):
+        line = run(a, torch, P, workloads, stream)
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(workloads.config1(theta=a.theta))
+    print(json.dumps(line), flush=True)
+
+
+def run(a, torch, P, workloads, stream):
+    c = workloads.config1(theta=a.theta)
+    case = P.Case.from_case(c, "f32", stream=stream)
+    case.set_graph_chunk(a.chunk)
+    case.set_step_kernel(a.variant)
+    nodes = int((case.classes() & 1).sum())
+    ms = time_steps(torch, case, a.steps, a.warmup)
+    ms_step = ms / a.steps
+    mlups = nodes * a.steps / (ms / 1e3) / 1e6
+    d = case.diagnostics()
+    # live duration of the fused step kernel (HIP events around each launch on
+    # the case's stream)
+    kern_ms = case.profile(a.profile_steps)
+    step_kern_ms = float(kern_ms[3])
+    alg = ALG_BYTES[("D2Q9", "f32")]
+    achieved = alg * nodes / (step_kern_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_step (fused time step)", "alg_bytes_per_node": alg,
+            "nodes_per_launch": nodes, "avg_ms": round(step_kern_ms, 5)}
+    # the three-kernel path on the same case, for reference
+    case.set_step_kernel(-1)
+    k3 = case.profile(a.profile_steps)
+    case.set_step_kernel(a.variant)
+    roof["three_kernel_path_ms"] = {"k_phi": round(float(k3[0]), 5), "k_mu": round(float(k3[1]), 5),
+                                    "k_collide": round(float(k3[2]), 5)}
+    line = {
+        "metric": "MLUPS (plain solver, 1 GPU)", "value": round(mlups, 1), "unit": "MLUPS",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "D2Q9 FP32 1024x512 flat-wall droplet R=80, theta=60, W=5, "
+                               "rho 10/1, tau 0.8, M 0.1, sigma 1e-3",
+                   "nodes": nodes, "graph_chunk": a.chunk},
+        "hbm_roofline_pct_step": round(100 * mlups * 1e6 * alg / (HBM_PEAK_GBS * 1e9), 2),
+        "roofline": roof,
+        "check": {"theta_deg": round(d["theta_deg"], 3), "mass": d["mass"],
+                  "nonfinite": d["nonfinite"]},
+    }
+    case.close()
+    if not a.no_extra:
+        # DRAM-bound twin: 8192 x 4096 (33.5 M nodes), same physics
+        big = workloads.config1(theta=a.theta, nx=8192, ny=4096)
+        cb = P.Case.from_case(big, "f32", stream=stream)
+        cb.set_graph_chunk(a.chunk)
+        cb.set_step_kernel(a.variant)
+        nb = int((cb.classes() & 1).sum())
+        k = 400
+        msb = time_steps(torch, cb, k, 20)
+        kb = cb.profile(20)
+        mlb = nb * k / (msb / 1e3) / 1e6
+        line["dram_twin"] = {"workload": "D2Q9 FP32 8192x4096", "MLUPS": round(mlb, 1),
+                             "hbm_roofline_pct": round(100 * mlb * 1e6 * alg / (HBM_PEAK_GBS * 1e9), 2),
+                             "k_step_ms": round(float(kb[3]), 4),
+                             "k_step_GBps_alg": round(alg * nb / (float(kb[3]) / 1e3) / 1e9, 1)}
+        cb.close()
+    if a.copy_calibration:
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = 2 * x.numel() * 4
+    return line
+
+
+if __name__ == "__main__":
+    main()

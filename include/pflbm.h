@@ -142,6 +142,17 @@ int pflbm_set_graph_chunk(pflbm_handle h, int32_t steps);
  * Drops any captured graph. */
 int pflbm_set_tile(pflbm_handle h, int32_t tx, int32_t ty, int32_t tz);
 
+/* Kernel path of pflbm_step: variant >= 0 selects a tile shape of the fused
+ * one-kernel step (the default is 2), -1 the three-kernel path (phi sum, mu
+ * stencil, collide-stream).  Every path gives bit-identical results.  Drops any
+ * captured graph. */
+int pflbm_set_step_kernel(pflbm_handle h, int32_t variant);
+
+/* Number of fused-step variants for a lattice; if tiles is non-NULL, fills up
+ * to capacity records of 5 ints: threads (by, bz) of a (64, by, bz) workgroup
+ * and the tile (tx, ty, tz) it updates.  (no device work) */
+int pflbm_step_variants(int32_t lattice, int32_t* tiles, int32_t capacity);
+
 /* Current fields as FP64 host arrays of nx*ny*nz (u: D arrays, component-major).
  * Any pointer may be NULL.  phi holds the ghost value on ghost nodes and 0 on
  * other solid nodes; p, u and mu are 0 on zeta = 0 nodes.  (sync) */
@@ -162,10 +173,11 @@ int pflbm_state_size(pflbm_handle h, size_t* bytes);
 int pflbm_get_state(pflbm_handle h, void* host, size_t bytes);
 int pflbm_set_state(pflbm_handle h, const void* host, size_t bytes);
 
-/* Time nsteps eager steps with HIP events around every kernel launch on the
- * case's stream; avg_ms[k] receives the mean duration in milliseconds of kernel
- * kind k for k < nkinds (0: phi sum, 1: mu stencil, 2: collide-stream; kinds
- * the library does not have read 0).  The steps count as real steps.  (sync) */
+/* Time nsteps (<= 100000) eager steps with HIP events around every kernel
+ * launch on the case's stream; avg_ms[k] receives the mean duration in
+ * milliseconds per step of kernel kind k for k < nkinds: 0 phi sum, 1 mu
+ * stencil, 2 collide-stream (three-kernel path), 3 fused step kernel; kinds the
+ * current path does not launch read 0.  The steps count as real steps.  (sync) */
 int pflbm_profile(pflbm_handle h, int64_t nsteps, double* avg_ms, int32_t nkinds);
 
 /* Time steps taken so far (-1 for a NULL handle). */

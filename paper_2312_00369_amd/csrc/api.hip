@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 
 #include "case.h"
@@ -729,33 +730,84 @@ int pflbm_set_state(pflbm_handle h, const void* host, size_t bytes) {
 int pflbm_profile(pflbm_handle h, int64_t nsteps, double* avg_ms, int32_t nkinds) {
   clear_error();
   if (int rc = check_handle(h)) return rc;
-  if (nsteps <= 0 || !avg_ms || nkinds <= 0) return set_error(PFLBM_EINVAL, "bad profile arguments");
-  constexpr int K = 3;
-  hipEvent_t ev[K + 1];
-  for (int k = 0; k <= K; ++k) PFLBM_HIP(hipEventCreate(&ev[k]));
-  double tot[K] = {0, 0, 0};
-  int rc = PFLBM_OK;
-  for (int64_t s = 0; s < nsteps && rc == PFLBM_OK; ++s) {
-    (void)hipEventRecord(ev[0], h->stream);
-    if ((rc = run_phi(h))) break;
-    (void)hipEventRecord(ev[1], h->stream);
-    if ((rc = run_mu(h))) break;
-    (void)hipEventRecord(ev[2], h->stream);
-    if ((rc = run_collide(h, 0, nullptr, nullptr))) break;
-    (void)hipEventRecord(ev[3], h->stream);
-    h->cur ^= 1;
-    h->step += 1;
-    if (hipEventSynchronize(ev[3]) != hipSuccess) { rc = set_error(PFLBM_EDEVICE, "event sync"); break; }
-    for (int k = 0; k < K; ++k) {
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
-      tot[k] += ms;
+  if (nsteps <= 0 || nsteps > 100000 || !avg_ms || nkinds <= 0)
+    return set_error(PFLBM_EINVAL, "bad profile arguments");
+  if (h->group) return set_error(PFLBM_ESTATE, "case is a group member");
+  // kinds: 0 k_phi, 1 k_mu, 2 k_collide (three-kernel path), 3 k_step (fused)
+  constexpr int K = 4;
+  const bool fused = h->variant >= 0;
+  const int per = fused ? 1 : 3;
+  const int64_t chunk = std::min<int64_t>(nsteps, 256);
+  std::vector<hipEvent_t> ev((size_t)chunk * per * 2, nullptr);
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto& x : ev) if (x) (void)hipEventDestroy(x);
+      return set_error(PFLBM_EDEVICE, "hipEventCreate failed");
     }
+  double tot[K] = {0, 0, 0, 0};
+  int rc = PFLBM_OK;
+  for (int64_t done = 0; done < nsteps && rc == PFLBM_OK;) {
+    const int64_t n = std::min<int64_t>(chunk, nsteps - done);
+    for (int64_t s = 0; s < n && rc == PFLBM_OK; ++s) {
+      hipEvent_t* e = &ev[(size_t)s * per * 2];
+      if (fused) {
+        (void)hipEventRecord(e[0], h->stream);
+        rc = run_step_fused(h);
+        (void)hipEventRecord(e[1], h->stream);
+      } else {
+        (void)hipEventRecord(e[0], h->stream);
+        if (!(rc = run_phi(h))) {
+          (void)hipEventRecord(e[1], h->stream);
+          (void)hipEventRecord(e[2], h->stream);
+          if (!(rc = run_mu(h))) {
+            (void)hipEventRecord(e[3], h->stream);
+            (void)hipEventRecord(e[4], h->stream);
+            rc = run_collide(h, 0, nullptr, nullptr);
+            (void)hipEventRecord(e[5], h->stream);
+          }
+        }
+      }
+      if (rc) break;
+      h->cur ^= 1;
+      h->step += 1;
+    }
+    if (rc) break;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) { rc = set_error(PFLBM_EDEVICE, "sync"); break; }
+    for (int64_t s = 0; s < n; ++s)
+      for (int k = 0; k < per; ++k) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[(size_t)(s * per + k) * 2], ev[(size_t)(s * per + k) * 2 + 1]);
+        tot[fused ? 3 : k] += ms;
+      }
+    done += n;
   }
-  for (int k = 0; k <= K; ++k) (void)hipEventDestroy(ev[k]);
+  for (auto& e : ev) (void)hipEventDestroy(e);
   if (rc) return rc;
   for (int k = 0; k < nkinds; ++k) avg_ms[k] = k < K ? tot[k] / (double)nsteps : 0.0;
   return PFLBM_OK;
+}
+
+int pflbm_set_step_kernel(pflbm_handle h, int32_t variant) {
+  clear_error();
+  if (int rc = check_handle(h)) return rc;
+  if (variant < -1 || variant >= kStepVariants)
+    return set_error(PFLBM_EINVAL, "step kernel variant %d outside [-1, %d)", variant, kStepVariants);
+  drop_graph(h);
+  h->variant = variant;
+  return PFLBM_OK;
+}
+
+int pflbm_step_variants(int32_t lattice, int32_t* tiles, int32_t capacity) {
+  clear_error();
+  if (lattice != PFLBM_D2Q9 && lattice != PFLBM_D3Q19)
+    return set_error(PFLBM_EUNSUPPORTED, "unknown lattice %d", lattice);
+  const int D = lattice == PFLBM_D2Q9 ? 2 : 3;
+  for (int v = 0; v < kStepVariants && v < capacity && tiles; ++v) {
+    int t[5];
+    step_variant_tile(D, v, t);
+    for (int k = 0; k < 5; ++k) tiles[5 * v + k] = t[k];
+  }
+  return kStepVariants;
 }
 
 }  // extern "C"

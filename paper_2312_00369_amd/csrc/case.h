@@ -77,6 +77,7 @@ struct pflbm_case_s {
   bool snap_valid = false;
   dim3 tile;
   int graph_chunk = 64;
+  int variant = 2;                // fused step kernel variant; -1 = three-kernel path
   hipGraphExec_t gexec = nullptr;
   int gexec_steps = 0;
   pflbm_group_s* group = nullptr;
@@ -90,4 +91,7 @@ int run_collide(pflbm_case_s* h, int mode, void* out_p, void* out_u);
 int run_init_g(pflbm_case_s* h);
 int run_reduce(pflbm_case_s* h, int update_snap, double* host_rec);
 int run_step_eager(pflbm_case_s* h);
+int run_step_fused(pflbm_case_s* h);
+constexpr int kStepVariants = 5;
+int step_variant_tile(int D, int v, int tile[5]);
 }  // namespace pflbm

@@ -53,6 +53,43 @@ struct Engine {
     return PFLBM_OK;
   }
 
+  template <int BY, int BZ, int KY, int KZ>
+  static int step_v(pflbm_case_s* h) {
+    const Geo& G = h->dv.geo;
+    constexpr int TY = BY * KY, TZ = (L::D == 3) ? BZ * KZ : 1;
+    const dim3 grid((G.PX + 63) / 64, (G.PY + TY - 1) / TY, (G.PZ + TZ - 1) / TZ);
+    const dim3 block(64, BY, (L::D == 3) ? BZ : 1);
+    const int c = h->cur;
+    hipLaunchKernelGGL((k_step<L, S, BY, (L::D == 3) ? BZ : 1, KY, (L::D == 3) ? KZ : 1>), grid,
+                       block, 0, h->stream, h->nodes, h->f[c], h->g[c], h->f[1 - c], h->g[1 - c],
+                       static_cast<C*>(h->s), G, h->dv.phys);
+    PFLBM_HIP(hipGetLastError());
+    return PFLBM_OK;
+  }
+
+  static int step_fused(pflbm_case_s* h) {
+    if (L::D == 2) {
+      switch (h->variant) {
+        case 0: return step_v<4, 1, 1, 1>(h);
+        case 1: return step_v<4, 1, 2, 1>(h);
+        case 2: return step_v<4, 1, 4, 1>(h);
+        case 3: return step_v<8, 1, 2, 1>(h);
+        case 4: return step_v<2, 1, 4, 1>(h);
+        default: break;
+      }
+    } else {
+      switch (h->variant) {
+        case 0: return step_v<2, 2, 1, 1>(h);
+        case 1: return step_v<2, 2, 2, 1>(h);
+        case 2: return step_v<2, 2, 2, 2>(h);
+        case 3: return step_v<4, 4, 1, 1>(h);
+        case 4: return step_v<4, 2, 1, 2>(h);
+        default: break;
+      }
+    }
+    return set_error(PFLBM_EINVAL, "unknown step variant %d", h->variant);
+  }
+
   static int init_g(pflbm_case_s* h) {
     const Geo& G = h->dv.geo;
     hipLaunchKernelGGL((k_init_g<L, S>), grid_of(G, h->tile), h->tile, 0, h->stream, h->nodes,
@@ -98,6 +135,7 @@ template <class L, int S> struct DoMu { static int go(pflbm_case_s* h) { return 
 template <class L, int S> struct DoCollide {
   static int go(pflbm_case_s* h, int m, void* p, void* u) { return Engine<L, S>::collide(h, m, p, u); }
 };
+template <class L, int S> struct DoStep { static int go(pflbm_case_s* h) { return Engine<L, S>::step_fused(h); } };
 template <class L, int S> struct DoInit { static int go(pflbm_case_s* h) { return Engine<L, S>::init_g(h); } };
 template <class L, int S> struct DoReduce {
   static int go(pflbm_case_s* h, int up) { return Engine<L, S>::reduce(h, up); }
@@ -111,6 +149,18 @@ int run_collide(pflbm_case_s* h, int mode, void* out_p, void* out_u) {
   return dispatch<DoCollide>(h, mode, out_p, out_u);
 }
 int run_init_g(pflbm_case_s* h) { return dispatch<DoInit>(h); }
+int run_step_fused(pflbm_case_s* h) { return dispatch<DoStep>(h); }
+
+// Tile of each fused-step variant: threads (64, by, bz), nodes (64, ty, tz).
+int step_variant_tile(int D, int v, int tile[5]) {
+  static const int t2[kStepVariants][5] = {
+      {4, 1, 64, 4, 1}, {4, 1, 64, 8, 1}, {4, 1, 64, 16, 1}, {8, 1, 64, 16, 1}, {2, 1, 64, 8, 1}};
+  static const int t3[kStepVariants][5] = {
+      {2, 2, 64, 2, 2}, {2, 2, 64, 4, 2}, {2, 2, 64, 4, 4}, {4, 4, 64, 4, 4}, {4, 2, 64, 4, 4}};
+  if (v < 0 || v >= kStepVariants) return -1;
+  for (int k = 0; k < 5; ++k) tile[k] = D == 2 ? t2[v][k] : t3[v][k];
+  return 0;
+}
 
 int run_reduce(pflbm_case_s* h, int update_snap, double* host_rec) {
   int rc = dispatch<DoReduce>(h, update_snap);
@@ -125,6 +175,12 @@ int run_reduce(pflbm_case_s* h, int update_snap, double* host_rec) {
 
 int run_step_eager(pflbm_case_s* h) {
   int rc;
+  if (h->variant >= 0) {
+    if ((rc = run_step_fused(h))) return rc;
+    h->cur ^= 1;
+    h->step += 1;
+    return PFLBM_OK;
+  }
   if ((rc = run_phi(h))) return rc;
   if ((rc = run_mu(h))) return rc;
   if ((rc = run_collide(h, 0, nullptr, nullptr))) return rc;

@@ -159,10 +159,79 @@ __global__ void k_phi(const uint32_t* __restrict__ nodes, const void* __restrict
   phi[n] = C(GS::load_rest(gsrc, n) + (double)small);
 }
 
+// ------------------------------------------------------------------ LDS stencil pieces
+// A tile of phi and node words in LDS with strides sx (x) and sxy (x*y).
+
+// Ghost mean over the 3^D block (Sec. 2.2.2); only zeta = 1 entries are read,
+// so filling ghosts in place is order-independent.
+template <class L, class C>
+__device__ inline C ghost_mean(const C* sphi, const uint32_t* sw, int t, int sx, int sxy) {
+  C num = C(0);
+  int den = 0;
+  constexpr int z0 = (L::D == 3) ? -1 : 0, z1 = (L::D == 3) ? 1 : 0;
+#pragma unroll
+  for (int dz = z0; dz <= z1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int t2 = t + dx + sx * dy + sxy * dz;
+        if (sw[t2] & kZeta) {
+          num += sphi[t2];
+          ++den;
+        }
+      }
+  return den > 0 ? num / C(den) : C(0);
+}
+
+// mu of Eq. (chemical_potencial2) at a zeta = 1 entry: isotropic Laplacian
+// (Eq. Laplace) of phi and a_v = |grad eps| (Eq. avvv) from the neighbours.
+template <class L, class C>
+__device__ inline C mu_at(const C* sphi, const uint32_t* sw, int t, int sx, int sxy,
+                          const Phys& P) {
+  const C ph = sphi[t];
+  C lap = C(0), ex = C(0), ey = C(0), ez = C(0);
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    const int t2 = t + L::cx(i) + sx * L::cy(i) + sxy * L::cz(i);
+    const C wi = C(L::w(i));
+    lap += C(2) * wi * (sphi[t2] - ph);
+    const C e = (sw[t2] & kFluid) ? C(1) : C(0);
+    ex += wi * C(L::cx(i)) * e;
+    ey += wi * C(L::cy(i)) * e;
+    ez += wi * C(L::cz(i)) * e;
+  }
+  const C inv_cs2 = C(3);
+  lap *= inv_cs2;
+  ex *= inv_cs2;
+  ey *= inv_cs2;
+  ez *= inv_cs2;
+  const C av = sqrt(ex * ex + ey * ey + ez * ez);
+  return C(4) * C(P.beta) * ph * (ph - C(1)) * (ph - C(0.5)) - C(P.kappa) * lap -
+         av * C(P.wet) * (ph - ph * ph);
+}
+
+// grad phi of Eq. (gradient) from neighbour values v(i) = phi(x + c_i).
+template <class L, class C, class Fn>
+__device__ inline void grad_of(Fn v, C& gx, C& gy, C& gz) {
+  gx = gy = gz = C(0);
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    const C t = C(L::w(i)) * v(i);
+    gx += C(L::cx(i)) * t;
+    gy += C(L::cy(i)) * t;
+    gz += C(L::cz(i)) * t;
+  }
+  gx *= C(3);
+  gy *= C(3);
+  gz *= C(3);
+}
+
 // ------------------------------------------------------------------ k_mu
 // Workgroup = one tile of blockDim nodes; LDS holds phi and node words of the
 // tile plus two halo layers (ghost nodes of the first halo layer need their own
 // neighbours).  Dynamic LDS bytes: (TX+4)(TY+4)(TZ+4 or 1) * (sizeof(C) + 4).
+// Writes mu on zeta = 1 nodes and phi on ghost nodes.
 template <class L, class C>
 __global__ void k_mu(const uint32_t* __restrict__ nodes, C* __restrict__ phi,
                      C* __restrict__ mu, Geo G, Phys P) {
@@ -203,27 +272,11 @@ __global__ void k_mu(const uint32_t* __restrict__ nodes, C* __restrict__ phi,
     sphi[t] = v;
   }
   __syncthreads();
-
-  // Ghost mean over the 3^D block: only zeta = 1 entries are read, so filling in
-  // place is order-independent.
   for (int t = tid; t < NL; t += nthr) {
     const int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
     const bool inner = lx >= 1 && lx < LX - 1 && ly >= 1 && ly < LY - 1 &&
                        (L::D == 2 || (lz >= 1 && lz < LZ - 1));
-    if (!inner || !(sw[t] & kGhost)) continue;
-    C num = C(0);
-    int den = 0;
-    const int z0 = (L::D == 3) ? -1 : 0, z1 = (L::D == 3) ? 1 : 0;
-    for (int dz = z0; dz <= z1; ++dz)
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int t2 = t + dx + LX * (dy + LY * dz);
-          if (sw[t2] & kZeta) {
-            num += sphi[t2];
-            ++den;
-          }
-        }
-    if (den > 0) sphi[t] = num / C(den);
+    if (inner && (sw[t] & kGhost)) sphi[t] = ghost_mean<L, C>(sphi, sw, t, LX, LX * LY);
   }
   __syncthreads();
 
@@ -232,78 +285,27 @@ __global__ void k_mu(const uint32_t* __restrict__ nodes, C* __restrict__ phi,
   const int t = (threadIdx.x + H) + LX * ((threadIdx.y + H) + LY * (threadIdx.z + HZ));
   const uint32_t w = sw[t];
   const long long n = G.idx(x, y, z);
-  if (w & kZeta) {
-    const C ph = sphi[t];
-    C lap = C(0), ex = C(0), ey = C(0), ez = C(0);
-#pragma unroll
-    for (int i = 1; i < L::Q; ++i) {
-      const int t2 = t + L::cx(i) + LX * (L::cy(i) + LY * L::cz(i));
-      const C wi = C(L::w(i));
-      lap += C(2) * wi * (sphi[t2] - ph);
-      const C e = (sw[t2] & kFluid) ? C(1) : C(0);
-      ex += wi * C(L::cx(i)) * e;
-      ey += wi * C(L::cy(i)) * e;
-      ez += wi * C(L::cz(i)) * e;
-    }
-    const C inv_cs2 = C(3);
-    lap *= inv_cs2;
-    ex *= inv_cs2;
-    ey *= inv_cs2;
-    ez *= inv_cs2;
-    const C av = sqrt(ex * ex + ey * ey + ez * ez);
-    const C m = C(4) * C(P.beta) * ph * (ph - C(1)) * (ph - C(0.5)) - C(P.kappa) * lap -
-                av * C(P.wet) * (ph - ph * ph);
-    mu[n] = m;
-  } else if (w & kGhost) {
-    phi[n] = sphi[t];
-  }
+  if (w & kZeta) mu[n] = mu_at<L, C>(sphi, sw, t, LX, LX * LY, P);
+  else if (w & kGhost) phi[n] = sphi[t];
 }
 
 // ------------------------------------------------------------------ node update
-// MODE 0: collide and write f*, g*, s.  MODE 1: write p and u only (fields).
-// MODE 2: write s only (initial s of the time-derivative term).
+// From the pulled populations, phi, mu and grad phi of one zeta = 1 node: rho,
+// F = mu grad phi + F_b, u and p (Sec. 2.1.2), s = u . grad phi, then
+// MODE 0: collide both sets and store f*, g*, s.  MODE 1: store p and u.
+// MODE 2: store s only.
 template <class L, int S, int MODE>
-__global__ void k_collide(const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
-                          const void* __restrict__ gsrc, void* __restrict__ fdst,
-                          void* __restrict__ gdst, const ComputeT<S>* __restrict__ phi,
-                          const ComputeT<S>* __restrict__ mu, ComputeT<S>* __restrict__ sprev,
-                          ComputeT<S>* __restrict__ out_p, ComputeT<S>* __restrict__ out_u,
-                          Geo G, Phys P) {
+__device__ inline void node_update(const ComputeT<S>* f, double g0, const ComputeT<S>* g,
+                                   ComputeT<S> ph, ComputeT<S> m, ComputeT<S> gx,
+                                   ComputeT<S> gy, ComputeT<S> gz, long long n,
+                                   void* __restrict__ fdst, void* __restrict__ gdst,
+                                   ComputeT<S>* __restrict__ sprev, ComputeT<S>* __restrict__ out_p,
+                                   ComputeT<S>* __restrict__ out_u, const Geo& G, const Phys& P) {
   using C = ComputeT<S>;
-  constexpr int Q = L::Q;
-  int x, y, z;
-  if (!node_coords(G, x, y, z)) return;
-  const long long n = G.idx(x, y, z);
-  const uint32_t word = nodes[n];
-  if (!(word & kZeta)) return;
-  long long nb[Q];
-  neighbours<L>(G, x, y, z, nb);
-
   using FS = Set<S, false>;
   using GS = Set<S, true>;
-  C f[Q], g[Q];
-  f[0] = C(FS::load_rest(fsrc, n));
-  const double g0 = GS::load_rest(gsrc, n);
-  g[0] = C(0);
-#pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    f[i] = pull<L, FS>(fsrc, i, n, nb, word, G.NQ, P.scale_f);
-    g[i] = pull<L, GS>(gsrc, i, n, nb, word, G.NQ, P.scale_g);
-  }
-  const C ph = phi[n];
-  const C m = mu[n];
+  constexpr int Q = L::Q;
   const C inv_cs2 = C(3);
-  C gx = C(0), gy = C(0), gz = C(0);
-#pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const C v = C(L::w(i)) * phi[nb[i]];
-    gx += C(L::cx(i)) * v;
-    gy += C(L::cy(i)) * v;
-    gz += C(L::cz(i)) * v;
-  }
-  gx *= inv_cs2;
-  gy *= inv_cs2;
-  gz *= inv_cs2;
   const C drho = C(P.rho_l - P.rho_g);
   const C rho = C(P.rho_g) + ph * drho;
   const C rx = drho * gx, ry = drho * gy, rz = drho * gz;           // grad rho
@@ -384,6 +386,209 @@ __global__ void k_collide(const uint32_t* __restrict__ nodes, const void* __rest
     else FS::store(fdst, i, n, G.NQ, fp, P.scale_f);
   }
   sprev[n] = s;
+}
+
+// Unfused node update: phi and mu come from the arrays k_phi / k_mu wrote.
+template <class L, int S, int MODE>
+__global__ void k_collide(const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
+                          const void* __restrict__ gsrc, void* __restrict__ fdst,
+                          void* __restrict__ gdst, const ComputeT<S>* __restrict__ phi,
+                          const ComputeT<S>* __restrict__ mu, ComputeT<S>* __restrict__ sprev,
+                          ComputeT<S>* __restrict__ out_p, ComputeT<S>* __restrict__ out_u,
+                          Geo G, Phys P) {
+  using C = ComputeT<S>;
+  constexpr int Q = L::Q;
+  int x, y, z;
+  if (!node_coords(G, x, y, z)) return;
+  const long long n = G.idx(x, y, z);
+  const uint32_t word = nodes[n];
+  if (!(word & kZeta)) return;
+  long long nb[Q];
+  neighbours<L>(G, x, y, z, nb);
+  using FS = Set<S, false>;
+  using GS = Set<S, true>;
+  C f[Q], g[Q];
+  f[0] = C(FS::load_rest(fsrc, n));
+  const double g0 = GS::load_rest(gsrc, n);
+  g[0] = C(0);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    f[i] = pull<L, FS>(fsrc, i, n, nb, word, G.NQ, P.scale_f);
+    g[i] = pull<L, GS>(gsrc, i, n, nb, word, G.NQ, P.scale_g);
+  }
+  C gx, gy, gz;
+  grad_of<L, C>([&](int i) { return phi[nb[i]]; }, gx, gy, gz);
+  node_update<L, S, MODE>(f, g0, g, phi[n], mu[n], gx, gy, gz, n, fdst, gdst, sprev, out_p,
+                          out_u, G, P);
+}
+
+// ------------------------------------------------------------------ fused step
+// One kernel per time step.  A workgroup of (64, BY, BZ) threads owns a tile of
+// 64 x (BY*KY) x (BZ*KZ) nodes (each thread KY*KZ nodes, strided by the block
+// size).  It pulls g for the tile and a one-node halo, forms phi there into LDS
+// (two halo layers when a ghost node lies within one node of the tile, since
+// ghost means need their own neighbours), fills ghosts, and then for every
+// tile node evaluates mu and grad phi from LDS, pulls f and collides.  phi and
+// mu never go to global memory; the pulled g of the tile stay in registers.
+// The arithmetic per node is that of k_phi + k_mu + k_collide, in the same
+// order, so both paths give bit-identical results.
+template <class L, int S, int BY, int BZ, int KY, int KZ>
+__global__ __launch_bounds__(64 * BY * BZ) void k_step(
+    const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
+    const void* __restrict__ gsrc, void* __restrict__ fdst, void* __restrict__ gdst,
+    ComputeT<S>* __restrict__ sprev, Geo G, Phys P) {
+  using C = ComputeT<S>;
+  using GS = Set<S, true>;
+  using FS = Set<S, false>;
+  constexpr int Q = L::Q;
+  constexpr bool D3 = (L::D == 3);
+  constexpr int TX = 64, TY = BY * KY, TZ = D3 ? BZ * KZ : 1;
+  constexpr int LX = TX + 4, LY = TY + 4, LZ = D3 ? TZ + 4 : 1;
+  constexpr int SX = LX, SXY = LX * LY;
+  constexpr int NL = LX * LY * LZ;
+  constexpr int HZ = D3 ? 2 : 0;
+  constexpr int NT = 64 * BY * BZ;
+  constexpr int KN = KY * KZ;
+  __shared__ C sphi[NL];
+  __shared__ uint32_t sw[NL];
+
+  const int lane = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
+  const int tid = lane + 64 * (ty + BY * tz);
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
+  const int P3[3] = {G.PX, G.PY, G.PZ};
+
+  // global node of LDS entry (lx, ly, lz), or -1 outside the padded grid
+  auto gnode = [&](int lx, int ly, int lz, int q[3]) -> long long {
+    q[0] = x0 - 2 + lx;
+    q[1] = y0 - 2 + ly;
+    q[2] = z0 - HZ + lz;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (G.per[d]) {
+        q[d] %= P3[d];
+        if (q[d] < 0) q[d] += P3[d];
+      } else if (q[d] < 0 || q[d] >= P3[d]) {
+        return -1;
+      }
+    }
+    return G.idx(q[0], q[1], q[2]);
+  };
+  auto is_tile = [&](int lx, int ly, int lz) {
+    return lx >= 2 && lx < 2 + TX && ly >= 2 && ly < 2 + TY && (!D3 || (lz >= 2 && lz < 2 + TZ));
+  };
+  // phi of a zeta = 1 node from its pulled g (same order as k_phi)
+  auto phi_of = [&](long long n, uint32_t w, const int q[3]) -> C {
+    long long nb[Q];
+    neighbours<L>(G, q[0], q[1], q[2], nb);
+    C small = C(0);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) small += pull<L, GS>(gsrc, i, n, nb, w, G.NQ, P.scale_g);
+    return C(GS::load_rest(gsrc, n) + (double)small);
+  };
+
+  // 1. node words of the tile and the first halo layer; any ghost there?
+  constexpr int H1X = TX + 2, H1Y = TY + 2, H1Z = D3 ? TZ + 2 : 1;
+  constexpr int N1 = H1X * H1Y * H1Z;
+  bool ghost_near = false;
+  for (int m = tid; m < N1; m += NT) {
+    const int lx = 1 + m % H1X, ly = 1 + (m / H1X) % H1Y, lz = (D3 ? 1 : 0) + m / (H1X * H1Y);
+    int q[3];
+    const long long n = gnode(lx, ly, lz, q);
+    const uint32_t w = n >= 0 ? nodes[n] : 0u;
+    sw[lx + SX * ly + SXY * lz] = w;
+    ghost_near |= (w & kGhost) != 0;
+  }
+  const bool need2 = __syncthreads_or(ghost_near);
+
+  // 2. own tile nodes: pull g, keep it, phi into LDS
+  double g0r[KN];
+  C gr[KN][Q];
+#pragma unroll
+  for (int k = 0; k < KN; ++k) {
+    const int ky = k % KY, kz = k / KY;
+    const int lx = 2 + lane, ly = 2 + ty + BY * ky, lz = HZ + (D3 ? tz + BZ * kz : 0);
+    const int t = lx + SX * ly + SXY * lz;
+    const uint32_t w = sw[t];
+    C ph = C(0);
+    g0r[k] = 0.0;
+    if (w & kZeta) {
+      int q[3];
+      const long long n = gnode(lx, ly, lz, q);
+      long long nb[Q];
+      neighbours<L>(G, q[0], q[1], q[2], nb);
+      C small = C(0);
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        gr[k][i] = pull<L, GS>(gsrc, i, n, nb, w, G.NQ, P.scale_g);
+        small += gr[k][i];
+      }
+      g0r[k] = GS::load_rest(gsrc, n);
+      ph = C(g0r[k] + (double)small);
+    }
+    sphi[t] = ph;
+  }
+  // 3. phi on the first halo layer
+  for (int m = tid; m < N1; m += NT) {
+    const int lx = 1 + m % H1X, ly = 1 + (m / H1X) % H1Y, lz = (D3 ? 1 : 0) + m / (H1X * H1Y);
+    if (is_tile(lx, ly, lz)) continue;
+    const int t = lx + SX * ly + SXY * lz;
+    const uint32_t w = sw[t];
+    C ph = C(0);
+    if (w & kZeta) {
+      int q[3];
+      const long long n = gnode(lx, ly, lz, q);
+      ph = phi_of(n, w, q);
+    }
+    sphi[t] = ph;
+  }
+  // 4. second halo layer, only where ghost means need it
+  if (need2) {
+    for (int m = tid; m < NL; m += NT) {
+      const int lx = m % LX, ly = (m / LX) % LY, lz = m / (LX * LY);
+      const bool ring2 = lx == 0 || lx == LX - 1 || ly == 0 || ly == LY - 1 ||
+                         (D3 && (lz == 0 || lz == LZ - 1));
+      if (!ring2) continue;
+      int q[3];
+      const long long n = gnode(lx, ly, lz, q);
+      const uint32_t w = n >= 0 ? nodes[n] : 0u;
+      sw[m] = w;
+      sphi[m] = (w & kZeta) ? phi_of(n, w, q) : C(0);
+    }
+  }
+  __syncthreads();
+  // 5. ghost means on the tile and the first halo layer
+  if (need2) {
+    for (int m = tid; m < N1; m += NT) {
+      const int lx = 1 + m % H1X, ly = 1 + (m / H1X) % H1Y, lz = (D3 ? 1 : 0) + m / (H1X * H1Y);
+      const int t = lx + SX * ly + SXY * lz;
+      if (sw[t] & kGhost) sphi[t] = ghost_mean<L, C>(sphi, sw, t, SX, SXY);
+    }
+    __syncthreads();
+  }
+  // 6. collide the tile nodes
+#pragma unroll
+  for (int k = 0; k < KN; ++k) {
+    const int ky = k % KY, kz = k / KY;
+    const int x = x0 + lane, y = y0 + ty + BY * ky, z = z0 + (D3 ? tz + BZ * kz : 0);
+    if (x >= G.PX || y >= G.PY || z >= G.PZ) continue;
+    const int lx = 2 + lane, ly = 2 + ty + BY * ky, lz = HZ + (D3 ? tz + BZ * kz : 0);
+    const int t = lx + SX * ly + SXY * lz;
+    const uint32_t w = sw[t];
+    if (!(w & kZeta)) continue;
+    const long long n = G.idx(x, y, z);
+    long long nb[Q];
+    neighbours<L>(G, x, y, z, nb);
+    C f[Q];
+    f[0] = C(FS::load_rest(fsrc, n));
+#pragma unroll
+    for (int i = 1; i < Q; ++i) f[i] = pull<L, FS>(fsrc, i, n, nb, w, G.NQ, P.scale_f);
+    const C m = mu_at<L, C>(sphi, sw, t, SX, SXY, P);
+    C gx, gy, gz;
+    grad_of<L, C>([&](int i) { return sphi[t + L::cx(i) + SX * L::cy(i) + SXY * L::cz(i)]; },
+                  gx, gy, gz);
+    node_update<L, S, 0>(f, g0r[k], gr[k], sphi[t], m, gx, gy, gz, n, fdst, gdst, sprev,
+                         nullptr, nullptr, G, P);
+  }
 }
 
 // ------------------------------------------------------------------ init

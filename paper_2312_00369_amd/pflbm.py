@@ -79,6 +79,8 @@ def _load():
         "pflbm_step": (ct.c_int, [vp, i64]),
         "pflbm_set_graph_chunk": (ct.c_int, [vp, i32]),
         "pflbm_set_tile": (ct.c_int, [vp, i32, i32, i32]),
+        "pflbm_set_step_kernel": (ct.c_int, [vp, i32]),
+        "pflbm_step_variants": (ct.c_int, [i32, vp, i32]),
         "pflbm_fields": (ct.c_int, [vp, vp, vp, vp, vp]),
         "pflbm_node_classes": (ct.c_int, [vp, vp]),
         "pflbm_diagnostics": (ct.c_int, [vp, P(pflbm_diag)]),
@@ -195,6 +197,15 @@ def lattice_table(lattice):
     return dict(c=c, w=w, opp=opp, k=k)
 
 
+def step_variants(lattice):
+    n = lib.pflbm_step_variants(LATTICE[lattice], None, 0)
+    if n < 0:
+        _check(n, "pflbm_step_variants")
+    t = np.zeros((n, 5), dtype=np.int32)
+    lib.pflbm_step_variants(LATTICE[lattice], _ptr(t), n)
+    return [dict(block=(64, int(r[0]), int(r[1])), tile=(int(r[2]), int(r[3]), int(r[4]))) for r in t]
+
+
 def _stream_ptr(stream):
     if stream is None:
         return None
@@ -242,6 +253,10 @@ class Case:
     def set_tile(self, tx, ty, tz=1):
         _check(lib.pflbm_set_tile(self.h, tx, ty, tz), "pflbm_set_tile")
 
+    def set_step_kernel(self, variant):
+        """variant >= 0: fused one-kernel step with that tile shape; -1: three kernels."""
+        _check(lib.pflbm_set_step_kernel(self.h, int(variant)), "pflbm_set_step_kernel")
+
     @property
     def steps(self):
         return int(lib.pflbm_step_count(self.h))
@@ -276,7 +291,7 @@ class Case:
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         _check(lib.pflbm_set_state(self.h, _ptr(buf), ct.c_size_t(buf.size)), "pflbm_set_state")
 
-    def profile(self, nsteps, nkinds=3):
+    def profile(self, nsteps, nkinds=4):
         out = np.zeros(nkinds)
         _check(lib.pflbm_profile(self.h, int(nsteps), _ptr(out), nkinds), "pflbm_profile")
         return out
