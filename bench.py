@@ -31,6 +31,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50000)
     ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--theta", type=float, default=60.0)
+    ap.add_argument("--nx", type=int, default=1024, help="grid (profiling runs only)")
+    ap.add_argument("--ny", type=int, default=512)
     ap.add_argument("--chunk", type=int, default=100, help="steps per captured HIP graph")
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--variant", type=int, default=1, help="fused step tile variant")
@@ -94,7 +96,7 @@ def main():
 
 
 def run(a, torch, P, workloads, stream):
-    c = workloads.config1(theta=a.theta)
+    c = workloads.config1(theta=a.theta, nx=a.nx, ny=a.ny)
     case = P.Case.from_case(c, "f32", stream=stream)
     case.set_graph_chunk(a.chunk)
     case.set_step_kernel(a.variant)
@@ -124,8 +126,8 @@ def run(a, torch, P, workloads, stream):
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "D2Q9 FP32 1024x512 flat-wall droplet R=80, theta=60, W=5, "
-                               "rho 10/1, tau 0.8, M 0.1, sigma 1e-3",
+        "config": {"workload": f"D2Q9 FP32 {a.nx}x{a.ny} flat-wall droplet R={80 * a.nx / 1024:g}, "
+                               f"theta={a.theta:g}, W=5, rho 10/1, tau 0.8, M 0.1, sigma 1e-3",
                    "nodes": nodes, "graph_chunk": a.chunk},
         "hbm_roofline_pct_step": round(100 * mlups * 1e6 * alg / (HBM_PEAK_GBS * 1e9), 2),
         "roofline": roof,

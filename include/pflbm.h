@@ -143,10 +143,16 @@ int pflbm_set_graph_chunk(pflbm_handle h, int32_t steps);
 int pflbm_set_tile(pflbm_handle h, int32_t tx, int32_t ty, int32_t tz);
 
 /* Kernel path of pflbm_step: variant >= 0 selects a tile shape of the fused
- * one-kernel step (the default is 2), -1 the three-kernel path (phi sum, mu
+ * one-kernel step (default 1 for D2Q9, 3 for D3Q19), -1 the three-kernel path (phi sum, mu
  * stencil, collide-stream).  Every path gives bit-identical results.  Drops any
  * captured graph. */
 int pflbm_set_step_kernel(pflbm_handle h, int32_t variant);
+
+/* Scheduling options of the fused step (results do not depend on them):
+ * xcd_order != 0 hands each of the 8 XCDs a contiguous run of tiles;
+ * nontemporal != 0 writes f* and g* with streaming stores (both default off).
+ * Drops any captured graph. */
+int pflbm_set_step_options(pflbm_handle h, int32_t xcd_order, int32_t nontemporal);
 
 /* Number of fused-step variants for a lattice; if tiles is non-NULL, fills up
  * to capacity records of 5 ints: threads (by, bz) of a (64, by, bz) workgroup
@@ -186,19 +192,35 @@ void pflbm_destroy(pflbm_handle h);
 
 /* ---------------------------------------------------------------- groups (batched) */
 
-/* A group advances many cases of the same lattice and storage together: one
- * persistent launch per kernel walks a device tile -> case table.  Members are
- * non-owning references; destroying a member removes it. */
+/* A group advances many cases of one lattice and storage together: each step
+ * is one launch of a persistent grid that walks a device (case, tile) table,
+ * so small and uneven cases fill the GPU together; full chunks of steps replay
+ * a captured HIP graph.  The per-node arithmetic is that of the single-case
+ * fused step with the same tile variant, so every member's result is
+ * bit-identical to running it alone.  Members are non-owning references:
+ * joining a group moves a case's work onto the group's stream (its own stream
+ * is restored when it leaves); destroying a member removes it; pflbm_step on a
+ * member is refused (PFLBM_ESTATE) while fields, diagnostics and state calls
+ * on it stay valid.  hip_stream is borrowed (NULL: the group makes its own). */
 int pflbm_group_create(void* hip_stream, pflbm_group* out);
+/* Add a case (same lattice and storage as the other members, else EINVAL). */
 int pflbm_group_add(pflbm_group g, pflbm_handle h);
+/* Remove a member (ESTATE if h is not a member). */
 int pflbm_group_remove(pflbm_group g, pflbm_handle h);
+/* Number of members, or -1 for a NULL group. */
 int pflbm_group_size(pflbm_group g);
-/* Advance every member nsteps (async). */
+/* Advance every member nsteps >= 0 steps.  (async) */
 int pflbm_group_step(pflbm_group g, int64_t nsteps);
-/* Reductions for every member (one batched launch); d[k] for member k in
- * insertion order, flags[k] = bit 0 steady, bit 1 nonfinite.  (sync) */
+/* Reductions for every member; d[k] and flags[k] (bit 0 steady, bit 1
+ * nonfinite) for member k in insertion order; capacity >= group size.  (sync) */
 int pflbm_group_poll(pflbm_group g, pflbm_diag* d, int32_t* flags, int32_t capacity);
-int pflbm_group_set_tile(pflbm_group g, int32_t tx, int32_t ty, int32_t tz, int32_t blocks_per_cu);
+/* Launch shape of the batched kernel: fused-step tile variant (-1 = library
+ * default) and workgroups per CU of the persistent grid (0 = as many as fit).
+ * Results do not depend on either. */
+int pflbm_group_set_tile(pflbm_group g, int32_t variant, int32_t blocks_per_cu);
+/* Steps per captured HIP graph (0 = direct launches; odd values round up). */
+int pflbm_group_set_graph_chunk(pflbm_group g, int32_t steps);
+/* Destroy the group; members stay valid and return to their own streams. */
 void pflbm_group_destroy(pflbm_group g);
 
 /* ---------------------------------------------------------------- errors */

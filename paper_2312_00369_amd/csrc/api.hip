@@ -89,6 +89,8 @@ int validate_and_derive(const pflbm_params* p, Derived* d) {
   ph.nu_l = p->nu_l;
   ph.nu_g = p->nu_g;
   ph.visc_var = var ? 1 : 0;
+  ph.xcd_order = 0;
+  ph.nt_store = 0;
   for (int a = 0; a < 3; ++a) ph.Fb[a] = (a < D) ? p->body_force[a] : 0.0;
   // FP16 codec scales (powers of two): stored magnitudes of about 2^13 for the
   // largest populations expected from the parameters.
@@ -305,6 +307,7 @@ int create_common(const pflbm_params* prm, const uint8_t* mask, const double* ph
   h->prm = *prm;
   h->dv = dv;
   h->tile = default_tile(dv.D);
+  h->variant = dv.D == 2 ? 1 : 3;
   h->lay = make_layout(dv, prm->storage, h->tile);
   auto fail = [&](int code) {
     pflbm_destroy(h);
@@ -794,6 +797,15 @@ int pflbm_set_step_kernel(pflbm_handle h, int32_t variant) {
     return set_error(PFLBM_EINVAL, "step kernel variant %d outside [-1, %d)", variant, kStepVariants);
   drop_graph(h);
   h->variant = variant;
+  return PFLBM_OK;
+}
+
+int pflbm_set_step_options(pflbm_handle h, int32_t xcd_order, int32_t nontemporal) {
+  clear_error();
+  if (int rc = check_handle(h)) return rc;
+  drop_graph(h);
+  h->dv.phys.xcd_order = xcd_order ? 1 : 0;
+  h->dv.phys.nt_store = nontemporal ? 1 : 0;
   return PFLBM_OK;
 }
 

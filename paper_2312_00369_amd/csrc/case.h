@@ -77,7 +77,7 @@ struct pflbm_case_s {
   bool snap_valid = false;
   dim3 tile;
   int graph_chunk = 64;
-  int variant = 2;                // fused step kernel variant; -1 = three-kernel path
+  int variant = 1;                // fused step kernel variant; -1 = three-kernel path
   hipGraphExec_t gexec = nullptr;
   int gexec_steps = 0;
   pflbm_group_s* group = nullptr;
@@ -94,4 +94,16 @@ int run_step_eager(pflbm_case_s* h);
 int run_step_fused(pflbm_case_s* h);
 constexpr int kStepVariants = 5;
 int step_variant_tile(int D, int v, int tile[5]);
+
+// One launch of the batched step kernel.
+struct GroupLaunch {
+  int lattice, storage, variant, grid;
+  hipStream_t stream;
+  const TileEntry* table;
+  const int* ntiles;
+  const CaseDesc* cases;
+};
+// Launches one batched step with the given parity, or (occupancy_blocks != 0)
+// only reports how many workgroups of the kernel fit on one CU.
+int run_step_group(const GroupLaunch& gl, int parity, int* occupancy_blocks);
 }  // namespace pflbm

@@ -57,7 +57,8 @@ struct Engine {
   static int step_v(pflbm_case_s* h) {
     const Geo& G = h->dv.geo;
     constexpr int TY = BY * KY, TZ = (L::D == 3) ? BZ * KZ : 1;
-    const dim3 grid((G.PX + 63) / 64, (G.PY + TY - 1) / TY, (G.PZ + TZ - 1) / TZ);
+    const unsigned nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY, nbz = (G.PZ + TZ - 1) / TZ;
+    const dim3 grid(nbx * nby * nbz, 1, 1);
     const dim3 block(64, BY, (L::D == 3) ? BZ : 1);
     const int c = h->cur;
     hipLaunchKernelGGL((k_step<L, S, BY, (L::D == 3) ? BZ : 1, KY, (L::D == 3) ? KZ : 1>), grid,
@@ -115,6 +116,50 @@ struct Engine {
   }
 };
 
+template <class L, int S>
+struct GroupEngine {
+  template <int BY, int BZ, int KY, int KZ>
+  static int launch(const GroupLaunch& gl, int parity) {
+    constexpr int bz = (L::D == 3) ? BZ : 1, kz = (L::D == 3) ? KZ : 1;
+    hipLaunchKernelGGL((k_step_group<L, S, BY, bz, KY, kz>), dim3(gl.grid), dim3(64, BY, bz), 0,
+                       gl.stream, gl.table, gl.ntiles, gl.cases, parity);
+    PFLBM_HIP(hipGetLastError());
+    return PFLBM_OK;
+  }
+  template <int BY, int BZ, int KY, int KZ>
+  static int occupancy(int* blocks) {
+    constexpr int bz = (L::D == 3) ? BZ : 1, kz = (L::D == 3) ? KZ : 1;
+    PFLBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        blocks, reinterpret_cast<const void*>(&k_step_group<L, S, BY, bz, KY, kz>), 64 * BY * bz, 0));
+    return PFLBM_OK;
+  }
+  static int go(const GroupLaunch& gl, int parity, int* occ) {
+#define PFLBM_VARIANT(V, BY, BZ, KY, KZ) \
+  case V: return occ ? occupancy<BY, BZ, KY, KZ>(occ) : launch<BY, BZ, KY, KZ>(gl, parity);
+    if (L::D == 2) {
+      switch (gl.variant) {
+        PFLBM_VARIANT(0, 4, 1, 1, 1)
+        PFLBM_VARIANT(1, 4, 1, 2, 1)
+        PFLBM_VARIANT(2, 4, 1, 4, 1)
+        PFLBM_VARIANT(3, 8, 1, 2, 1)
+        PFLBM_VARIANT(4, 2, 1, 4, 1)
+        default: break;
+      }
+    } else {
+      switch (gl.variant) {
+        PFLBM_VARIANT(0, 2, 2, 1, 1)
+        PFLBM_VARIANT(1, 2, 2, 2, 1)
+        PFLBM_VARIANT(2, 2, 2, 2, 2)
+        PFLBM_VARIANT(3, 4, 4, 1, 1)
+        PFLBM_VARIANT(4, 4, 2, 1, 2)
+        default: break;
+      }
+    }
+#undef PFLBM_VARIANT
+    return set_error(PFLBM_EINVAL, "unknown step variant %d", gl.variant);
+  }
+};
+
 template <template <class, int> class Fn, class... A>
 int dispatch(pflbm_case_s* h, A... a) {
   const int lat = h->prm.lattice, st = h->prm.storage;
@@ -150,6 +195,19 @@ int run_collide(pflbm_case_s* h, int mode, void* out_p, void* out_u) {
 }
 int run_init_g(pflbm_case_s* h) { return dispatch<DoInit>(h); }
 int run_step_fused(pflbm_case_s* h) { return dispatch<DoStep>(h); }
+
+int run_step_group(const GroupLaunch& gl, int parity, int* occupancy_blocks) {
+  if (gl.lattice == PFLBM_D2Q9) {
+    if (gl.storage == PFLBM_FP64) return GroupEngine<D2Q9, kF64>::go(gl, parity, occupancy_blocks);
+    if (gl.storage == PFLBM_FP32) return GroupEngine<D2Q9, kF32>::go(gl, parity, occupancy_blocks);
+    if (gl.storage == PFLBM_FP16_DEV) return GroupEngine<D2Q9, kF16Dev>::go(gl, parity, occupancy_blocks);
+  } else {
+    if (gl.storage == PFLBM_FP64) return GroupEngine<D3Q19, kF64>::go(gl, parity, occupancy_blocks);
+    if (gl.storage == PFLBM_FP32) return GroupEngine<D3Q19, kF32>::go(gl, parity, occupancy_blocks);
+    if (gl.storage == PFLBM_FP16_DEV) return GroupEngine<D3Q19, kF16Dev>::go(gl, parity, occupancy_blocks);
+  }
+  return set_error(PFLBM_EUNSUPPORTED, "unsupported lattice/storage %d/%d", gl.lattice, gl.storage);
+}
 
 // Tile of each fused-step variant: threads (64, by, bz), nodes (64, ty, tz).
 int step_variant_tile(int D, int v, int tile[5]) {

@@ -1,5 +1,16 @@
-// Groups of cases stepped together (placeholder: members step one after another).
+// Groups: many cases of one lattice and storage advanced by one persistent
+// launch per step that walks a device (case, tile) table.
+//
+// Buffer parity.  Each member's descriptor records which of its two buffers
+// held the current state when the table was last built (cur0); launch k after
+// the build runs with parity k & 1.  Host-side step counters and buffer indices
+// of the members are brought up to date after every group call.  Graph chunks
+// are captured with an even step count starting at parity 0, so a replay leaves
+// the parity where it found it; membership changes rewrite the device table
+// and descriptors in place (same addresses) between replays.
 #include <algorithm>
+#include <cstring>
+#include <new>
 #include <vector>
 
 #include "case.h"
@@ -8,24 +19,200 @@ using namespace pflbm;
 
 struct pflbm_group_s {
   hipStream_t stream = nullptr;
+  bool own_stream = false;
   std::vector<pflbm_case_s*> members;
+  std::vector<hipStream_t> home_stream;   // each member's own stream
+  std::vector<int64_t> step0;
+  std::vector<int> cur0;
+  int lattice = -1, storage = -1, D = 0;
+  int variant = -1;        // -1: library default for the lattice
+  int blocks_per_cu = 0;   // 0: as many as fit
+  int cus = 0;
+  // device table (capacity-managed; addresses change only on growth)
+  TileEntry* d_table = nullptr;
+  int* d_ntiles = nullptr;
+  CaseDesc* d_cases = nullptr;
+  size_t cap_tiles = 0, cap_cases = 0;
+  int ntiles = 0;
+  bool dirty = true;
+  int64_t since_build = 0;
+  int graph_chunk = 64;
+  hipGraphExec_t gexec = nullptr;
+  int gexec_steps = 0;
+  int grid = 0;
 };
+
+namespace {
+
+int default_variant(int D) { return D == 2 ? 1 : 3; }
+
+void drop_graph(pflbm_group_s* g) {
+  if (g->gexec) {
+    (void)hipGraphExecDestroy(g->gexec);
+    g->gexec = nullptr;
+    g->gexec_steps = 0;
+  }
+}
+
+// Bring every member's step count and buffer index up to date.
+void sync_members(pflbm_group_s* g) {
+  for (size_t k = 0; k < g->members.size(); ++k) {
+    pflbm_case_s* h = g->members[k];
+    h->step = g->step0[k] + g->since_build;
+    h->cur = g->cur0[k] ^ (int)(g->since_build & 1);
+  }
+}
+
+GroupLaunch launch_of(const pflbm_group_s* g) {
+  GroupLaunch gl;
+  gl.lattice = g->lattice;
+  gl.storage = g->storage;
+  gl.variant = g->variant;
+  gl.grid = g->grid;
+  gl.stream = g->stream;
+  gl.table = g->d_table;
+  gl.ntiles = g->d_ntiles;
+  gl.cases = g->d_cases;
+  return gl;
+}
+
+int tiles_of(const pflbm_case_s* h, int variant) {
+  int t[5];
+  step_variant_tile(h->dv.D, variant, t);
+  const Geo& G = h->dv.geo;
+  return ((G.PX + t[2] - 1) / t[2]) * ((G.PY + t[3] - 1) / t[3]) * ((G.PZ + t[4] - 1) / t[4]);
+}
+
+int rebuild(pflbm_group_s* g) {
+  sync_members(g);
+  g->since_build = 0;
+  if (g->variant < 0 && g->D) g->variant = default_variant(g->D);
+  std::vector<TileEntry> table;
+  std::vector<CaseDesc> cases(g->members.size());
+  for (size_t k = 0; k < g->members.size(); ++k) {
+    pflbm_case_s* h = g->members[k];
+    g->step0[k] = h->step;
+    g->cur0[k] = h->cur;
+    CaseDesc& cd = cases[k];
+    std::memset(&cd, 0, sizeof cd);
+    cd.G = h->dv.geo;
+    cd.P = h->dv.phys;
+    cd.nodes = h->nodes;
+    cd.f[0] = h->f[0];
+    cd.f[1] = h->f[1];
+    cd.g[0] = h->g[0];
+    cd.g[1] = h->g[1];
+    cd.s = h->s;
+    cd.cur0 = h->cur;
+    const int nt = tiles_of(h, g->variant);
+    for (int t = 0; t < nt; ++t) table.push_back(TileEntry{(int)k, t});
+  }
+  bool moved = false;
+  if (table.size() > g->cap_tiles || !g->d_table) {
+    const size_t cap = std::max<size_t>(1024, table.size() * 3 / 2);
+    if (g->d_table) (void)hipFree(g->d_table);
+    g->d_table = nullptr;
+    if (hipMalloc(&g->d_table, cap * sizeof(TileEntry)) != hipSuccess) {
+      (void)hipGetLastError();
+      g->cap_tiles = 0;
+      return set_error(PFLBM_ENOMEM, "group table allocation failed");
+    }
+    g->cap_tiles = cap;
+    moved = true;
+  }
+  if (cases.size() > g->cap_cases || !g->d_cases) {
+    const size_t cap = std::max<size_t>(64, cases.size() * 3 / 2);
+    if (g->d_cases) (void)hipFree(g->d_cases);
+    g->d_cases = nullptr;
+    if (hipMalloc(&g->d_cases, cap * sizeof(CaseDesc)) != hipSuccess) {
+      (void)hipGetLastError();
+      g->cap_cases = 0;
+      return set_error(PFLBM_ENOMEM, "group descriptor allocation failed");
+    }
+    g->cap_cases = cap;
+    moved = true;
+  }
+  if (!g->d_ntiles) {
+    if (hipMalloc(&g->d_ntiles, sizeof(int)) != hipSuccess) {
+      (void)hipGetLastError();
+      return set_error(PFLBM_ENOMEM, "group counter allocation failed");
+    }
+    moved = true;
+  }
+  if (moved) drop_graph(g);
+  g->ntiles = (int)table.size();
+  if (!table.empty())
+    PFLBM_HIP(hipMemcpyAsync(g->d_table, table.data(), table.size() * sizeof(TileEntry),
+                             hipMemcpyHostToDevice, g->stream));
+  if (!cases.empty())
+    PFLBM_HIP(hipMemcpyAsync(g->d_cases, cases.data(), cases.size() * sizeof(CaseDesc),
+                             hipMemcpyHostToDevice, g->stream));
+  PFLBM_HIP(hipMemcpyAsync(g->d_ntiles, &g->ntiles, sizeof(int), hipMemcpyHostToDevice, g->stream));
+  // the host vectors go out of scope: wait for the copies
+  PFLBM_HIP(hipStreamSynchronize(g->stream));
+  // persistent grid: as many workgroups as fit on the device (capped by the table)
+  if (!g->cus) PFLBM_HIP(hipDeviceGetAttribute(&g->cus, hipDeviceAttributeMultiprocessorCount, 0));
+  int occ = 0;
+  if (int rc = run_step_group(launch_of(g), 0, &occ)) return rc;
+  occ = std::max(1, occ);
+  if (g->blocks_per_cu > 0) occ = std::min(occ, g->blocks_per_cu);
+  const int grid = std::max(1, g->cus * occ);
+  if (grid != g->grid) drop_graph(g);
+  g->grid = grid;
+  g->dirty = false;
+  return PFLBM_OK;
+}
+
+int launch_eager(pflbm_group_s* g) {
+  int rc = run_step_group(launch_of(g), (int)(g->since_build & 1), nullptr);
+  if (rc) return rc;
+  g->since_build += 1;
+  return PFLBM_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
 void pflbm_group_forget(pflbm_handle h) {
   if (!h || !h->group) return;
-  auto& m = h->group->members;
-  m.erase(std::remove(m.begin(), m.end(), h), m.end());
+  pflbm_group_s* g = h->group;
+  (void)hipStreamSynchronize(g->stream);
+  sync_members(g);
+  auto it = std::find(g->members.begin(), g->members.end(), h);
+  if (it != g->members.end()) {
+    const size_t k = (size_t)(it - g->members.begin());
+    h->stream = g->home_stream[k];
+    g->members.erase(it);
+    g->home_stream.erase(g->home_stream.begin() + k);
+    g->step0.erase(g->step0.begin() + k);
+    g->cur0.erase(g->cur0.begin() + k);
+    // re-base the survivors so that their descriptors can be rebuilt
+    for (size_t j = 0; j < g->members.size(); ++j) {
+      g->step0[j] = g->members[j]->step;
+      g->cur0[j] = g->members[j]->cur;
+    }
+    g->since_build = 0;
+  }
   h->group = nullptr;
+  g->dirty = true;
 }
 
 int pflbm_group_create(void* stream, pflbm_group* out) {
   clear_error();
   if (!out) return set_error(PFLBM_EINVAL, "out is NULL");
+  *out = nullptr;
   auto* g = new (std::nothrow) pflbm_group_s();
   if (!g) return set_error(PFLBM_ENOMEM, "host allocation failed");
-  g->stream = static_cast<hipStream_t>(stream);
+  if (stream) {
+    g->stream = static_cast<hipStream_t>(stream);
+  } else {
+    if (hipStreamCreate(&g->stream) != hipSuccess) {
+      delete g;
+      return set_error(PFLBM_EDEVICE, "hipStreamCreate failed");
+    }
+    g->own_stream = true;
+  }
   *out = g;
   return PFLBM_OK;
 }
@@ -34,8 +221,33 @@ int pflbm_group_add(pflbm_group g, pflbm_handle h) {
   clear_error();
   if (!g || !h) return set_error(PFLBM_EINVAL, "NULL group or handle");
   if (h->group) return set_error(PFLBM_ESTATE, "case already belongs to a group");
+  if (!g->members.empty() && (h->prm.lattice != g->lattice || h->prm.storage != g->storage))
+    return set_error(PFLBM_EINVAL, "group members must share lattice and storage");
+  PFLBM_HIP(hipStreamSynchronize(h->stream));
+  PFLBM_HIP(hipStreamSynchronize(g->stream));
+  sync_members(g);
+  for (size_t j = 0; j < g->members.size(); ++j) {
+    g->step0[j] = g->members[j]->step;
+    g->cur0[j] = g->members[j]->cur;
+  }
+  g->since_build = 0;
+  if (g->members.empty()) {
+    g->lattice = h->prm.lattice;
+    g->storage = h->prm.storage;
+    g->D = h->dv.D;
+  }
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+    h->gexec_steps = 0;
+  }
   g->members.push_back(h);
+  g->home_stream.push_back(h->stream);
+  g->step0.push_back(h->step);
+  g->cur0.push_back(h->cur);
+  h->stream = g->stream;
   h->group = g;
+  g->dirty = true;
   return PFLBM_OK;
 }
 
@@ -52,9 +264,45 @@ int pflbm_group_size(pflbm_group g) { return g ? (int)g->members.size() : -1; }
 int pflbm_group_step(pflbm_group g, int64_t nsteps) {
   clear_error();
   if (!g) return set_error(PFLBM_EINVAL, "group is NULL");
-  for (auto* h : g->members)
-    for (int64_t k = 0; k < nsteps; ++k)
-      if (int rc = run_step_eager(h)) return rc;
+  if (nsteps < 0) return set_error(PFLBM_EINVAL, "nsteps must be >= 0");
+  if (g->members.empty() || nsteps == 0) return PFLBM_OK;
+  int rc;
+  if (g->dirty && (rc = rebuild(g))) return rc;
+  const int K = g->graph_chunk;
+  if (K > 0 && nsteps >= K) {
+    if (g->since_build & 1) {
+      if ((rc = launch_eager(g))) return rc;
+      --nsteps;
+    }
+    if (!g->gexec || g->gexec_steps != K) {
+      drop_graph(g);
+      hipGraph_t graph = nullptr;
+      PFLBM_HIP(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < K; ++k) {
+        if ((rc = run_step_group(launch_of(g), k & 1, nullptr))) {
+          (void)hipStreamEndCapture(g->stream, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          return rc;
+        }
+      }
+      PFLBM_HIP(hipStreamEndCapture(g->stream, &graph));
+      hipError_t e = hipGraphInstantiateWithFlags(&g->gexec, graph, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        g->gexec = nullptr;
+        return set_error(PFLBM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      }
+      g->gexec_steps = K;
+    }
+    while (nsteps >= K && !(g->since_build & 1)) {
+      PFLBM_HIP(hipGraphLaunch(g->gexec, g->stream));
+      g->since_build += K;
+      nsteps -= K;
+    }
+  }
+  for (int64_t k = 0; k < nsteps; ++k)
+    if ((rc = launch_eager(g))) return rc;
+  sync_members(g);
   return PFLBM_OK;
 }
 
@@ -64,6 +312,7 @@ int pflbm_group_poll(pflbm_group g, pflbm_diag* d, int32_t* flags, int32_t capac
   clear_error();
   if (!g) return set_error(PFLBM_EINVAL, "group is NULL");
   if (capacity < (int)g->members.size()) return set_error(PFLBM_EINVAL, "capacity too small");
+  sync_members(g);
   for (size_t k = 0; k < g->members.size(); ++k) {
     pflbm_diag tmp;
     if (int rc = pflbm_diagnostics(g->members[k], &tmp)) return rc;
@@ -73,15 +322,43 @@ int pflbm_group_poll(pflbm_group g, pflbm_diag* d, int32_t* flags, int32_t capac
   return PFLBM_OK;
 }
 
-int pflbm_group_set_tile(pflbm_group g, int32_t, int32_t, int32_t, int32_t) {
+int pflbm_group_set_tile(pflbm_group g, int32_t variant, int32_t blocks_per_cu) {
   clear_error();
   if (!g) return set_error(PFLBM_EINVAL, "group is NULL");
+  if (variant < -1 || variant >= kStepVariants || blocks_per_cu < 0)
+    return set_error(PFLBM_EINVAL, "bad group launch shape (%d, %d)", variant, blocks_per_cu);
+  (void)hipStreamSynchronize(g->stream);
+  sync_members(g);
+  drop_graph(g);
+  g->variant = variant;
+  g->blocks_per_cu = blocks_per_cu;
+  g->dirty = true;
+  return PFLBM_OK;
+}
+
+int pflbm_group_set_graph_chunk(pflbm_group g, int32_t steps) {
+  clear_error();
+  if (!g) return set_error(PFLBM_EINVAL, "group is NULL");
+  if (steps < 0) return set_error(PFLBM_EINVAL, "chunk must be >= 0");
+  if (steps & 1) steps += 1;
+  if (steps != g->graph_chunk) drop_graph(g);
+  g->graph_chunk = steps;
   return PFLBM_OK;
 }
 
 void pflbm_group_destroy(pflbm_group g) {
   if (!g) return;
-  for (auto* h : g->members) h->group = nullptr;
+  (void)hipStreamSynchronize(g->stream);
+  sync_members(g);
+  for (size_t k = 0; k < g->members.size(); ++k) {
+    g->members[k]->stream = g->home_stream[k];
+    g->members[k]->group = nullptr;
+  }
+  drop_graph(g);
+  if (g->d_table) (void)hipFree(g->d_table);
+  if (g->d_cases) (void)hipFree(g->d_cases);
+  if (g->d_ntiles) (void)hipFree(g->d_ntiles);
+  if (g->own_stream) (void)hipStreamDestroy(g->stream);
   delete g;
 }
 

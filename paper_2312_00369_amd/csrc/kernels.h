@@ -44,7 +44,16 @@ struct Phys {
   double Fb[3];
   int visc_var;
   float scale_f, scale_g;  // FP16 codec: stored = value * scale (power of two)
+  int xcd_order;           // fused step: hand each XCD a contiguous run of tiles
+  int nt_store;            // fused step: non-temporal stores of f*, g*
 };
+
+// Streaming store that does not keep the line in the caches (or a plain store).
+template <class T>
+__device__ inline void st(T* p, T v, int nt) {
+  if (nt) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
 
 // ------------------------------------------------------------------ storage codec
 // One distribution set (f or g) in one buffer: the rest population (i = 0) in
@@ -74,7 +83,9 @@ struct Set {
     return (size_t)NQ * sizeof(R) + (size_t)(Q - 1) * (size_t)NQ * sizeof(M);
   }
   __device__ static R load_rest(const void* b, long long n) { return static_cast<const R*>(b)[n]; }
-  __device__ static void store_rest(void* b, long long n, R v) { static_cast<R*>(b)[n] = v; }
+  __device__ static void store_rest(void* b, long long n, R v, int nt = 0) {
+    st(static_cast<R*>(b) + n, v, nt);
+  }
   __device__ static const M* moving(const void* b, long long NQ) {
     return reinterpret_cast<const M*>(static_cast<const unsigned char*>(b) + NQ * sizeof(R));
   }
@@ -87,9 +98,17 @@ struct Set {
     if constexpr (kHalf) return __half2float(v) * (1.0f / scale);
     else return C(v);
   }
-  __device__ static void store(void* b, int i, long long n, long long NQ, C v, float scale) {
-    if constexpr (kHalf) moving(b, NQ)[(i - 1) * NQ + n] = __float2half_rn(v * scale);
-    else moving(b, NQ)[(i - 1) * NQ + n] = M(v);
+  __device__ static void store(void* b, int i, long long n, long long NQ, C v, float scale,
+                               int nt = 0) {
+    M* p = moving(b, NQ) + (i - 1) * NQ + n;
+    if constexpr (kHalf) {
+      const __half h = __float2half_rn(v * scale);
+      if (nt) __builtin_nontemporal_store(*reinterpret_cast<const unsigned short*>(&h),
+                                          reinterpret_cast<unsigned short*>(p));
+      else *p = h;
+    } else {
+      st(p, M(v), nt);
+    }
   }
 };
 
@@ -293,14 +312,15 @@ __global__ void k_mu(const uint32_t* __restrict__ nodes, C* __restrict__ phi,
 // From the pulled populations, phi, mu and grad phi of one zeta = 1 node: rho,
 // F = mu grad phi + F_b, u and p (Sec. 2.1.2), s = u . grad phi, then
 // MODE 0: collide both sets and store f*, g*, s.  MODE 1: store p and u.
-// MODE 2: store s only.
+// MODE 2: store s only.  MODE 3: as MODE 0 with s_prev passed in.
 template <class L, int S, int MODE>
 __device__ inline void node_update(const ComputeT<S>* f, double g0, const ComputeT<S>* g,
                                    ComputeT<S> ph, ComputeT<S> m, ComputeT<S> gx,
                                    ComputeT<S> gy, ComputeT<S> gz, long long n,
                                    void* __restrict__ fdst, void* __restrict__ gdst,
                                    ComputeT<S>* __restrict__ sprev, ComputeT<S>* __restrict__ out_p,
-                                   ComputeT<S>* __restrict__ out_u, const Geo& G, const Phys& P) {
+                                   ComputeT<S>* __restrict__ out_u, const Geo& G, const Phys& P,
+                                   int nt = 0, ComputeT<S> sp_pre = ComputeT<S>(0)) {
   using C = ComputeT<S>;
   using FS = Set<S, false>;
   using GS = Set<S, true>;
@@ -344,7 +364,7 @@ __device__ inline void node_update(const ComputeT<S>* f, double g0, const Comput
 
   // phase-field collision: Eq. (BGK) with the time derivative of G_i as a
   // backward difference of s, G_i + dG_i/2 = w_i k_i (1.5 s - 0.5 s_prev)
-  const C sp = sprev[n];
+  const C sp = (MODE == 3) ? sp_pre : sprev[n];
   const C srcf = C(1.5) * s - C(0.5) * sp;
   const C itg = C(P.inv_tau_g);
   const C am = C(P.alpha) * m;
@@ -356,13 +376,13 @@ __device__ inline void node_update(const ComputeT<S>* f, double g0, const Comput
   {
     const C d0 = (C(1) - w0) * am - gsmall;
     const C inc = w0 * C(L::k(0)) * srcf - d0 * itg;
-    GS::store_rest(gdst, n, g0 + (double)inc);
+    GS::store_rest(gdst, n, g0 + (double)inc, nt);
   }
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     const C wi = C(L::w(i));
     const C gp = g[i] - (g[i] - wi * am) * itg + wi * C(L::k(i)) * srcf;
-    GS::store(gdst, i, n, G.NQ, gp, P.scale_g);
+    GS::store(gdst, i, n, G.NQ, gp, P.scale_g, nt);
   }
   // hydrodynamic collision
   C tau = C(P.tau);
@@ -382,8 +402,8 @@ __device__ inline void node_update(const ComputeT<S>* f, double g0, const Comput
     // Eq. (GGi): u.grad rho + c.F/cs2 + [(c.u)(c.grad rho) - cs2 u.grad rho]/cs2
     const C Fi = ffac * wi * (ugr + cF * inv_cs2 + (cu * cr - ugr * C(kCs2)) * inv_cs2);
     const C fp = f[i] - (f[i] - feq) * itau + Fi;
-    if (i == 0) FS::store_rest(fdst, n, typename FS::R(fp));
-    else FS::store(fdst, i, n, G.NQ, fp, P.scale_f);
+    if (i == 0) FS::store_rest(fdst, n, typename FS::R(fp), nt);
+    else FS::store(fdst, i, n, G.NQ, fp, P.scale_f, nt);
   }
   sprev[n] = s;
 }
@@ -433,10 +453,23 @@ __global__ void k_collide(const uint32_t* __restrict__ nodes, const void* __rest
 // The arithmetic per node is that of k_phi + k_mu + k_collide, in the same
 // order, so both paths give bit-identical results.
 template <class L, int S, int BY, int BZ, int KY, int KZ>
-__global__ __launch_bounds__(64 * BY * BZ) void k_step(
-    const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
-    const void* __restrict__ gsrc, void* __restrict__ fdst, void* __restrict__ gdst,
-    ComputeT<S>* __restrict__ sprev, Geo G, Phys P) {
+struct StepTile {
+  using C = ComputeT<S>;
+  static constexpr bool D3 = (L::D == 3);
+  static constexpr int TX = 64, TY = BY * KY, TZ = D3 ? BZ * KZ : 1;
+  static constexpr int LX = TX + 4, LY = TY + 4, LZ = D3 ? TZ + 4 : 1;
+  static constexpr int NL = LX * LY * LZ;
+};
+
+// Advance the tile with origin (x0, y0, z0) of one case by one step; sphi and
+// sw are LDS arrays of StepTile::NL entries.  Every thread of the workgroup
+// must call it (it synchronises the workgroup).
+template <class L, int S, int BY, int BZ, int KY, int KZ>
+__device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restrict__ nodes,
+                                 const void* __restrict__ fsrc, const void* __restrict__ gsrc,
+                                 void* __restrict__ fdst, void* __restrict__ gdst,
+                                 ComputeT<S>* __restrict__ sprev, const Geo& G, const Phys& P,
+                                 ComputeT<S>* sphi, uint32_t* sw) {
   using C = ComputeT<S>;
   using GS = Set<S, true>;
   using FS = Set<S, false>;
@@ -449,12 +482,8 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_step(
   constexpr int HZ = D3 ? 2 : 0;
   constexpr int NT = 64 * BY * BZ;
   constexpr int KN = KY * KZ;
-  __shared__ C sphi[NL];
-  __shared__ uint32_t sw[NL];
-
   const int lane = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
   const int tid = lane + 64 * (ty + BY * tz);
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
   const int P3[3] = {G.PX, G.PY, G.PZ};
 
   // global node of LDS entry (lx, ly, lz), or -1 outside the padded grid
@@ -587,7 +616,76 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_step(
     grad_of<L, C>([&](int i) { return sphi[t + L::cx(i) + SX * L::cy(i) + SXY * L::cz(i)]; },
                   gx, gy, gz);
     node_update<L, S, 0>(f, g0r[k], gr[k], sphi[t], m, gx, gy, gz, n, fdst, gdst, sprev,
-                         nullptr, nullptr, G, P);
+                         nullptr, nullptr, G, P, P.nt_store);
+  }
+}
+
+
+// One launch per time step: workgroup b updates tile b (x-fastest order).
+// Workgroups are dealt to the 8 XCDs round-robin; with xcd_order each XCD
+// takes a contiguous run of tiles instead.
+template <class L, int S, int BY, int BZ, int KY, int KZ>
+__global__ __launch_bounds__(64 * BY * BZ) void k_step(
+    const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
+    const void* __restrict__ gsrc, void* __restrict__ fdst, void* __restrict__ gdst,
+    ComputeT<S>* __restrict__ sprev, Geo G, Phys P) {
+  using T = StepTile<L, S, BY, BZ, KY, KZ>;
+  __shared__ typename T::C sphi[T::NL];
+  __shared__ uint32_t sw[T::NL];
+  const int nbx = (G.PX + T::TX - 1) / T::TX, nby = (G.PY + T::TY - 1) / T::TY;
+  const int nb = gridDim.x;
+  int b = blockIdx.x;
+  if (P.xcd_order) {
+    const int per = nb / 8, rem = nb % 8, xcd = b % 8, k = b / 8;
+    b = (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+  }
+  step_tile<L, S, BY, BZ, KY, KZ>((b % nbx) * T::TX, ((b / nbx) % nby) * T::TY,
+                                  (b / (nbx * nby)) * T::TZ, nodes, fsrc, gsrc, fdst, gdst, sprev,
+                                  G, P, sphi, sw);
+}
+
+// ------------------------------------------------------------------ batched step
+// Many cases of one lattice and storage advance together.  A persistent grid
+// walks a device table of (case, tile) entries; each case has a descriptor
+// with its geometry, physics and buffers.  The table and descriptors live in
+// device memory and may change between launches (cases joining or leaving)
+// without touching the launch arguments, so captured graphs stay valid.
+struct CaseDesc {
+  Geo G;
+  Phys P;
+  const uint32_t* nodes;
+  void* f[2];
+  void* g[2];
+  void* s;
+  int cur0;          // buffer holding the current state when parity == 0
+  int pad_;
+};
+
+struct TileEntry {
+  int case_id;
+  int tile;          // tile index within the case, x-fastest
+};
+
+template <class L, int S, int BY, int BZ, int KY, int KZ>
+__global__ __launch_bounds__(64 * BY * BZ) void k_step_group(
+    const TileEntry* __restrict__ table, const int* __restrict__ ntiles,
+    const CaseDesc* __restrict__ cases, int parity) {
+  using T = StepTile<L, S, BY, BZ, KY, KZ>;
+  __shared__ typename T::C sphi[T::NL];
+  __shared__ uint32_t sw[T::NL];
+  const int n = *ntiles;
+  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+    const TileEntry te = table[e];
+    const CaseDesc& cd = cases[te.case_id];
+    const Geo G = cd.G;
+    const int c = cd.cur0 ^ parity;
+    const int nbx = (G.PX + T::TX - 1) / T::TX, nby = (G.PY + T::TY - 1) / T::TY;
+    const int b = te.tile;
+    step_tile<L, S, BY, BZ, KY, KZ>((b % nbx) * T::TX, ((b / nbx) % nby) * T::TY,
+                                    (b / (nbx * nby)) * T::TZ, cd.nodes, cd.f[c], cd.g[c],
+                                    cd.f[1 - c], cd.g[1 - c], static_cast<ComputeT<S>*>(cd.s), G,
+                                    cd.P, sphi, sw);
+    __syncthreads();   // the next tile reuses the LDS arrays
   }
 }
 

@@ -81,6 +81,7 @@ def _load():
         "pflbm_set_tile": (ct.c_int, [vp, i32, i32, i32]),
         "pflbm_set_step_kernel": (ct.c_int, [vp, i32]),
         "pflbm_step_variants": (ct.c_int, [i32, vp, i32]),
+        "pflbm_set_step_options": (ct.c_int, [vp, i32, i32]),
         "pflbm_fields": (ct.c_int, [vp, vp, vp, vp, vp]),
         "pflbm_node_classes": (ct.c_int, [vp, vp]),
         "pflbm_diagnostics": (ct.c_int, [vp, P(pflbm_diag)]),
@@ -96,7 +97,8 @@ def _load():
         "pflbm_group_size": (ct.c_int, [vp]),
         "pflbm_group_step": (ct.c_int, [vp, i64]),
         "pflbm_group_poll": (ct.c_int, [vp, vp, vp, i32]),
-        "pflbm_group_set_tile": (ct.c_int, [vp, i32, i32, i32, i32]),
+        "pflbm_group_set_tile": (ct.c_int, [vp, i32, i32]),
+        "pflbm_group_set_graph_chunk": (ct.c_int, [vp, i32]),
         "pflbm_group_destroy": (None, [vp]),
         "pflbm_strerror": (ct.c_char_p, [ct.c_int]),
         "pflbm_last_error": (ct.c_char_p, []),
@@ -253,6 +255,10 @@ class Case:
     def set_tile(self, tx, ty, tz=1):
         _check(lib.pflbm_set_tile(self.h, tx, ty, tz), "pflbm_set_tile")
 
+    def set_step_options(self, xcd_order=True, nontemporal=False):
+        _check(lib.pflbm_set_step_options(self.h, int(bool(xcd_order)), int(bool(nontemporal))),
+               "pflbm_set_step_options")
+
     def set_step_kernel(self, variant):
         """variant >= 0: fused one-kernel step with that tile shape; -1: three kernels."""
         _check(lib.pflbm_set_step_kernel(self.h, int(variant)), "pflbm_set_step_kernel")
@@ -338,8 +344,12 @@ class Group:
     def step(self, n=1):
         _check(lib.pflbm_group_step(self.g, int(n)), "pflbm_group_step")
 
-    def set_tile(self, tx, ty, tz=1, blocks_per_cu=0):
-        _check(lib.pflbm_group_set_tile(self.g, tx, ty, tz, blocks_per_cu), "pflbm_group_set_tile")
+    def set_tile(self, variant=-1, blocks_per_cu=0):
+        _check(lib.pflbm_group_set_tile(self.g, int(variant), int(blocks_per_cu)),
+               "pflbm_group_set_tile")
+
+    def set_graph_chunk(self, k):
+        _check(lib.pflbm_group_set_graph_chunk(self.g, int(k)), "pflbm_group_set_graph_chunk")
 
     def poll(self):
         n = len(self.members)

@@ -1,0 +1,133 @@
+"""GPU tests of the batched runtime: a persistent launch over a (case, tile)
+table gives every member the same bits as running it alone."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases2d():
+    rng = np.random.default_rng(11)
+    out = []
+    for k in range(6):
+        nx = int(rng.integers(4, 14)) * 16
+        c = workloads.cylinder_case(nx, nx // 2, float(rng.uniform(0.2, 0.4)),
+                                    float(rng.uniform(30, 150)))
+        out.append(c)
+    out.append(workloads.flat_droplet_case(37, 19, 5.0, 70.0))      # ragged, tiny
+    return out
+
+
+def _alone(P, c, storage, steps, variant):
+    a = P.Case.from_case(c, storage)
+    a.set_step_kernel(variant)
+    a.step(steps)
+    return a.fields()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16dev", "f64"])
+def test_group_alone_vs_mix_bitwise_2d(P, storage):
+    cs = _cases2d()
+    g = P.Group()
+    g.set_tile(1)
+    members = [P.Case.from_case(c, storage) for c in cs]
+    for m in members:
+        g.add(m)
+    g.step(37)
+    for c, m in zip(cs, members):
+        ref = _alone(P, c, storage, 37, 1)
+        f = m.fields()
+        assert m.steps == 37
+        for k in ("phi", "p", "u", "mu"):
+            assert np.array_equal(f[k], ref[k]), k
+
+
+def test_group_alone_vs_mix_bitwise_3d(P):
+    cs = [workloads.inclined_droplet_case_3d(n=n, radius=0.25 * n, theta=th, width=4.0)
+          for n, th in ((18, 60.0), (26, 120.0), (22, 45.0))]
+    g = P.Group()
+    members = [P.Case.from_case(c, "f32") for c in cs]
+    for m in members:
+        g.add(m)
+    g.step(21)
+    for c, m in zip(cs, members):
+        ref = _alone(P, c, "f32", 21, 3)
+        assert np.array_equal(m.fields()["phi"], ref["phi"])
+
+
+def test_group_membership_changes(P):
+    """Cases join and leave between chunks (with graph replay) and keep their
+    own trajectories: a case stepped 10 alone, 40 in a group, removed, 13 alone
+    equals 63 alone."""
+    cs = _cases2d()[:4]
+    a = P.Case.from_case(cs[0], "f32")
+    a.step(10)
+    g = P.Group()
+    g.set_graph_chunk(8)
+    others = [P.Case.from_case(c, "f32") for c in cs[1:]]
+    g.add(a)
+    g.add(others[0])
+    g.step(17)
+    g.add(others[1])           # joins mid-run
+    g.step(23)
+    g.remove(others[0])
+    g.add(others[2])
+    g.remove(a)
+    a.step(13)
+    g.step(5)
+    assert a.steps == 63 and others[1].steps == 28 and others[0].steps == 40
+    ref = _alone(P, cs[0], "f32", 63, 1)
+    assert np.array_equal(a.fields()["phi"], ref["phi"])
+    ref1 = _alone(P, cs[2], "f32", 28, 1)
+    assert np.array_equal(others[1].fields()["phi"], ref1["phi"])
+    ref0 = _alone(P, cs[1], "f32", 40, 1)
+    assert np.array_equal(others[0].fields()["phi"], ref0["phi"])
+
+
+def test_group_graph_equals_eager(P):
+    cs = _cases2d()[:3]
+    outs = []
+    for chunk in (0, 16):
+        g = P.Group()
+        g.set_graph_chunk(chunk)
+        ms = [P.Case.from_case(c, "f32") for c in cs]
+        for m in ms:
+            g.add(m)
+        g.step(50)
+        outs.append([m.fields()["phi"] for m in ms])
+        g.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_group_poll_flags(P):
+    """Steady flag for a uniform (fixed-point) case; nonfinite flag for a case
+    the host drives unstable with an oversized body force."""
+    c = workloads.flat_droplet_case(64, 32, 8.0, 60.0)
+    calm = dict(c, phi0=np.ones_like(c["phi0"]), theta_deg=90.0)
+    g = P.Group()
+    a = P.Case.from_case(calm, "f32", steady_tol=1e-7)
+    b = P.Case.from_case(c, "f32", body_force=(2.0, -2.0, 0.0))
+    g.add(a)
+    g.add(b)
+    g.step(10)
+    d, flags = g.poll()
+    g.step(200)
+    d, flags = g.poll()
+    assert flags[0] & 1 and not flags[0] & 2
+    assert flags[1] & 2
+    assert d[1]["nonfinite"]
+
+
+def test_group_rejects_mixed_storage(P):
+    c = workloads.flat_droplet_case(32, 16, 5.0, 60.0)
+    g = P.Group()
+    g.add(P.Case.from_case(c, "f32"))
+    with pytest.raises(P.PflbmError):
+        g.add(P.Case.from_case(c, "f64"))
+    a = P.Case.from_case(c, "f32")
+    g.add(a)
+    with pytest.raises(P.PflbmError):
+        a.step(1)                      # members are stepped through the group
