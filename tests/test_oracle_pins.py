@@ -330,9 +330,37 @@ def test_tanh_profile_is_equilibrium():
     assert np.abs(o.fields()["phi"][:, 0] - prof).max() < 1e-2
 
 
+def _cap_case(nx, ny, r0, theta_wall, theta_init, sigma, W):
+    """Droplet of the equal-area cap of a radius-r0 semicircle at theta_init,
+    resting on the wall plane y = -0.5 (Sec. 3.1 equilibrium shape phi_r)."""
+    c = workloads.flat_droplet_case(nx, ny, r0, theta_wall, W, sigma)
+    R = odiag.cap_radius_2d(r0, theta_init)
+    yc = -0.5 - R * math.cos(math.radians(theta_init))
+    c["phi0"] = workloads.droplet((nx, ny), (nx / 2, yc), R, W)
+    return c
+
+
+def test_equilibrium_cap_is_kept_and_approached():
+    """Table 1 / Sec. 3.1: the equilibrium angle equals the prescribed theta.  The
+    paper's analytic cap for theta = 120 deg stays at 120 deg, while a 90 deg
+    semicircle under theta = 120 deg climbs towards it; the angle is measured
+    against the bounce-back wall plane."""
+    W, sigma = 4.0, 1e-2
+    keep = oracle_for(_cap_case(96, 48, 15.0, 120.0, 120.0, sigma, W), mobility=0.2)
+    move = oracle_for(_cap_case(96, 48, 15.0, 120.0, 90.0, sigma, W), mobility=0.2)
+    wall = dict(kind="plane", point=(0.0, -0.5), normal=(0.0, 1.0))
+    keep.step(2500)
+    move.step(2500)
+    zk = keep.domain(keep.zeta)
+    th_keep = odiag.contact_angle(keep.fields()["phi"], zk, wall, W)[0]
+    th_move = odiag.contact_angle(move.fields()["phi"], zk, wall, W)[0]
+    assert abs(th_keep - 120.0) < 1.5, th_keep
+    assert th_move > 95.0, th_move          # moved about a third of the way in 2500 steps
+
+
 def test_contact_angle_ninety_keeps_semicircle():
     """cos(theta) = 0 switches the wall term off (Eq. chemical_potencial2): the
-    semicircle on a flat wall stays at 90 degrees."""
+    semicircle centred on the wall plane stays at 90 degrees."""
     c = workloads.flat_droplet_case(96, 48, 15.0, 90.0)
     o = oracle_for(c)
     o.step(1500)

@@ -10,6 +10,14 @@ flat wall (Sec. 3.1), on an inclined wall built as a staircase (Sec. 3.2) and on
 a cylinder or sphere (Sec. 3.3); the initial field is the tanh droplet of Eq.
 (initialphi).  Each case also records the wall it rests on (a plane, or a circle
 or sphere), which the contact-angle estimators need.
+
+Where the wall is.  A node-centred mask puts the geometric surface half a node
+outside its outermost solid nodes.  Those outermost solid nodes become boundary
+nodes that carry populations, so the bounce-back wall and the mirror plane of
+the zero-gradient ghost condition lie one node further in: half-way between the
+boundary nodes and the ghost nodes.  The recorded wall is that plane (the
+geometric surface moved one node into the solid), and droplets are centred on
+it.
 """
 import math
 
@@ -80,13 +88,13 @@ def _case(lattice, shape, periodic, mask, phi0, theta, sigma, width, wall, **kw)
 
 def flat_droplet_case(nx=128, ny=64, radius=20.0, theta=60.0, width=4.0,
                       sigma=1e-3, lattice="D2Q9"):
-    """Droplet centred on the wetting plane of a flat bottom wall; walls at the
-    bottom and top rows; periodic in x.  The wetting plane of a one-row solid is
-    y = 0.5, half-way between the solid row and the first fluid row."""
+    """Droplet centred on a flat bottom wall; one solid row at the bottom and at
+    the top; periodic in x.  The solid row y = 0 holds the boundary nodes, so the
+    wall plane is y = -0.5."""
     shape = (nx, ny)
     mask = flat_walls(shape)
-    phi0 = droplet(shape, (nx / 2, 0.5), radius, width)
-    wall = dict(kind="plane", point=(0.0, 0.5), normal=(0.0, 1.0))
+    phi0 = droplet(shape, (nx / 2, -0.5), radius, width)
+    wall = dict(kind="plane", point=(0.0, -0.5), normal=(0.0, 1.0))
     return _case(lattice, shape, (True, False), mask, phi0, theta, sigma, width, wall)
 
 
@@ -107,13 +115,16 @@ def config1(theta=60.0, nx=1024, ny=512):
 def inclined_droplet_case_3d(n=256, radius=40.0, theta=45.0, angle=30.0, width=5.0,
                              sigma=1e-3, storage="f32"):
     """n^3 D3Q19, non-periodic; staircase solid below a plane tilted by `angle`
-    through (n/2, n/4) in the x-z plane; droplet centred on that plane."""
+    through (n/2, n/4) in the x-z plane; droplet centred on the wall plane (that
+    plane moved one node into the solid)."""
     shape = (n, n, n)
     xp, zp = n / 2.0, n / 4.0
     mask = inclined_plane(shape, (xp, zp), angle)
-    phi0 = droplet(shape, (xp, n / 2.0, zp), radius, width)
     a = math.radians(angle)
-    wall = dict(kind="plane", point=(xp, n / 2.0, zp), normal=(-math.sin(a), 0.0, math.cos(a)))
+    nrm = (-math.sin(a), 0.0, math.cos(a))
+    c0 = (xp - nrm[0], n / 2.0, zp - nrm[2])
+    phi0 = droplet(shape, c0, radius, width)
+    wall = dict(kind="plane", point=c0, normal=nrm)
     return _case("D3Q19", shape, (False, False, False), mask, phi0, theta, sigma, width,
                  wall, storage=storage, steps=20000,
                  name=f"inclined-{n}^3-{storage}")
@@ -125,13 +136,14 @@ def config2(storage="f32", n=256):
 
 def cylinder_case(nx, ny, rc_frac, theta, width=4.0, sigma=1e-3, drop_frac=0.3):
     """Solid cylinder of radius rc_frac*ny near the bottom, droplet of radius
-    drop_frac*R_c centred on its top; walls at the bottom and top rows."""
+    drop_frac*R_c centred on its top; walls at the bottom and top rows.  The
+    wall circle has radius R_c - 1."""
     rc = rc_frac * ny
     center = (nx / 2.0, rc + 0.05 * ny)
     mask = np.maximum(ball((nx, ny), center, rc), flat_walls((nx, ny)))
     rd = drop_frac * rc
-    phi0 = droplet((nx, ny), (center[0], center[1] + rc), rd, width)
-    wall = dict(kind="circle", center=center, radius=rc)
+    phi0 = droplet((nx, ny), (center[0], center[1] + rc - 1.0), rd, width)
+    wall = dict(kind="circle", center=center, radius=rc - 1.0)
     return _case("D2Q9", (nx, ny), (True, False), mask, phi0, theta, sigma, width, wall,
                  storage="f32", name=f"cyl-{nx}x{ny}")
 
@@ -167,9 +179,11 @@ def serving_request(rng, idx):
             a = 30.0
             xp, yp = nx / 2.0, ny / 4.0
             mask = np.maximum(inclined_plane((nx, ny), (xp, yp), a), flat_walls((nx, ny)))
-            phi0 = droplet((nx, ny), (xp, yp), R, 5.0)
             r = math.radians(a)
-            wall = dict(kind="plane", point=(xp, yp), normal=(-math.sin(r), math.cos(r)))
+            nrm = (-math.sin(r), math.cos(r))
+            c0 = (xp - nrm[0], yp - nrm[1])
+            phi0 = droplet((nx, ny), c0, R, 5.0)
+            wall = dict(kind="plane", point=c0, normal=nrm)
             c = _case("D2Q9", (nx, ny), (True, False), mask, phi0, th, 1e-3, 5.0, wall)
         else:
             c = cylinder_case(nx, ny, 0.3, th, width=5.0, drop_frac=R / (0.3 * ny))
@@ -179,8 +193,8 @@ def serving_request(rng, idx):
         shape = (n, n, n)
         if geom == "flat":
             mask = flat_walls(shape, bottom=True, top=False)
-            phi0 = droplet(shape, (n / 2, n / 2, 0.5), R, 5.0)
-            wall = dict(kind="plane", point=(0.0, 0.0, 0.5), normal=(0.0, 0.0, 1.0))
+            phi0 = droplet(shape, (n / 2, n / 2, -0.5), R, 5.0)
+            wall = dict(kind="plane", point=(0.0, 0.0, -0.5), normal=(0.0, 0.0, 1.0))
         elif geom == "inclined":
             c = inclined_droplet_case_3d(n=n, radius=R, theta=th)
             mask, phi0, wall = c["mask"], c["phi0"], c["wall"]
@@ -188,8 +202,8 @@ def serving_request(rng, idx):
             rs = 0.3 * n
             center = (n / 2, n / 2, rs + 0.05 * n)
             mask = ball(shape, center, rs)
-            phi0 = droplet(shape, (n / 2, n / 2, center[2] + rs), R, 5.0)
-            wall = dict(kind="circle", center=center, radius=rs)
+            phi0 = droplet(shape, (n / 2, n / 2, center[2] + rs - 1.0), R, 5.0)
+            wall = dict(kind="circle", center=center, radius=rs - 1.0)
         c = _case("D3Q19", shape, (False, False, False), mask, phi0, th, 1e-3, 5.0, wall)
     c.update(storage="f32", geometry=geom, name=f"req-{idx:03d}-{geom}-{c['lattice']}")
     return c
