@@ -15,6 +15,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -41,6 +43,13 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-tol", type=float, default=1e-4)
+    ap.add_argument("--serve-chunk", type=int, default=500)
+    ap.add_argument("--serve-max-steps", type=int, default=20000)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--batch-steps", type=int, default=1000)
     return ap.parse_args()
 
@@ -125,6 +134,56 @@ def batched(a, torch, P, workloads, stream):
             "nonfinite_cases": int(sum(1 for f in flags if f & 2))}
 
 
+def served(a, torch, P, workloads):
+    """Continuous batching over Poisson arrivals of mixed 2D / 3D cases (the
+    serving workload at reduced sizes), then the same requests one at a time on
+    the plain solver for the same step counts."""
+    from paper_2312_00369_amd.serve import GpuExecutor, Server
+    reqs = workloads.config4(seed=4, n_requests=a.serve_requests, rate=a.serve_rate,
+                             nx_range=(128, 384), n3_range=(32, 64))
+    for r in reqs:
+        r["steady_tol"] = a.serve_tol
+    ex = GpuExecutor()
+    srv = Server(ex, budget_bytes=a.serve_budget_gb * 2 ** 30, max_slots=64,
+                 chunk_steps=a.serve_chunk, max_steps=a.serve_max_steps)
+    rec, summ = srv.run(reqs)
+    # one case at a time: same requests, same step counts, plain solver + graphs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    node_steps = 0
+    for r in rec:
+        if "steps" not in r:
+            continue
+        c = reqs[r["index"]]
+        h = P.Case.from_case(c, "f32", steady_tol=a.serve_tol)
+        h.set_graph_chunk(100)
+        done = 0
+        while done < r["steps"]:
+            k = min(a.serve_chunk, r["steps"] - done)
+            h.step(k)
+            h.diagnostics()            # the same poll cadence as the server
+            done += k
+        node_steps += done * int(np.prod(c["shape"]))
+        h.close()
+    torch.cuda.synchronize()
+    t_alone = time.perf_counter() - t0
+    nodes_served = sum(int(r.get("steps", 0)) * int(np.prod(reqs[r["index"]]["shape"]))
+                       for r in rec)
+    out = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+    out.update({"workload": f"{len(reqs)} Poisson arrivals at {a.serve_rate}/s: 2D 128x64..384x192, "
+                            f"3D 32^3..64^3, flat/inclined/curved, theta U[30,150], FP32; steady = "
+                            f"max|dphi| <= {a.serve_tol} over {a.serve_chunk} steps, cap "
+                            f"{a.serve_max_steps}",
+                "one_at_a_time_wall_s": round(t_alone, 3),
+                "one_at_a_time_MLUPS": round(node_steps / t_alone / 1e6, 1),
+                "served_MLUPS_busy": round(nodes_served / summ["gpu_busy_s"] / 1e6, 1)
+                if summ["gpu_busy_s"] else None,
+                "throughput_vs_one_at_a_time": round(t_alone / summ["wall_s"], 2),
+                "status": {s: sum(1 for r in rec if r.get("status") == s)
+                           for s in ("steady", "step cap", "nonfinite")}})
+    return out
+
+
 def cpu_baseline(c, budget_s=15.0):
     """The FP64 oracle, unmodified, on a bounded sample of the same workload."""
     import numpy as np
@@ -160,6 +219,9 @@ def main():
     stream = torch.cuda.Stream()          # default priority; the library launches on it
     with torch.cuda.stream(stream):
         line = run(a, torch, P, workloads, stream)
+    if not a.no_serve:
+        with torch.cuda.stream(stream):
+            line["served"] = served(a, torch, P, workloads)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(workloads.config1(theta=a.theta))
     print(json.dumps(line), flush=True)

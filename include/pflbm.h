@@ -137,14 +137,17 @@ int pflbm_step(pflbm_handle h, int64_t nsteps);
 /* Steps per captured HIP graph (0 = launch kernels directly).  Default 64. */
 int pflbm_set_graph_chunk(pflbm_handle h, int32_t steps);
 
-/* Launch shape of the stencil and collide kernels: threads along x, y, z of one
- * workgroup (tx a multiple of 64, tx*ty*tz <= 1024).  Results do not depend on it.
- * Drops any captured graph. */
+/* Launch shape of the node-parallel kernels (phi sum, mu stencil, collide-stream
+ * of the three-kernel path, the phi pass of the split step, and the
+ * reductions): threads along x, y, z of one workgroup (tx a multiple of 64,
+ * tx*ty*tz <= 1024).  Results do not depend on it.  Drops any captured graph. */
 int pflbm_set_tile(pflbm_handle h, int32_t tx, int32_t ty, int32_t tz);
 
-/* Kernel path of pflbm_step: variant >= 0 selects a tile shape of the fused
- * one-kernel step (default 1 for D2Q9, 3 for D3Q19), -1 the three-kernel path (phi sum, mu
- * stencil, collide-stream).  Every path gives bit-identical results.  Drops any
+/* Kernel path of pflbm_step.  variant 0-4: the fused one-kernel step with one
+ * of five tile shapes; 5-7: the split step (a phi pass, then one kernel for
+ * ghosts, mu and collide-stream) with one of three tile shapes; -1: the
+ * three-kernel path (phi sum, mu stencil, collide-stream).  Defaults: 1 for
+ * D2Q9, 6 for D3Q19.  Every path gives bit-identical results.  Drops any
  * captured graph. */
 int pflbm_set_step_kernel(pflbm_handle h, int32_t variant);
 
@@ -154,9 +157,10 @@ int pflbm_set_step_kernel(pflbm_handle h, int32_t variant);
  * Drops any captured graph. */
 int pflbm_set_step_options(pflbm_handle h, int32_t xcd_order, int32_t nontemporal);
 
-/* Number of fused-step variants for a lattice; if tiles is non-NULL, fills up
- * to capacity records of 5 ints: threads (by, bz) of a (64, by, bz) workgroup
- * and the tile (tx, ty, tz) it updates.  (no device work) */
+/* Number of step variants for a lattice (see pflbm_set_step_kernel); if tiles
+ * is non-NULL, fills up to capacity records of 5 ints: threads (by, bz) of a
+ * (64, by, bz) workgroup and the tile (tx, ty, tz) it updates.  (no device
+ * work) */
 int pflbm_step_variants(int32_t lattice, int32_t* tiles, int32_t capacity);
 
 /* Current fields as FP64 host arrays of nx*ny*nz (u: D arrays, component-major).

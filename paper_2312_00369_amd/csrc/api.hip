@@ -73,6 +73,8 @@ int validate_and_derive(const pflbm_params* p, Derived* d) {
   G.PZ = P[2];
   G.SX = (int)round_up((size_t)P[0], 32);
   d->N = (long long)G.SX * G.PY * G.PZ;
+  if (d->N >= (1LL << 31))
+    return set_error(PFLBM_EUNSUPPORTED, "padded grid of %lld nodes exceeds 2^31", d->N);
   G.NQ = (long long)round_up((size_t)d->N, 256);
 
   Phys& ph = d->phys;
@@ -307,7 +309,7 @@ int create_common(const pflbm_params* prm, const uint8_t* mask, const double* ph
   h->prm = *prm;
   h->dv = dv;
   h->tile = default_tile(dv.D);
-  h->variant = dv.D == 2 ? 1 : 3;
+  h->variant = dv.D == 2 ? 1 : 6;
   h->lay = make_layout(dv, prm->storage, h->tile);
   auto fail = [&](int code) {
     pflbm_destroy(h);
@@ -576,8 +578,10 @@ int pflbm_node_classes(pflbm_handle h, uint8_t* classes) {
   return PFLBM_OK;
 }
 
+}  // extern "C"
+
 // Kasa circle / sphere fit from the moment record, then the contact angle.
-static void finish_diag(const pflbm_case_s* h, const double* r, pflbm_diag* d) {
+void pflbm::finish_diag(const pflbm_case_s* h, const double* r, pflbm_diag* d) {
   std::memset(d, 0, sizeof *d);
   d->step = h->step;
   d->mass = r[kRecMass];
@@ -646,6 +650,8 @@ static void finish_diag(const pflbm_case_s* h, const double* r, pflbm_diag* d) {
   cost = std::fmin(1.0, std::fmax(-1.0, cost));
   d->theta_deg = std::acos(cost) * 180.0 / M_PI;
 }
+
+extern "C" {
 
 int pflbm_diagnostics(pflbm_handle h, pflbm_diag* d) {
   clear_error();
@@ -727,6 +733,7 @@ int pflbm_set_state(pflbm_handle h, const void* host, size_t bytes) {
   PFLBM_HIP(hipStreamSynchronize(h->stream));
   h->step = hd.step;
   h->snap_valid = false;
+  group_member_changed(h);
   return PFLBM_OK;
 }
 

@@ -92,7 +92,7 @@ int run_init_g(pflbm_case_s* h);
 int run_reduce(pflbm_case_s* h, int update_snap, double* host_rec);
 int run_step_eager(pflbm_case_s* h);
 int run_step_fused(pflbm_case_s* h);
-constexpr int kStepVariants = 5;
+constexpr int kStepVariants = 8;
 int step_variant_tile(int D, int v, int tile[5]);
 
 // One launch of the batched step kernel.
@@ -106,4 +106,11 @@ struct GroupLaunch {
 // Launches one batched step with the given parity, or (occupancy_blocks != 0)
 // only reports how many workgroups of the kernel fit on one CU.
 int run_step_group(const GroupLaunch& gl, int parity, int* occupancy_blocks);
+void group_member_changed(pflbm_case_s* h);
+// Batched phi + diagnostics reductions over a group's table: out[k * kRecN ..]
+// receives member k's record.
+int run_group_diag(const GroupLaunch& gl, int parity, int ty, int tz, double* partial,
+                   double* out, int ncases, int update_snap);
+// Contact-angle fit and flags from a reduction record.
+void finish_diag(const pflbm_case_s* h, const double* rec, pflbm_diag* d);
 }  // namespace pflbm

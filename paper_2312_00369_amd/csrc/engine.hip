@@ -68,9 +68,27 @@ struct Engine {
     return PFLBM_OK;
   }
 
+  template <int BY, int BZ>
+  static int split_v(pflbm_case_s* h) {
+    const Geo& G = h->dv.geo;
+    int rc = phi(h);
+    if (rc) return rc;
+    constexpr int bz = (L::D == 3) ? BZ : 1;
+    const unsigned nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY, nbz = (G.PZ + bz - 1) / bz;
+    const int c = h->cur;
+    hipLaunchKernelGGL((k_stepB<L, S, BY, bz>), dim3(nbx * nby * nbz), dim3(64, BY, bz), 0,
+                       h->stream, h->nodes, h->f[c], h->g[c], h->f[1 - c], h->g[1 - c],
+                       static_cast<C*>(h->s), static_cast<const C*>(h->phi), G, h->dv.phys);
+    PFLBM_HIP(hipGetLastError());
+    return PFLBM_OK;
+  }
+
   static int step_fused(pflbm_case_s* h) {
     if (L::D == 2) {
       switch (h->variant) {
+        case 5: return split_v<4, 1>(h);
+        case 6: return split_v<8, 1>(h);
+        case 7: return split_v<16, 1>(h);
         case 0: return step_v<4, 1, 1, 1>(h);
         case 1: return step_v<4, 1, 2, 1>(h);
         case 2: return step_v<4, 1, 4, 1>(h);
@@ -85,6 +103,9 @@ struct Engine {
         case 2: return step_v<2, 2, 2, 2>(h);
         case 3: return step_v<4, 4, 1, 1>(h);
         case 4: return step_v<4, 2, 1, 2>(h);
+        case 5: return split_v<4, 4>(h);
+        case 6: return split_v<2, 2>(h);
+        case 7: return split_v<4, 2>(h);
         default: break;
       }
     }
@@ -133,7 +154,27 @@ struct GroupEngine {
         blocks, reinterpret_cast<const void*>(&k_step_group<L, S, BY, bz, KY, kz>), 64 * BY * bz, 0));
     return PFLBM_OK;
   }
+  template <int BY, int BZ>
+  static int launch_split(const GroupLaunch& gl, int parity) {
+    constexpr int bz = (L::D == 3) ? BZ : 1;
+    hipLaunchKernelGGL((k_phi_group<L, S, BY, bz>), dim3(gl.grid), dim3(64, BY, bz), 0, gl.stream,
+                       gl.table, gl.ntiles, gl.cases, parity);
+    PFLBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_stepB_group<L, S, BY, bz>), dim3(gl.grid), dim3(64, BY, bz), 0,
+                       gl.stream, gl.table, gl.ntiles, gl.cases, parity);
+    PFLBM_HIP(hipGetLastError());
+    return PFLBM_OK;
+  }
+  template <int BY, int BZ>
+  static int occupancy_split(int* blocks) {
+    constexpr int bz = (L::D == 3) ? BZ : 1;
+    PFLBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        blocks, reinterpret_cast<const void*>(&k_stepB_group<L, S, BY, bz>), 64 * BY * bz, 0));
+    return PFLBM_OK;
+  }
   static int go(const GroupLaunch& gl, int parity, int* occ) {
+#define PFLBM_SPLIT(V, BY, BZ) \
+  case V: return occ ? occupancy_split<BY, BZ>(occ) : launch_split<BY, BZ>(gl, parity);
 #define PFLBM_VARIANT(V, BY, BZ, KY, KZ) \
   case V: return occ ? occupancy<BY, BZ, KY, KZ>(occ) : launch<BY, BZ, KY, KZ>(gl, parity);
     if (L::D == 2) {
@@ -143,6 +184,9 @@ struct GroupEngine {
         PFLBM_VARIANT(2, 4, 1, 4, 1)
         PFLBM_VARIANT(3, 8, 1, 2, 1)
         PFLBM_VARIANT(4, 2, 1, 4, 1)
+        PFLBM_SPLIT(5, 4, 1)
+        PFLBM_SPLIT(6, 8, 1)
+        PFLBM_SPLIT(7, 16, 1)
         default: break;
       }
     } else {
@@ -152,10 +196,14 @@ struct GroupEngine {
         PFLBM_VARIANT(2, 2, 2, 2, 2)
         PFLBM_VARIANT(3, 4, 4, 1, 1)
         PFLBM_VARIANT(4, 4, 2, 1, 2)
+        PFLBM_SPLIT(5, 4, 4)
+        PFLBM_SPLIT(6, 2, 2)
+        PFLBM_SPLIT(7, 4, 2)
         default: break;
       }
     }
 #undef PFLBM_VARIANT
+#undef PFLBM_SPLIT
     return set_error(PFLBM_EINVAL, "unknown step variant %d", gl.variant);
   }
 };
@@ -196,6 +244,41 @@ int run_collide(pflbm_case_s* h, int mode, void* out_p, void* out_u) {
 int run_init_g(pflbm_case_s* h) { return dispatch<DoInit>(h); }
 int run_step_fused(pflbm_case_s* h) { return dispatch<DoStep>(h); }
 
+namespace {
+template <class L, int S>
+int group_diag_t(const GroupLaunch& gl, int parity, int ty, int tz, double* partial, double* out,
+                 int ncases, int update_snap) {
+  using C = ComputeT<S>;
+  hipLaunchKernelGGL((k_phi_group_all<L, S>), dim3(gl.grid), dim3(256), 0, gl.stream, gl.table,
+                     gl.ntiles, gl.cases, parity, ty, tz);
+  PFLBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_reduce_group<L, C>), dim3(gl.grid), dim3(256), 0, gl.stream, gl.table,
+                     gl.ntiles, gl.cases, partial, ty, tz, update_snap);
+  PFLBM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_final_group<kRecN>, dim3(ncases), dim3(256), 0, gl.stream, partial,
+                     gl.cases, out);
+  PFLBM_HIP(hipGetLastError());
+  return PFLBM_OK;
+}
+}  // namespace
+
+int run_group_diag(const GroupLaunch& gl, int parity, int ty, int tz, double* partial,
+                   double* out, int ncases, int update_snap) {
+  if (ncases <= 0) return PFLBM_OK;
+#define PFLBM_GD(LT, ST) return group_diag_t<LT, ST>(gl, parity, ty, tz, partial, out, ncases, update_snap)
+  if (gl.lattice == PFLBM_D2Q9) {
+    if (gl.storage == PFLBM_FP64) PFLBM_GD(D2Q9, kF64);
+    if (gl.storage == PFLBM_FP32) PFLBM_GD(D2Q9, kF32);
+    if (gl.storage == PFLBM_FP16_DEV) PFLBM_GD(D2Q9, kF16Dev);
+  } else {
+    if (gl.storage == PFLBM_FP64) PFLBM_GD(D3Q19, kF64);
+    if (gl.storage == PFLBM_FP32) PFLBM_GD(D3Q19, kF32);
+    if (gl.storage == PFLBM_FP16_DEV) PFLBM_GD(D3Q19, kF16Dev);
+  }
+#undef PFLBM_GD
+  return set_error(PFLBM_EUNSUPPORTED, "unsupported lattice/storage %d/%d", gl.lattice, gl.storage);
+}
+
 int run_step_group(const GroupLaunch& gl, int parity, int* occupancy_blocks) {
   if (gl.lattice == PFLBM_D2Q9) {
     if (gl.storage == PFLBM_FP64) return GroupEngine<D2Q9, kF64>::go(gl, parity, occupancy_blocks);
@@ -211,10 +294,13 @@ int run_step_group(const GroupLaunch& gl, int parity, int* occupancy_blocks) {
 
 // Tile of each fused-step variant: threads (64, by, bz), nodes (64, ty, tz).
 int step_variant_tile(int D, int v, int tile[5]) {
+  // variants 0-4: fused one-kernel step; 5-7: split step (phi pass + collide pass)
   static const int t2[kStepVariants][5] = {
-      {4, 1, 64, 4, 1}, {4, 1, 64, 8, 1}, {4, 1, 64, 16, 1}, {8, 1, 64, 16, 1}, {2, 1, 64, 8, 1}};
+      {4, 1, 64, 4, 1}, {4, 1, 64, 8, 1}, {4, 1, 64, 16, 1}, {8, 1, 64, 16, 1}, {2, 1, 64, 8, 1},
+      {4, 1, 64, 4, 1}, {8, 1, 64, 8, 1}, {16, 1, 64, 16, 1}};
   static const int t3[kStepVariants][5] = {
-      {2, 2, 64, 2, 2}, {2, 2, 64, 4, 2}, {2, 2, 64, 4, 4}, {4, 4, 64, 4, 4}, {4, 2, 64, 4, 4}};
+      {2, 2, 64, 2, 2}, {2, 2, 64, 4, 2}, {2, 2, 64, 4, 4}, {4, 4, 64, 4, 4}, {4, 2, 64, 4, 4},
+      {4, 4, 64, 4, 4}, {2, 2, 64, 2, 2}, {4, 2, 64, 4, 2}};
   if (v < 0 || v >= kStepVariants) return -1;
   for (int k = 0; k < 5; ++k) tile[k] = D == 2 ? t2[v][k] : t3[v][k];
   return 0;

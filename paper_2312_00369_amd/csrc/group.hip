@@ -40,11 +40,15 @@ struct pflbm_group_s {
   hipGraphExec_t gexec = nullptr;
   int gexec_steps = 0;
   int grid = 0;
+  // batched diagnostics buffers (partials per table entry, records per member)
+  double* d_partial = nullptr;
+  double* d_rec = nullptr;
+  size_t cap_partial = 0, cap_rec = 0;
 };
 
 namespace {
 
-int default_variant(int D) { return D == 2 ? 1 : 3; }
+int default_variant(int D) { return D == 2 ? 1 : 6; }
 
 void drop_graph(pflbm_group_s* g) {
   if (g->gexec) {
@@ -103,8 +107,13 @@ int rebuild(pflbm_group_s* g) {
     cd.g[0] = h->g[0];
     cd.g[1] = h->g[1];
     cd.s = h->s;
+    cd.phi = h->phi;
+    cd.snap = h->snap;
+    cd.W = h->dv.wall;
     cd.cur0 = h->cur;
     const int nt = tiles_of(h, g->variant);
+    cd.tile0 = (int)table.size();
+    cd.ntile = nt;
     for (int t = 0; t < nt; ++t) table.push_back(TileEntry{(int)k, t});
   }
   bool moved = false;
@@ -139,6 +148,28 @@ int rebuild(pflbm_group_s* g) {
     }
     moved = true;
   }
+  if (table.size() > g->cap_partial || !g->d_partial) {
+    const size_t cap = std::max<size_t>(1024, table.size() * 3 / 2);
+    if (g->d_partial) (void)hipFree(g->d_partial);
+    g->d_partial = nullptr;
+    if (hipMalloc(&g->d_partial, cap * kRecN * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      g->cap_partial = 0;
+      return set_error(PFLBM_ENOMEM, "group partial records allocation failed");
+    }
+    g->cap_partial = cap;
+  }
+  if (cases.size() > g->cap_rec || !g->d_rec) {
+    const size_t cap = std::max<size_t>(64, cases.size() * 3 / 2);
+    if (g->d_rec) (void)hipFree(g->d_rec);
+    g->d_rec = nullptr;
+    if (hipMalloc(&g->d_rec, cap * kRecN * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      g->cap_rec = 0;
+      return set_error(PFLBM_ENOMEM, "group records allocation failed");
+    }
+    g->cap_rec = cap;
+  }
   if (moved) drop_graph(g);
   g->ntiles = (int)table.size();
   if (!table.empty())
@@ -171,6 +202,20 @@ int launch_eager(pflbm_group_s* g) {
 }
 
 }  // namespace
+
+namespace pflbm {
+// A member's step count was set from outside (checkpoint restore): re-base its
+// entry so that the group's bookkeeping reproduces it.
+void group_member_changed(pflbm_case_s* h) {
+  pflbm_group_s* g = h->group;
+  if (!g) return;
+  for (size_t k = 0; k < g->members.size(); ++k)
+    if (g->members[k] == h) {
+      g->step0[k] = h->step - g->since_build;
+      g->cur0[k] = h->cur ^ (int)(g->since_build & 1);
+    }
+}
+}  // namespace pflbm
 
 extern "C" {
 
@@ -306,16 +351,29 @@ int pflbm_group_step(pflbm_group g, int64_t nsteps) {
   return PFLBM_OK;
 }
 
-int pflbm_diagnostics(pflbm_handle h, pflbm_diag* d);
-
 int pflbm_group_poll(pflbm_group g, pflbm_diag* d, int32_t* flags, int32_t capacity) {
   clear_error();
   if (!g) return set_error(PFLBM_EINVAL, "group is NULL");
   if (capacity < (int)g->members.size()) return set_error(PFLBM_EINVAL, "capacity too small");
+  if (g->members.empty()) return PFLBM_OK;
+  int rc;
+  if (g->dirty && (rc = rebuild(g))) return rc;
+  int t[5];
+  step_variant_tile(g->D, g->variant, t);
+  const int nc = (int)g->members.size();
+  if ((rc = run_group_diag(launch_of(g), (int)(g->since_build & 1), t[3], t[4], g->d_partial,
+                           g->d_rec, nc, 1)))
+    return rc;
+  std::vector<double> rec((size_t)nc * kRecN);
+  PFLBM_HIP(hipMemcpyAsync(rec.data(), g->d_rec, rec.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, g->stream));
+  PFLBM_HIP(hipStreamSynchronize(g->stream));
   sync_members(g);
-  for (size_t k = 0; k < g->members.size(); ++k) {
+  for (int k = 0; k < nc; ++k) {
+    pflbm_case_s* h = g->members[k];
     pflbm_diag tmp;
-    if (int rc = pflbm_diagnostics(g->members[k], &tmp)) return rc;
+    finish_diag(h, &rec[(size_t)k * kRecN], &tmp);
+    h->snap_valid = true;
     if (d) d[k] = tmp;
     if (flags) flags[k] = (tmp.steady ? 1 : 0) | (tmp.nonfinite ? 2 : 0);
   }
@@ -358,6 +416,8 @@ void pflbm_group_destroy(pflbm_group g) {
   if (g->d_table) (void)hipFree(g->d_table);
   if (g->d_cases) (void)hipFree(g->d_cases);
   if (g->d_ntiles) (void)hipFree(g->d_ntiles);
+  if (g->d_partial) (void)hipFree(g->d_partial);
+  if (g->d_rec) (void)hipFree(g->d_rec);
   if (g->own_stream) (void)hipStreamDestroy(g->stream);
   delete g;
 }

@@ -28,14 +28,17 @@ namespace pflbm {
 enum Storage { kF64 = 0, kF32 = 1, kF16Dev = 2 };
 
 // ------------------------------------------------------------------ geometry
+// Node index within one case (the padded grid has fewer than 2^31 nodes).
+using nidx = uint32_t;
+
 struct Geo {
   int PX, PY, PZ;    // padded extents: periodic axes as given, others + 2
   int SX;            // x stride (>= PX); nodes x >= PX are dead
   int per[3];        // periodic flags
   int pad[3];        // 0 periodic, 1 otherwise: domain x = padded x - pad
   long long NQ;      // stride between populations (>= SX*PY*PZ)
-  __host__ __device__ long long idx(int x, int y, int z) const {
-    return x + (long long)SX * (y + (long long)PY * z);
+  __host__ __device__ nidx idx(int x, int y, int z) const {
+    return (nidx)x + (nidx)SX * ((nidx)y + (nidx)PY * (nidx)z);
   }
 };
 
@@ -82,8 +85,8 @@ struct Set {
   __host__ __device__ static size_t bytes(long long NQ, int Q) {
     return (size_t)NQ * sizeof(R) + (size_t)(Q - 1) * (size_t)NQ * sizeof(M);
   }
-  __device__ static R load_rest(const void* b, long long n) { return static_cast<const R*>(b)[n]; }
-  __device__ static void store_rest(void* b, long long n, R v, int nt = 0) {
+  __device__ static R load_rest(const void* b, nidx n) { return static_cast<const R*>(b)[n]; }
+  __device__ static void store_rest(void* b, nidx n, R v, int nt = 0) {
     st(static_cast<R*>(b) + n, v, nt);
   }
   __device__ static const M* moving(const void* b, long long NQ) {
@@ -92,15 +95,20 @@ struct Set {
   __device__ static M* moving(void* b, long long NQ) {
     return reinterpret_cast<M*>(static_cast<unsigned char*>(b) + NQ * sizeof(R));
   }
-  // population i >= 1
-  __device__ static C load(const void* b, int i, long long n, long long NQ, float scale) {
-    const M v = moving(b, NQ)[(i - 1) * NQ + n];
+  __device__ static C decode(M v, float scale) {
     if constexpr (kHalf) return __half2float(v) * (1.0f / scale);
     else return C(v);
   }
-  __device__ static void store(void* b, int i, long long n, long long NQ, C v, float scale,
+  // population i >= 1
+  __device__ static const M* pop(const void* b, int i, long long NQ) {
+    return moving(b, NQ) + (size_t)(i - 1) * (size_t)NQ;
+  }
+  __device__ static C load(const void* b, int i, nidx n, long long NQ, float scale) {
+    return decode(pop(b, i, NQ)[n], scale);
+  }
+  __device__ static void store(void* b, int i, nidx n, long long NQ, C v, float scale,
                                int nt = 0) {
-    M* p = moving(b, NQ) + (i - 1) * NQ + n;
+    M* p = moving(b, NQ) + (size_t)(i - 1) * (size_t)NQ + n;
     if constexpr (kHalf) {
       const __half h = __float2half_rn(v * scale);
       if (nt) __builtin_nontemporal_store(*reinterpret_cast<const unsigned short*>(&h),
@@ -124,7 +132,7 @@ __device__ inline int wrap1(int q, int P, int per) {
 // Flat indices of x + c_i for all i, for a zeta = 1 node (interior along
 // non-periodic axes, so only periodic axes can wrap).
 template <class L>
-__device__ inline void neighbours(const Geo& G, int x, int y, int z, long long nb[L::Q]) {
+__device__ inline void neighbours(const Geo& G, int x, int y, int z, nidx nb[L::Q]) {
   const int xs[3] = {wrap1(x - 1, G.PX, G.per[0]), x, wrap1(x + 1, G.PX, G.per[0])};
   const int ys[3] = {wrap1(y - 1, G.PY, G.per[1]), y, wrap1(y + 1, G.PY, G.per[1])};
   int zs[3] = {z, z, z};
@@ -141,13 +149,13 @@ __device__ inline void neighbours(const Geo& G, int x, int y, int z, long long n
 // population of n itself when x - c_i is a zeta = 0 node (bounce-back).  The
 // rest population never moves.
 template <class L, class SetT>
-__device__ inline typename SetT::C pull(const void* buf, int i, long long n,
-                                        const long long nb[L::Q], uint32_t word, long long NQ,
-                                        float scale) {
+__device__ inline typename SetT::C pull(const void* buf, int i, nidx n, const nidx nb[L::Q],
+                                        uint32_t word, long long NQ, float scale) {
   const bool bb = (word >> (kLinkShift + i)) & 1u;
-  const long long src = bb ? n : nb[L::opp(i)];
-  const int dir = bb ? L::opp(i) : i;
-  return SetT::load(buf, dir, src, NQ, scale);
+  const nidx src = bb ? n : nb[L::opp(i)];
+  // both population bases are uniform; each lane picks one
+  const typename SetT::M* p = bb ? SetT::pop(buf, L::opp(i), NQ) : SetT::pop(buf, i, NQ);
+  return SetT::decode(p[src], scale);
 }
 
 __device__ inline bool node_coords(const Geo& G, int& x, int& y, int& z) {
@@ -164,10 +172,10 @@ __global__ void k_phi(const uint32_t* __restrict__ nodes, const void* __restrict
   using C = ComputeT<S>;
   int x, y, z;
   if (!node_coords(G, x, y, z)) return;
-  const long long n = G.idx(x, y, z);
+  const nidx n = G.idx(x, y, z);
   const uint32_t word = nodes[n];
   if (!(word & kZeta)) return;
-  long long nb[L::Q];
+  nidx nb[L::Q];
   neighbours<L>(G, x, y, z, nb);
   using GS = Set<S, true>;
   // g_0 carries phi; the moving populations are small.  Summing them first and
@@ -283,7 +291,7 @@ __global__ void k_mu(const uint32_t* __restrict__ nodes, C* __restrict__ phi,
     uint32_t w = 0;
     C v = C(0);
     if (ok) {
-      const long long n = G.idx(q[0], q[1], q[2]);
+      const nidx n = G.idx(q[0], q[1], q[2]);
       w = nodes[n];
       if (w & kZeta) v = phi[n];
     }
@@ -303,7 +311,7 @@ __global__ void k_mu(const uint32_t* __restrict__ nodes, C* __restrict__ phi,
   if (!node_coords(G, x, y, z)) return;
   const int t = (threadIdx.x + H) + LX * ((threadIdx.y + H) + LY * (threadIdx.z + HZ));
   const uint32_t w = sw[t];
-  const long long n = G.idx(x, y, z);
+  const nidx n = G.idx(x, y, z);
   if (w & kZeta) mu[n] = mu_at<L, C>(sphi, sw, t, LX, LX * LY, P);
   else if (w & kGhost) phi[n] = sphi[t];
 }
@@ -316,7 +324,7 @@ __global__ void k_mu(const uint32_t* __restrict__ nodes, C* __restrict__ phi,
 template <class L, int S, int MODE>
 __device__ inline void node_update(const ComputeT<S>* f, double g0, const ComputeT<S>* g,
                                    ComputeT<S> ph, ComputeT<S> m, ComputeT<S> gx,
-                                   ComputeT<S> gy, ComputeT<S> gz, long long n,
+                                   ComputeT<S> gy, ComputeT<S> gz, nidx n,
                                    void* __restrict__ fdst, void* __restrict__ gdst,
                                    ComputeT<S>* __restrict__ sprev, ComputeT<S>* __restrict__ out_p,
                                    ComputeT<S>* __restrict__ out_u, const Geo& G, const Phys& P,
@@ -420,10 +428,10 @@ __global__ void k_collide(const uint32_t* __restrict__ nodes, const void* __rest
   constexpr int Q = L::Q;
   int x, y, z;
   if (!node_coords(G, x, y, z)) return;
-  const long long n = G.idx(x, y, z);
+  const nidx n = G.idx(x, y, z);
   const uint32_t word = nodes[n];
   if (!(word & kZeta)) return;
-  long long nb[Q];
+  nidx nb[Q];
   neighbours<L>(G, x, y, z, nb);
   using FS = Set<S, false>;
   using GS = Set<S, true>;
@@ -506,8 +514,8 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
     return lx >= 2 && lx < 2 + TX && ly >= 2 && ly < 2 + TY && (!D3 || (lz >= 2 && lz < 2 + TZ));
   };
   // phi of a zeta = 1 node from its pulled g (same order as k_phi)
-  auto phi_of = [&](long long n, uint32_t w, const int q[3]) -> C {
-    long long nb[Q];
+  auto phi_of = [&](nidx n, uint32_t w, const int q[3]) -> C {
+    nidx nb[Q];
     neighbours<L>(G, q[0], q[1], q[2], nb);
     C small = C(0);
 #pragma unroll
@@ -543,7 +551,7 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
     if (w & kZeta) {
       int q[3];
       const long long n = gnode(lx, ly, lz, q);
-      long long nb[Q];
+      nidx nb[Q];
       neighbours<L>(G, q[0], q[1], q[2], nb);
       C small = C(0);
 #pragma unroll
@@ -604,8 +612,8 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
     const int t = lx + SX * ly + SXY * lz;
     const uint32_t w = sw[t];
     if (!(w & kZeta)) continue;
-    const long long n = G.idx(x, y, z);
-    long long nb[Q];
+    const nidx n = G.idx(x, y, z);
+    nidx nb[Q];
     neighbours<L>(G, x, y, z, nb);
     C f[Q];
     f[0] = C(FS::load_rest(fsrc, n));
@@ -644,12 +652,154 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_step(
                                   G, P, sphi, sw);
 }
 
+// ------------------------------------------------------------------ split step
+// Two launches per step: k_phi writes phi, then this kernel loads phi and the
+// node words of the tile with a two-node halo into LDS (4 bytes per entry, from
+// L2), fills ghosts, evaluates mu and grad phi from LDS, pulls f and g and
+// collides.  One thread per node; workgroup (64, BY, BZ).  g is read twice per
+// step, but nothing is recomputed on the halo, which suits D3Q19 where a
+// one-node halo around a 64 x 4 x 4 tile already has 1.3 times its nodes.
+template <class L, int S, int BY, int BZ>
+__device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __restrict__ nodes,
+                                  const void* __restrict__ fsrc, const void* __restrict__ gsrc,
+                                  void* __restrict__ fdst, void* __restrict__ gdst,
+                                  ComputeT<S>* __restrict__ sprev,
+                                  const ComputeT<S>* __restrict__ phi, const Geo& G,
+                                  const Phys& P, ComputeT<S>* sphi, uint32_t* sw) {
+  using C = ComputeT<S>;
+  using GS = Set<S, true>;
+  using FS = Set<S, false>;
+  constexpr int Q = L::Q;
+  constexpr bool D3 = (L::D == 3);
+  constexpr int TX = 64, TY = BY, TZ = D3 ? BZ : 1;
+  constexpr int LX = TX + 4, LY = TY + 4, LZ = D3 ? TZ + 4 : 1;
+  constexpr int SX = LX, SXY = LX * LY, NL = LX * LY * LZ;
+  constexpr int HZ = D3 ? 2 : 0;
+  constexpr int NT = 64 * BY * (D3 ? BZ : 1);
+  const int lane = threadIdx.x, ty = threadIdx.y, tz = D3 ? threadIdx.z : 0;
+  const int tid = lane + 64 * (ty + BY * tz);
+  const int P3[3] = {G.PX, G.PY, G.PZ};
+  // word and phi of LDS entry (lx, ly, lz); zeta = 0 entries hold phi = 0
+  auto load_entry = [&](int lx, int ly, int lz) -> uint32_t {
+    int q[3] = {x0 - 2 + lx, y0 - 2 + ly, z0 - HZ + lz};
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (G.per[d]) {
+        q[d] %= P3[d];
+        if (q[d] < 0) q[d] += P3[d];
+      } else if (q[d] < 0 || q[d] >= P3[d]) {
+        ok = false;
+      }
+    }
+    uint32_t w = 0;
+    C v = C(0);
+    if (ok) {
+      const nidx n = G.idx(q[0], q[1], q[2]);
+      w = nodes[n];
+      if (w & kZeta) v = phi[n];
+    }
+    const int m = lx + SX * ly + SXY * lz;
+    sw[m] = w;
+    sphi[m] = v;
+    return w;
+  };
+  // tile and first halo layer; the second layer only where ghost means need it
+  constexpr int H1X = TX + 2, H1Y = TY + 2, H1Z = D3 ? TZ + 2 : 1;
+  constexpr int N1 = H1X * H1Y * H1Z;
+  bool ghost_near = false;
+  for (int m = tid; m < N1; m += NT) {
+    const int lx = 1 + m % H1X, ly = 1 + (m / H1X) % H1Y, lz = (D3 ? 1 : 0) + m / (H1X * H1Y);
+    ghost_near |= (load_entry(lx, ly, lz) & kGhost) != 0;
+  }
+  if (__syncthreads_or(ghost_near)) {
+    for (int m = tid; m < NL; m += NT) {
+      const int lx = m % LX, ly = (m / LX) % LY, lz = m / (LX * LY);
+      const bool ring2 = lx == 0 || lx == LX - 1 || ly == 0 || ly == LY - 1 ||
+                         (D3 && (lz == 0 || lz == LZ - 1));
+      if (ring2) load_entry(lx, ly, lz);
+    }
+    __syncthreads();
+    for (int m = tid; m < N1; m += NT) {
+      const int lx = 1 + m % H1X, ly = 1 + (m / H1X) % H1Y, lz = (D3 ? 1 : 0) + m / (H1X * H1Y);
+      const int t = lx + SX * ly + SXY * lz;
+      if (sw[t] & kGhost) sphi[t] = ghost_mean<L, C>(sphi, sw, t, SX, SXY);
+    }
+    __syncthreads();
+  }
+  const int x = x0 + lane, y = y0 + ty, z = z0 + tz;
+  if (x >= G.PX || y >= G.PY || z >= G.PZ) return;
+  const int t = (2 + lane) + SX * (2 + ty) + SXY * (HZ + tz);
+  const uint32_t w = sw[t];
+  if (!(w & kZeta)) return;
+  const nidx n = G.idx(x, y, z);
+  nidx nb[Q];
+  neighbours<L>(G, x, y, z, nb);
+  C f[Q], g[Q];
+  f[0] = C(FS::load_rest(fsrc, n));
+  const double g0 = GS::load_rest(gsrc, n);
+  g[0] = C(0);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    f[i] = pull<L, FS>(fsrc, i, n, nb, w, G.NQ, P.scale_f);
+    g[i] = pull<L, GS>(gsrc, i, n, nb, w, G.NQ, P.scale_g);
+  }
+  const C m = mu_at<L, C>(sphi, sw, t, SX, SXY, P);
+  C gx, gy, gz;
+  grad_of<L, C>([&](int i) { return sphi[t + L::cx(i) + SX * L::cy(i) + SXY * L::cz(i)]; },
+                gx, gy, gz);
+  node_update<L, S, 0>(f, g0, g, sphi[t], m, gx, gy, gz, n, fdst, gdst, sprev, nullptr, nullptr,
+                       G, P, P.nt_store);
+}
+
+template <class L, int S, int BY, int BZ>
+__global__ __launch_bounds__(64 * BY * BZ) void k_stepB(
+    const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
+    const void* __restrict__ gsrc, void* __restrict__ fdst, void* __restrict__ gdst,
+    ComputeT<S>* __restrict__ sprev, const ComputeT<S>* __restrict__ phi, Geo G, Phys P) {
+  constexpr bool D3 = (L::D == 3);
+  constexpr int NL = 68 * (BY + 4) * (D3 ? BZ + 4 : 1);
+  __shared__ ComputeT<S> sphi[NL];
+  __shared__ uint32_t sw[NL];
+  const int TZ = D3 ? BZ : 1;
+  const int nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY;
+  const int b = blockIdx.x;
+  stepB_tile<L, S, BY, BZ>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ, nodes,
+                           fsrc, gsrc, fdst, gdst, sprev, phi, G, P, sphi, sw);
+}
+
+// phi of the tile nodes (64 x BY x BZ) from pulled g, same arithmetic as k_phi.
+template <class L, int S, int BY, int BZ>
+__device__ inline void phi_tile(int x0, int y0, int z0, const uint32_t* __restrict__ nodes,
+                                const void* __restrict__ gsrc, ComputeT<S>* __restrict__ phi,
+                                const Geo& G, const Phys& P) {
+  using C = ComputeT<S>;
+  using GS = Set<S, true>;
+  const int x = x0 + threadIdx.x, y = y0 + threadIdx.y, z = z0 + ((L::D == 3) ? threadIdx.z : 0);
+  if (x >= G.PX || y >= G.PY || z >= G.PZ) return;
+  const nidx n = G.idx(x, y, z);
+  const uint32_t w = nodes[n];
+  if (!(w & kZeta)) return;
+  nidx nb[L::Q];
+  neighbours<L>(G, x, y, z, nb);
+  C small = C(0);
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) small += pull<L, GS>(gsrc, i, n, nb, w, G.NQ, P.scale_g);
+  phi[n] = C(GS::load_rest(gsrc, n) + (double)small);
+}
+
 // ------------------------------------------------------------------ batched step
 // Many cases of one lattice and storage advance together.  A persistent grid
 // walks a device table of (case, tile) entries; each case has a descriptor
 // with its geometry, physics and buffers.  The table and descriptors live in
 // device memory and may change between launches (cases joining or leaving)
 // without touching the launch arguments, so captured graphs stay valid.
+struct Wall {
+  int kind;          // 0 none, 1 plane, 2 ball
+  double p[3], nrm[3], radius, width;
+  double ref[3];     // coordinates are taken relative to this point
+};
+
 struct CaseDesc {
   Geo G;
   Phys P;
@@ -657,7 +807,11 @@ struct CaseDesc {
   void* f[2];
   void* g[2];
   void* s;
+  void* phi;         // phi array (split-step variants, diagnostics)
+  void* snap;        // steady-state reference phi
+  Wall W;            // wall of the contact-angle fit
   int cur0;          // buffer holding the current state when parity == 0
+  int tile0, ntile;  // the member's entries in the tile table
   int pad_;
 };
 
@@ -689,6 +843,51 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_step_group(
   }
 }
 
+
+// Batched split step: the phi pass and the collide pass, each over the table.
+template <class L, int S, int BY, int BZ>
+__global__ __launch_bounds__(64 * BY * BZ) void k_phi_group(
+    const TileEntry* __restrict__ table, const int* __restrict__ ntiles,
+    const CaseDesc* __restrict__ cases, int parity) {
+  const int n = *ntiles;
+  const int TZ = (L::D == 3) ? BZ : 1;
+  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+    const TileEntry te = table[e];
+    const CaseDesc& cd = cases[te.case_id];
+    const Geo G = cd.G;
+    const int c = cd.cur0 ^ parity;
+    const int nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY;
+    const int b = te.tile;
+    phi_tile<L, S, BY, BZ>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ,
+                           cd.nodes, cd.g[c], static_cast<ComputeT<S>*>(cd.phi), G, cd.P);
+  }
+}
+
+template <class L, int S, int BY, int BZ>
+__global__ __launch_bounds__(64 * BY * BZ) void k_stepB_group(
+    const TileEntry* __restrict__ table, const int* __restrict__ ntiles,
+    const CaseDesc* __restrict__ cases, int parity) {
+  constexpr bool D3 = (L::D == 3);
+  constexpr int NL = 68 * (BY + 4) * (D3 ? BZ + 4 : 1);
+  __shared__ ComputeT<S> sphi[NL];
+  __shared__ uint32_t sw[NL];
+  const int n = *ntiles;
+  const int TZ = D3 ? BZ : 1;
+  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+    const TileEntry te = table[e];
+    const CaseDesc& cd = cases[te.case_id];
+    const Geo G = cd.G;
+    const int c = cd.cur0 ^ parity;
+    const int nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY;
+    const int b = te.tile;
+    stepB_tile<L, S, BY, BZ>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ,
+                             cd.nodes, cd.f[c], cd.g[c], cd.f[1 - c], cd.g[1 - c],
+                             static_cast<ComputeT<S>*>(cd.s),
+                             static_cast<const ComputeT<S>*>(cd.phi), G, cd.P, sphi, sw);
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------ init
 // g at t = 0 is g_eq(phi0, mu0) after streaming; store it where the first pull
 // will find it (the inverse of the pull map).  f = 0 is set by a memset.
@@ -699,10 +898,10 @@ __global__ void k_init_g(const uint32_t* __restrict__ nodes, void* __restrict__ 
   using C = ComputeT<S>;
   int x, y, z;
   if (!node_coords(G, x, y, z)) return;
-  const long long n = G.idx(x, y, z);
+  const nidx n = G.idx(x, y, z);
   const uint32_t word = nodes[n];
   if (!(word & kZeta)) return;
-  long long nb[L::Q];
+  nidx nb[L::Q];
   neighbours<L>(G, x, y, z, nb);
   using GS = Set<S, true>;
   const C am = C(P.alpha) * mu[n];
@@ -724,12 +923,6 @@ enum {
   kRecMass = 0, kRecS, kRecResid, kRecNonfinite, kRecCount,
   kRecX, kRecY, kRecZ, kRecXX, kRecXY, kRecXZ, kRecYY, kRecYZ, kRecZZ,
   kRecXR, kRecYR, kRecZR, kRecRR, kRecAbsMax, kRecN
-};
-
-struct Wall {
-  int kind;          // 0 none, 1 plane, 2 ball
-  double p[3], nrm[3], radius, width;
-  double ref[3];     // coordinates are taken relative to this point
 };
 
 __device__ inline double wall_dist(const Wall& W, double x, double y, double z) {
@@ -760,45 +953,44 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-// One partial record per workgroup; blockDim must be a multiple of 64 (<= 1024).
-// Interface points lie on edges (x, x + e_a) inside the domain between two
-// zeta = 1 nodes where exactly one phi is below 1/2 (no periodic seam).
+// Contribution of node (x, y, z) to a diagnostics record.  Interface points lie
+// on edges (x, x + e_a) inside the domain between two zeta = 1 nodes where
+// exactly one phi is below 1/2 (no periodic seam).
 template <class L, class C>
-__global__ void k_reduce_partial(const uint32_t* __restrict__ nodes, const C* __restrict__ phi,
-                                 const C* __restrict__ s, C* __restrict__ snap,
-                                 double* __restrict__ partial, Geo G, Wall W, int update_snap) {
-  __shared__ double red[16][kRecN];
-  double acc[kRecN];
+__device__ inline void node_contrib(double* acc, const uint32_t* __restrict__ nodes,
+                                    const C* __restrict__ phi, const C* __restrict__ s,
+                                    C* __restrict__ snap, int x, int y, int z, const Geo& G,
+                                    const Wall& W, int update_snap) {
+  const nidx n = G.idx(x, y, z);
+  const uint32_t w = nodes[n];
+  if (!(w & kZeta)) return;
+  const double ph = (double)phi[n];
+  acc[kRecMass] += ph;
+  acc[kRecS] += (double)s[n];
+  const double sn = (double)snap[n];
+  acc[kRecResid] = fmax(acc[kRecResid], fabs(ph - sn));
+  acc[kRecAbsMax] = fmax(acc[kRecAbsMax], fabs(ph));
+  if (!isfinite(ph) || !isfinite((double)s[n])) acc[kRecNonfinite] += 1.0;
+  if (update_snap) snap[n] = phi[n];
+  const double X = x - G.pad[0], Y = y - G.pad[1], Z = (L::D == 3) ? z - G.pad[2] : 0;
+  const int P3[3] = {G.PX, G.PY, G.PZ};
+  const int c3[3] = {x, y, z};
 #pragma unroll
-  for (int k = 0; k < kRecN; ++k) acc[k] = 0.0;
-  int x, y, z;
-  if (node_coords(G, x, y, z)) {
-    const long long n = G.idx(x, y, z);
-    const uint32_t w = nodes[n];
-    if (w & kZeta) {
-      const double ph = (double)phi[n];
-      acc[kRecMass] = ph;
-      acc[kRecS] = (double)s[n];
-      const double sn = (double)snap[n];
-      acc[kRecResid] = fabs(ph - sn);
-      acc[kRecAbsMax] = fabs(ph);
-      if (!isfinite(ph) || !isfinite(acc[kRecS])) acc[kRecNonfinite] = 1.0;
-      if (update_snap) snap[n] = phi[n];
-      const double X = x - G.pad[0], Y = y - G.pad[1], Z = (L::D == 3) ? z - G.pad[2] : 0;
-      const int P3[3] = {G.PX, G.PY, G.PZ};
-      const int c3[3] = {x, y, z};
-#pragma unroll
-      for (int a = 0; a < L::D; ++a) {
-        if (c3[a] + 1 >= P3[a]) continue;
-        const long long n2 = n + (a == 0 ? 1LL : a == 1 ? (long long)G.SX : (long long)G.SX * G.PY);
-        if (!(nodes[n2] & kZeta)) continue;
-        const double p2 = (double)phi[n2];
-        if ((ph < 0.5) == (p2 < 0.5)) continue;
-        const double t = (0.5 - ph) / (p2 - ph);
-        add_point<C>(acc, W, X + (a == 0 ? t : 0.0), Y + (a == 1 ? t : 0.0), Z + (a == 2 ? t : 0.0));
-      }
-    }
+  for (int a = 0; a < L::D; ++a) {
+    if (c3[a] + 1 >= P3[a]) continue;
+    const nidx n2 = n + (a == 0 ? 1u : a == 1 ? (nidx)G.SX : (nidx)G.SX * (nidx)G.PY);
+    if (!(nodes[n2] & kZeta)) continue;
+    const double p2 = (double)phi[n2];
+    if ((ph < 0.5) == (p2 < 0.5)) continue;
+    const double t = (0.5 - ph) / (p2 - ph);
+    add_point<C>(acc, W, X + (a == 0 ? t : 0.0), Y + (a == 1 ? t : 0.0), Z + (a == 2 ? t : 0.0));
   }
+}
+
+// Workgroup reduction of per-thread records into out[0..kRecN) (sums, except
+// the residual and |phi| maxima).  blockDim is a multiple of 64, at most 1024.
+__device__ inline void block_record(double* acc, double* out) {
+  __shared__ double red[16][kRecN];
   const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
   const int lane = tid & 63, wv = tid >> 6;
   const int nw = (blockDim.x * blockDim.y * blockDim.z + 63) / 64;
@@ -812,9 +1004,23 @@ __global__ void k_reduce_partial(const uint32_t* __restrict__ nodes, const C* __
     double v = red[0][tid];
     for (int j = 1; j < nw; ++j)
       v = (tid == kRecResid || tid == kRecAbsMax) ? fmax(v, red[j][tid]) : v + red[j][tid];
-    const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
-    partial[b * kRecN + tid] = v;
+    out[tid] = v;
   }
+  __syncthreads();
+}
+
+// One partial record per workgroup (grid over the padded nodes).
+template <class L, class C>
+__global__ void k_reduce_partial(const uint32_t* __restrict__ nodes, const C* __restrict__ phi,
+                                 const C* __restrict__ s, C* __restrict__ snap,
+                                 double* __restrict__ partial, Geo G, Wall W, int update_snap) {
+  double acc[kRecN];
+#pragma unroll
+  for (int k = 0; k < kRecN; ++k) acc[k] = 0.0;
+  int x, y, z;
+  if (node_coords(G, x, y, z)) node_contrib<L, C>(acc, nodes, phi, s, snap, x, y, z, G, W, update_snap);
+  const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+  block_record(acc, partial + b * kRecN);
 }
 
 // Sums nparts partial records in a fixed order (deterministic); one workgroup of 256.
@@ -847,6 +1053,93 @@ __global__ void k_reduce_final(const double* __restrict__ partial, long long npa
       v = (k == kRecResid || k == kRecAbsMax) ? fmax(v, red[j][k]) : v + red[j][k];
     out[k] = v;
   }
+}
+
+
+// ------------------------------------------------------------------ batched diagnostics
+// For a group poll: phi of every member (same arithmetic as k_phi), then one
+// partial record per table entry, then per member a fixed-order sum of its
+// entries' partials.  Tiles are (64, ty, tz) nodes, walked by 256 threads.
+template <class L, int S>
+__global__ __launch_bounds__(256) void k_phi_group_all(const TileEntry* __restrict__ table,
+                                                        const int* __restrict__ ntiles,
+                                                        const CaseDesc* __restrict__ cases,
+                                                        int parity, int ty, int tz) {
+  using C = ComputeT<S>;
+  using GS = Set<S, true>;
+  const int n = *ntiles;
+  const int tid = threadIdx.x;
+  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+    const TileEntry te = table[e];
+    const CaseDesc& cd = cases[te.case_id];
+    const Geo G = cd.G;
+    const void* gsrc = cd.g[cd.cur0 ^ parity];
+    C* phi = static_cast<C*>(cd.phi);
+    const int nbx = (G.PX + 63) / 64, nby = (G.PY + ty - 1) / ty;
+    const int b = te.tile;
+    const int x0 = (b % nbx) * 64, y0 = ((b / nbx) % nby) * ty, z0 = (b / (nbx * nby)) * tz;
+    for (int m = tid; m < 64 * ty * tz; m += 256) {
+      const int x = x0 + m % 64, y = y0 + (m / 64) % ty, z = z0 + m / (64 * ty);
+      if (x >= G.PX || y >= G.PY || z >= G.PZ) continue;
+      const nidx nn = G.idx(x, y, z);
+      const uint32_t w = cd.nodes[nn];
+      if (!(w & kZeta)) continue;
+      nidx nb[L::Q];
+      neighbours<L>(G, x, y, z, nb);
+      C small = C(0);
+#pragma unroll
+      for (int i = 1; i < L::Q; ++i) small += pull<L, GS>(gsrc, i, nn, nb, w, G.NQ, cd.P.scale_g);
+      phi[nn] = C(GS::load_rest(gsrc, nn) + (double)small);
+    }
+  }
+}
+
+template <class L, class C>
+__global__ __launch_bounds__(256) void k_reduce_group(const TileEntry* __restrict__ table,
+                                                       const int* __restrict__ ntiles,
+                                                       const CaseDesc* __restrict__ cases,
+                                                       double* __restrict__ partial, int ty,
+                                                       int tz, int update_snap) {
+  const int n = *ntiles;
+  const int tid = threadIdx.x;
+  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+    const TileEntry te = table[e];
+    const CaseDesc& cd = cases[te.case_id];
+    const Geo G = cd.G;
+    const int nbx = (G.PX + 63) / 64, nby = (G.PY + ty - 1) / ty;
+    const int b = te.tile;
+    const int x0 = (b % nbx) * 64, y0 = ((b / nbx) % nby) * ty, z0 = (b / (nbx * nby)) * tz;
+    double acc[kRecN];
+#pragma unroll
+    for (int k = 0; k < kRecN; ++k) acc[k] = 0.0;
+    for (int m = tid; m < 64 * ty * tz; m += 256) {
+      const int x = x0 + m % 64, y = y0 + (m / 64) % ty, z = z0 + m / (64 * ty);
+      if (x >= G.PX || y >= G.PY || z >= G.PZ) continue;
+      node_contrib<L, C>(acc, cd.nodes, static_cast<const C*>(cd.phi),
+                         static_cast<const C*>(cd.s), static_cast<C*>(cd.snap), x, y, z, G,
+                         cd.W, update_snap);
+    }
+    block_record(acc, partial + (long long)e * kRecN);
+  }
+}
+
+// One workgroup of 256 per member: fixed-order sum of its table entries.
+template <int NR>
+__global__ __launch_bounds__(256) void k_reduce_final_group(const double* __restrict__ partial,
+                                                             const CaseDesc* __restrict__ cases,
+                                                             double* __restrict__ out) {
+  static_assert(NR == kRecN, "record size");
+  const CaseDesc& cd = cases[blockIdx.x];
+  double acc[kRecN];
+#pragma unroll
+  for (int k = 0; k < kRecN; ++k) acc[k] = 0.0;
+  for (int t = threadIdx.x; t < cd.ntile; t += blockDim.x) {
+    const double* p = partial + (long long)(cd.tile0 + t) * kRecN;
+#pragma unroll
+    for (int k = 0; k < kRecN; ++k)
+      acc[k] = (k == kRecResid || k == kRecAbsMax) ? fmax(acc[k], p[k]) : acc[k] + p[k];
+  }
+  block_record(acc, out + (long long)blockIdx.x * kRecN);
 }
 
 }  // namespace pflbm

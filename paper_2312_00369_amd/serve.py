@@ -1,0 +1,227 @@
+"""Continuous-batching server for droplet / wetting cases.
+
+Requests arrive over time (each carries its arrival time).  A request is
+admitted, first come first served, as soon as its HBM footprint fits the free
+budget and a slot is free; admitted cases join the running group of their
+lattice and storage at the next chunk boundary and advance together with the
+cases already resident.  After every chunk the groups are polled: cases that
+are steady (max |phi(t) - phi(t - chunk)| <= steady_tol), non-finite, or at
+their step cap leave, their memory is freed and waiting requests are admitted.
+
+The executor is an interface (`Executor`): `GpuExecutor` drives the HIP
+library; tests drive the same scheduler with a fake executor and clock.
+Time-to-steady is measured from a request's arrival to the poll that found it
+steady.
+"""
+import collections
+import time
+
+
+class Executor:
+    """What the scheduler needs from a backend."""
+
+    def now(self):
+        raise NotImplementedError
+
+    def wait_until(self, t):
+        raise NotImplementedError
+
+    def footprint(self, req):
+        raise NotImplementedError
+
+    def admit(self, req):
+        """Create the case on the device and add it to its group; returns a key."""
+        raise NotImplementedError
+
+    def step(self, nsteps):
+        """Advance every admitted case nsteps."""
+        raise NotImplementedError
+
+    def poll(self):
+        """{key: dict(steady=bool, nonfinite=bool, steps=int, theta_deg=..., mass=...)}"""
+        raise NotImplementedError
+
+    def release(self, key):
+        """Remove the case, free its memory; returns its final record (dict)."""
+        raise NotImplementedError
+
+
+class GpuExecutor(Executor):
+    """Cases on the GPU, one group per (lattice, storage)."""
+
+    def __init__(self, stream=None, keep_fields=False, variant_2d=-1, variant_3d=-1):
+        from . import pflbm as P
+        self.P = P
+        self.groups = {}
+        self.cases = {}
+        self.keep_fields = keep_fields
+        self.variants = {P.D2Q9: variant_2d, P.D3Q19: variant_3d}
+        self.stream = stream
+        self._next = 0
+
+    def now(self):
+        return time.perf_counter()
+
+    def wait_until(self, t):
+        dt = t - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+
+    def params(self, req):
+        return self.P.params_from_case(req, req.get("storage", "f32"),
+                                       steady_tol=req.get("steady_tol", 1e-5))
+
+    def footprint(self, req):
+        return self.P.footprint(self.params(req))
+
+    def admit(self, req):
+        prm = self.params(req)
+        case = self.P.Case(prm, req["mask"], req["phi0"], stream=self.stream)
+        gk = (prm.lattice, prm.storage)
+        if gk not in self.groups:
+            g = self.P.Group(stream=self.stream)
+            g.set_tile(self.variants[prm.lattice], 0)
+            self.groups[gk] = g
+        self.groups[gk].add(case)
+        key = self._next
+        self._next += 1
+        self.cases[key] = (case, gk)
+        return key
+
+    def step(self, nsteps):
+        for g in self.groups.values():
+            if len(g.members):
+                g.step(nsteps)
+
+    def poll(self):
+        out = {}
+        by_case = {id(c): k for k, (c, _) in self.cases.items()}
+        for g in self.groups.values():
+            if not len(g.members):
+                continue
+            diags, flags = g.poll()
+            for m, d, f in zip(g.members, diags, flags):
+                out[by_case[id(m)]] = dict(steady=bool(f & 1), nonfinite=bool(f & 2),
+                                           steps=d["step"], theta_deg=d["theta_deg"],
+                                           mass=d["mass"], residual=d["steady_residual"])
+        return out
+
+    def release(self, key):
+        case, gk = self.cases.pop(key)
+        d = case.diagnostics()
+        rec = dict(steps=d["step"], theta_deg=d["theta_deg"], mass=d["mass"],
+                   nonfinite=d["nonfinite"])
+        if self.keep_fields:
+            rec["fields"] = case.fields()
+        self.groups[gk].remove(case)
+        case.close()
+        return rec
+
+
+class Server:
+    def __init__(self, executor, budget_bytes, max_slots=64, chunk_steps=1000,
+                 max_steps=200000):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_slots = int(max_slots)
+        self.chunk = int(chunk_steps)
+        self.max_steps = int(max_steps)
+
+    def run(self, requests):
+        """Serve `requests` (dicts with 'arrival_s'); returns (records, summary)."""
+        ex = self.ex
+        pending = collections.deque(sorted(range(len(requests)),
+                                           key=lambda i: requests[i]["arrival_s"]))
+        waiting = collections.deque()
+        active = {}             # key -> request index
+        used = 0
+        fps = {}
+        rec = [dict(index=i, arrival_s=requests[i]["arrival_s"]) for i in range(len(requests))]
+        t0 = ex.now()
+        busy = 0.0
+
+        def clock():
+            return ex.now() - t0
+
+        while pending or waiting or active:
+            now = clock()
+            while pending and requests[pending[0]]["arrival_s"] <= now:
+                waiting.append(pending.popleft())
+            # admission: first come first served, by footprint and slots
+            while waiting and len(active) < self.max_slots:
+                i = waiting[0]
+                fp = ex.footprint(requests[i])
+                if fp > self.budget:
+                    waiting.popleft()
+                    rec[i].update(refused="footprint exceeds the budget", footprint=fp)
+                    continue
+                if used + fp > self.budget:
+                    break
+                waiting.popleft()
+                key = ex.admit(requests[i])
+                active[key] = i
+                fps[key] = fp
+                used += fp
+                rec[i].update(admit_s=clock(), footprint=fp)
+            if not active:
+                if pending:
+                    ex.wait_until(t0 + requests[pending[0]]["arrival_s"])
+                    continue
+                break
+            tb = clock()
+            ex.step(self.chunk)
+            status = ex.poll()
+            busy += clock() - tb
+            done_t = clock()
+            for key, st in status.items():
+                i = active.get(key)
+                if i is None:
+                    continue
+                finished = st["steady"] or st["nonfinite"] or st["steps"] >= self.max_steps
+                if not finished:
+                    continue
+                r = ex.release(key)
+                del active[key]
+                used -= fps.pop(key)
+                rec[i].update(r)
+                rec[i]["done_s"] = done_t
+                rec[i]["steady"] = bool(st["steady"])
+                rec[i]["status"] = ("steady" if st["steady"] else
+                                    "nonfinite" if st["nonfinite"] else "step cap")
+                if st["steady"]:
+                    rec[i]["time_to_steady_s"] = done_t - rec[i]["arrival_s"]
+        wall = clock()
+        return rec, summarize(rec, wall, busy, requests)
+
+
+def percentile(xs, q):
+    if not xs:
+        return None
+    s = sorted(xs)
+    k = (len(s) - 1) * q / 100.0
+    lo, hi = int(k), min(int(k) + 1, len(s) - 1)
+    return s[lo] + (s[hi] - s[lo]) * (k - lo)
+
+
+def _nodes(req):
+    if "nodes" in req:
+        return int(req["nodes"])
+    n = 1
+    for v in req["shape"]:
+        n *= int(v)
+    return n
+
+
+def summarize(rec, wall, busy, requests):
+    tts = [r["time_to_steady_s"] for r in rec if "time_to_steady_s" in r]
+    served = [r for r in rec if "done_s" in r]
+    node_steps = sum(int(r.get("steps", 0)) * _nodes(requests[r["index"]]) for r in served)
+    span = max(requests[-1]["arrival_s"], 1e-9) if requests else 0.0
+    return dict(requests=len(rec), served=len(served), steady=len(tts),
+                refused=sum(1 for r in rec if "refused" in r),
+                wall_s=wall, gpu_busy_s=busy,
+                cases_per_s=len(served) / wall if wall > 0 else None,
+                aggregate_MLUPS=node_steps / wall / 1e6 if wall > 0 else None,
+                p50_time_to_steady_s=percentile(tts, 50),
+                p99_time_to_steady_s=percentile(tts, 99),
+                offered_rate_per_s=(len(requests) / span) if span else None)

@@ -44,16 +44,32 @@ def test_group_alone_vs_mix_bitwise_2d(P, storage):
             assert np.array_equal(f[k], ref[k]), k
 
 
-def test_group_alone_vs_mix_bitwise_3d(P):
+@pytest.mark.parametrize("variant", [3, 5, 6])
+def test_group_alone_vs_mix_bitwise_3d(P, variant):
+    """Fused (3) and split (5, 6) batched kernels."""
     cs = [workloads.inclined_droplet_case_3d(n=n, radius=0.25 * n, theta=th, width=4.0)
           for n, th in ((18, 60.0), (26, 120.0), (22, 45.0))]
     g = P.Group()
+    g.set_tile(variant)
     members = [P.Case.from_case(c, "f32") for c in cs]
     for m in members:
         g.add(m)
     g.step(21)
     for c, m in zip(cs, members):
-        ref = _alone(P, c, "f32", 21, 3)
+        ref = _alone(P, c, "f32", 21, variant)
+        assert np.array_equal(m.fields()["phi"], ref["phi"])
+
+
+def test_group_split_variant_2d(P):
+    cs = _cases2d()[:4]
+    g = P.Group()
+    g.set_tile(6)
+    members = [P.Case.from_case(c, "f32") for c in cs]
+    for m in members:
+        g.add(m)
+    g.step(15)
+    for c, m in zip(cs, members):
+        ref = _alone(P, c, "f32", 15, 1)
         assert np.array_equal(m.fields()["phi"], ref["phi"])
 
 
@@ -131,3 +147,28 @@ def test_group_rejects_mixed_storage(P):
     g.add(a)
     with pytest.raises(P.PflbmError):
         a.step(1)                      # members are stepped through the group
+
+
+@pytest.mark.parametrize("variant", [1, 6])
+def test_group_poll_matches_single_diagnostics(P, variant):
+    """The batched reductions (one launch sequence for all members) give each
+    member the record its own diagnostics call gives, up to summation order."""
+    cs = _cases2d()[:5]
+    g = P.Group()
+    g.set_tile(variant)
+    ms = [P.Case.from_case(c, "f32") for c in cs]
+    for m in ms:
+        g.add(m)
+    g.step(40)
+    d, flags = g.poll()
+    g.step(40)
+    d, flags = g.poll()
+    for m, dk in zip(ms, d):
+        g.remove(m)
+        ref = m.diagnostics()
+        assert abs(dk["mass"] - ref["mass"]) <= 1e-12 * abs(ref["mass"])
+        assert abs(dk["s_sum"] - ref["s_sum"]) <= 1e-9 * max(1e-12, abs(ref["s_sum"])) + 1e-15
+        assert dk["n_points"] == ref["n_points"]
+        assert (np.isnan(dk["theta_deg"]) and np.isnan(ref["theta_deg"])) or \
+            abs(dk["theta_deg"] - ref["theta_deg"]) < 1e-8
+        assert dk["step"] == ref["step"] == 80

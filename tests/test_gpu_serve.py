@@ -1,0 +1,70 @@
+"""GPU tests of the serving loop and the autotuner."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests():
+    rng = np.random.default_rng(21)
+    reqs = []
+    t = 0.0
+    for k in range(6):
+        t += float(rng.exponential(0.02))
+        if k % 3 == 2:
+            c = workloads.inclined_droplet_case_3d(n=20, radius=5.0, theta=float(rng.uniform(40, 140)),
+                                                   width=4.0)
+        else:
+            nx = int(rng.integers(4, 9)) * 16
+            c = workloads.flat_droplet_case(nx, nx // 2, 0.25 * nx / 2, float(rng.uniform(40, 140)))
+        c["storage"] = "f32"
+        c["steady_tol"] = 2e-3
+        c["arrival_s"] = t
+        reqs.append(c)
+    return reqs
+
+
+def test_serving_results_equal_alone(P):
+    """Cases that arrive while others run are batched with them, and each served
+    result equals the same case run alone for the same number of steps."""
+    from paper_2312_00369_amd.serve import GpuExecutor, Server
+    reqs = _requests()
+    ex = GpuExecutor(keep_fields=True)
+    rec, summ = Server(ex, budget_bytes=2 << 30, max_slots=4, chunk_steps=100,
+                       max_steps=1500).run(reqs)
+    assert summ["served"] == len(reqs)
+    for r in rec:
+        c = reqs[r["index"]]
+        a = P.Case.from_case(c, "f32")
+        a.step(r["steps"])
+        assert np.array_equal(a.fields()["phi"], r["fields"]["phi"]), r["index"]
+    # at most four resident at once; someone had to wait for a slot or joined mid-run
+    assert all("admit_s" in r for r in rec)
+
+
+def test_autotune_keeps_state_and_results(P):
+    from paper_2312_00369_amd import autotune
+    c = workloads.flat_droplet_case(200, 90, 20.0, 70.0)
+    a = P.Case.from_case(c, "f32")
+    b = P.Case.from_case(c, "f32")
+    a.step(20)
+    b.step(20)
+    out = autotune.tune_case(a, steps=30)
+    assert 0 <= out["variant"] < len(P.step_variants("D2Q9"))
+    assert a.steps == 20
+    a.step(30)
+    b.step(30)
+    assert np.array_equal(a.fields()["phi"], b.fields()["phi"])
+    g = P.Group()
+    ms = [P.Case.from_case(c, "f32") for _ in range(3)]
+    for m in ms:
+        g.add(m)
+    best = autotune.tune_group(g, steps=20, blocks_per_cu=(0, 2))
+    assert all(m.steps == 0 for m in ms)
+    g.step(30)
+    ref = P.Case.from_case(c, "f32")
+    ref.set_step_kernel(best["variant"])
+    ref.step(30)
+    assert np.array_equal(ms[1].fields()["phi"], ref.fields()["phi"])

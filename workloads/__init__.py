@@ -164,13 +164,14 @@ def config3(seed=3, n_cases=64):
     return out
 
 
-def serving_request(rng, idx):
+def serving_request(rng, idx, nx_range=(256, 1024), n3_range=(64, 192)):
     """One request of the serving workload: 2D (256x128 .. 1024x512) or 3D
     (64^3 .. 192^3), geometry flat / inclined / curved, theta ~ U[30, 150]."""
     th = float(rng.uniform(30.0, 150.0))
     geom = ["flat", "inclined", "curved"][int(rng.integers(0, 3))]
     if rng.uniform() < 0.5:
-        nx = int(rng.integers(0, (1024 - 256) // 32 + 1)) * 32 + 256
+        lo, hi = nx_range
+        nx = int(rng.integers(0, (hi - lo) // 32 + 1)) * 32 + lo
         ny = nx // 2
         R = 0.2 * ny
         if geom == "flat":
@@ -188,7 +189,8 @@ def serving_request(rng, idx):
         else:
             c = cylinder_case(nx, ny, 0.3, th, width=5.0, drop_frac=R / (0.3 * ny))
     else:
-        n = int(rng.integers(0, (192 - 64) // 16 + 1)) * 16 + 64
+        lo, hi = n3_range
+        n = int(rng.integers(0, (hi - lo) // 16 + 1)) * 16 + lo
         R = 0.2 * n
         shape = (n, n, n)
         if geom == "flat":
@@ -209,14 +211,14 @@ def serving_request(rng, idx):
     return c
 
 
-def config4(seed=4, n_requests=200, rate=20.0):
+def config4(seed=4, n_requests=200, rate=20.0, nx_range=(256, 1024), n3_range=(64, 192)):
     """Poisson arrivals (mean `rate` per second) of mixed serving requests."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
     for k in range(n_requests):
         t += float(rng.exponential(1.0 / rate))
-        c = serving_request(rng, k)
+        c = serving_request(rng, k, nx_range, n3_range)
         c["arrival_s"] = t
         out.append(c)
     return out
