@@ -145,9 +145,10 @@ int pflbm_set_tile(pflbm_handle h, int32_t tx, int32_t ty, int32_t tz);
 
 /* Kernel path of pflbm_step.  variant 0-4: the fused one-kernel step with one
  * of five tile shapes; 5-7: the split step (a phi pass, then one kernel for
- * ghosts, mu and collide-stream) with one of three tile shapes; -1: the
- * three-kernel path (phi sum, mu stencil, collide-stream).  Defaults: 1 for
- * D2Q9, 6 for D3Q19.  Every path gives bit-identical results.  Drops any
+ * ghosts, mu and collide-stream) with one of three tile shapes; 8-10 (D3Q19
+ * only): the split step whose second kernel marches along z over 64 x ty x tz
+ * columns; -1: the three-kernel path (phi sum, mu stencil, collide-stream).  Defaults: 1 for
+ * D2Q9, 7 for D3Q19.  Every path gives bit-identical results.  Drops any
  * captured graph. */
 int pflbm_set_step_kernel(pflbm_handle h, int32_t variant);
 

@@ -309,7 +309,7 @@ int create_common(const pflbm_params* prm, const uint8_t* mask, const double* ph
   h->prm = *prm;
   h->dv = dv;
   h->tile = default_tile(dv.D);
-  h->variant = dv.D == 2 ? 1 : 6;
+  h->variant = dv.D == 2 ? 1 : 7;
   h->lay = make_layout(dv, prm->storage, h->tile);
   auto fail = [&](int code) {
     pflbm_destroy(h);
@@ -800,8 +800,9 @@ int pflbm_profile(pflbm_handle h, int64_t nsteps, double* avg_ms, int32_t nkinds
 int pflbm_set_step_kernel(pflbm_handle h, int32_t variant) {
   clear_error();
   if (int rc = check_handle(h)) return rc;
-  if (variant < -1 || variant >= kStepVariants)
-    return set_error(PFLBM_EINVAL, "step kernel variant %d outside [-1, %d)", variant, kStepVariants);
+  if (variant < -1 || variant >= step_variant_count(h->dv.D))
+    return set_error(PFLBM_EINVAL, "step kernel variant %d outside [-1, %d)", variant,
+                     step_variant_count(h->dv.D));
   drop_graph(h);
   h->variant = variant;
   return PFLBM_OK;
@@ -821,12 +822,13 @@ int pflbm_step_variants(int32_t lattice, int32_t* tiles, int32_t capacity) {
   if (lattice != PFLBM_D2Q9 && lattice != PFLBM_D3Q19)
     return set_error(PFLBM_EUNSUPPORTED, "unknown lattice %d", lattice);
   const int D = lattice == PFLBM_D2Q9 ? 2 : 3;
-  for (int v = 0; v < kStepVariants && v < capacity && tiles; ++v) {
+  const int count = step_variant_count(D);
+  for (int v = 0; v < count && v < capacity && tiles; ++v) {
     int t[5];
     step_variant_tile(D, v, t);
     for (int k = 0; k < 5; ++k) tiles[5 * v + k] = t[k];
   }
-  return kStepVariants;
+  return count;
 }
 
 }  // extern "C"

@@ -83,6 +83,23 @@ struct Engine {
     return PFLBM_OK;
   }
 
+  template <int TY, int TZ>
+  static int column_v(pflbm_case_s* h) {
+    if constexpr (L::D == 3) {
+      const Geo& G = h->dv.geo;
+      int rc = phi(h);
+      if (rc) return rc;
+      const unsigned nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY, nbz = (G.PZ + TZ - 1) / TZ;
+      const int c = h->cur;
+      hipLaunchKernelGGL((k_stepC<L, S, TY, TZ>), dim3(nbx * nby * nbz), dim3(64, TY), 0,
+                         h->stream, h->nodes, h->f[c], h->g[c], h->f[1 - c], h->g[1 - c],
+                         static_cast<C*>(h->s), static_cast<const C*>(h->phi), G, h->dv.phys);
+      PFLBM_HIP(hipGetLastError());
+      return PFLBM_OK;
+    }
+    return set_error(PFLBM_EINVAL, "z-marching variants are for D3Q19");
+  }
+
   static int step_fused(pflbm_case_s* h) {
     if (L::D == 2) {
       switch (h->variant) {
@@ -106,6 +123,9 @@ struct Engine {
         case 5: return split_v<4, 4>(h);
         case 6: return split_v<2, 2>(h);
         case 7: return split_v<4, 2>(h);
+        case 8: return column_v<4, 16>(h);
+        case 9: return column_v<8, 16>(h);
+        case 10: return column_v<8, 32>(h);
         default: break;
       }
     }
@@ -165,6 +185,28 @@ struct GroupEngine {
     PFLBM_HIP(hipGetLastError());
     return PFLBM_OK;
   }
+  template <int TY, int TZ>
+  static int launch_column(const GroupLaunch& gl, int parity) {
+    if constexpr (L::D == 3) {
+      hipLaunchKernelGGL((k_phi_group_all<L, S>), dim3(gl.grid), dim3(256), 0, gl.stream,
+                         gl.table, gl.ntiles, gl.cases, parity, TY, TZ);
+      PFLBM_HIP(hipGetLastError());
+      hipLaunchKernelGGL((k_stepC_group<L, S, TY, TZ>), dim3(gl.grid), dim3(64, TY), 0, gl.stream,
+                         gl.table, gl.ntiles, gl.cases, parity);
+      PFLBM_HIP(hipGetLastError());
+      return PFLBM_OK;
+    }
+    return set_error(PFLBM_EINVAL, "z-marching variants are for D3Q19");
+  }
+  template <int TY, int TZ>
+  static int occupancy_column(int* blocks) {
+    if constexpr (L::D == 3) {
+      PFLBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          blocks, reinterpret_cast<const void*>(&k_stepC_group<L, S, TY, TZ>), 64 * TY, 0));
+      return PFLBM_OK;
+    }
+    return set_error(PFLBM_EINVAL, "z-marching variants are for D3Q19");
+  }
   template <int BY, int BZ>
   static int occupancy_split(int* blocks) {
     constexpr int bz = (L::D == 3) ? BZ : 1;
@@ -175,6 +217,8 @@ struct GroupEngine {
   static int go(const GroupLaunch& gl, int parity, int* occ) {
 #define PFLBM_SPLIT(V, BY, BZ) \
   case V: return occ ? occupancy_split<BY, BZ>(occ) : launch_split<BY, BZ>(gl, parity);
+#define PFLBM_COLUMN(V, TY, TZ) \
+  case V: return occ ? occupancy_column<TY, TZ>(occ) : launch_column<TY, TZ>(gl, parity);
 #define PFLBM_VARIANT(V, BY, BZ, KY, KZ) \
   case V: return occ ? occupancy<BY, BZ, KY, KZ>(occ) : launch<BY, BZ, KY, KZ>(gl, parity);
     if (L::D == 2) {
@@ -199,11 +243,15 @@ struct GroupEngine {
         PFLBM_SPLIT(5, 4, 4)
         PFLBM_SPLIT(6, 2, 2)
         PFLBM_SPLIT(7, 4, 2)
+        PFLBM_COLUMN(8, 4, 16)
+        PFLBM_COLUMN(9, 8, 16)
+        PFLBM_COLUMN(10, 8, 32)
         default: break;
       }
     }
 #undef PFLBM_VARIANT
 #undef PFLBM_SPLIT
+#undef PFLBM_COLUMN
     return set_error(PFLBM_EINVAL, "unknown step variant %d", gl.variant);
   }
 };
@@ -292,16 +340,20 @@ int run_step_group(const GroupLaunch& gl, int parity, int* occupancy_blocks) {
   return set_error(PFLBM_EUNSUPPORTED, "unsupported lattice/storage %d/%d", gl.lattice, gl.storage);
 }
 
-// Tile of each fused-step variant: threads (64, by, bz), nodes (64, ty, tz).
+int step_variant_count(int D) { return D == 2 ? 8 : 11; }
+
+// Tile of each step variant: threads (64, by, bz), nodes (64, ty, tz).
 int step_variant_tile(int D, int v, int tile[5]) {
-  // variants 0-4: fused one-kernel step; 5-7: split step (phi pass + collide pass)
-  static const int t2[kStepVariants][5] = {
+  // variants 0-4: fused one-kernel step; 5-7: split step (phi pass + collide
+  // pass); 8-10 (D3Q19 only): split step marching along z
+  static const int t2[8][5] = {
       {4, 1, 64, 4, 1}, {4, 1, 64, 8, 1}, {4, 1, 64, 16, 1}, {8, 1, 64, 16, 1}, {2, 1, 64, 8, 1},
       {4, 1, 64, 4, 1}, {8, 1, 64, 8, 1}, {16, 1, 64, 16, 1}};
-  static const int t3[kStepVariants][5] = {
+  static const int t3[11][5] = {
       {2, 2, 64, 2, 2}, {2, 2, 64, 4, 2}, {2, 2, 64, 4, 4}, {4, 4, 64, 4, 4}, {4, 2, 64, 4, 4},
-      {4, 4, 64, 4, 4}, {2, 2, 64, 2, 2}, {4, 2, 64, 4, 2}};
-  if (v < 0 || v >= kStepVariants) return -1;
+      {4, 4, 64, 4, 4}, {2, 2, 64, 2, 2}, {4, 2, 64, 4, 2},
+      {4, 1, 64, 4, 16}, {8, 1, 64, 8, 16}, {8, 1, 64, 8, 32}};
+  if (v < 0 || v >= step_variant_count(D)) return -1;
   for (int k = 0; k < 5; ++k) tile[k] = D == 2 ? t2[v][k] : t3[v][k];
   return 0;
 }

@@ -48,7 +48,7 @@ struct pflbm_group_s {
 
 namespace {
 
-int default_variant(int D) { return D == 2 ? 1 : 6; }
+int default_variant(int D) { return D == 2 ? 1 : 7; }
 
 void drop_graph(pflbm_group_s* g) {
   if (g->gexec) {
@@ -91,6 +91,8 @@ int rebuild(pflbm_group_s* g) {
   sync_members(g);
   g->since_build = 0;
   if (g->variant < 0 && g->D) g->variant = default_variant(g->D);
+  if (g->D && g->variant >= step_variant_count(g->D))
+    return set_error(PFLBM_EINVAL, "step variant %d does not exist for this lattice", g->variant);
   std::vector<TileEntry> table;
   std::vector<CaseDesc> cases(g->members.size());
   for (size_t k = 0; k < g->members.size(); ++k) {

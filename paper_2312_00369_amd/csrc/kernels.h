@@ -763,7 +763,12 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_stepB(
   __shared__ uint32_t sw[NL];
   const int TZ = D3 ? BZ : 1;
   const int nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY;
-  const int b = blockIdx.x;
+  const int nb = gridDim.x;
+  int b = blockIdx.x;
+  if (P.xcd_order) {
+    const int per = nb / 8, rem = nb % 8, xcd = b % 8, k = b / 8;
+    b = (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+  }
   stepB_tile<L, S, BY, BZ>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ, nodes,
                            fsrc, gsrc, fdst, gdst, sprev, phi, G, P, sphi, sw);
 }
@@ -786,6 +791,179 @@ __device__ inline void phi_tile(int x0, int y0, int z0, const uint32_t* __restri
 #pragma unroll
   for (int i = 1; i < L::Q; ++i) small += pull<L, GS>(gsrc, i, n, nb, w, G.NQ, P.scale_g);
   phi[n] = C(GS::load_rest(gsrc, n) + (double)small);
+}
+
+// ------------------------------------------------------------------ z-marching split step (3D)
+// Second pass of the split step for D3Q19, marching along z.  A workgroup of
+// (64, TY) threads owns a column of 64 x TY x TZ nodes and walks it one z
+// plane at a time.  LDS holds a ring of five phi / node-word planes (z-2 ..
+// z+2, each 68 x (TY+4) with a two-node halo in x and y): a new plane is loaded
+// per step, ghost means are filled one plane ahead, and the plane z is
+// collided.  Rows shared by consecutive planes of the pulls come from cache,
+// so neighbouring tiles along z no longer refetch them.
+template <class L, int S, int TY, int TZ>
+struct ColumnTile {
+  static constexpr int LX = 68, LY = TY + 4, PLANE = LX * LY, NL = 5 * PLANE;
+};
+
+template <class L, int S, int TY, int TZ>
+__device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __restrict__ nodes,
+                                  const void* __restrict__ fsrc, const void* __restrict__ gsrc,
+                                  void* __restrict__ fdst, void* __restrict__ gdst,
+                                  ComputeT<S>* __restrict__ sprev,
+                                  const ComputeT<S>* __restrict__ phi, const Geo& G,
+                                  const Phys& P, ComputeT<S>* sphi, uint32_t* sw) {
+  static_assert(L::D == 3, "z marching is for D3Q19");
+  using C = ComputeT<S>;
+  using GS = Set<S, true>;
+  using FS = Set<S, false>;
+  constexpr int Q = L::Q;
+  constexpr int LX = 68, LY = TY + 4, PL = LX * LY;
+  constexpr int NT = 64 * TY;
+  const int lane = threadIdx.x, ty = threadIdx.y;
+  const int tid = lane + 64 * ty;
+  const int P3[3] = {G.PX, G.PY, G.PZ};
+  // ring slot of plane z (z >= z0 - 2)
+  auto slot = [&](int z) { return (z - z0 + 2) % 5; };
+  auto load_plane = [&](int z) {
+    C* fp = sphi + slot(z) * PL;
+    uint32_t* wp = sw + slot(z) * PL;
+    int qz = z;
+    bool zok = true;
+    if (G.per[2]) {
+      qz %= P3[2];
+      if (qz < 0) qz += P3[2];
+    } else if (qz < 0 || qz >= P3[2]) {
+      zok = false;
+    }
+    for (int m = tid; m < PL; m += NT) {
+      const int lx = m % LX, ly = m / LX;
+      int q[2] = {x0 - 2 + lx, y0 - 2 + ly};
+      bool ok = zok;
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        if (G.per[d]) {
+          q[d] %= P3[d];
+          if (q[d] < 0) q[d] += P3[d];
+        } else if (q[d] < 0 || q[d] >= P3[d]) {
+          ok = false;
+        }
+      }
+      uint32_t w = 0;
+      C v = C(0);
+      if (ok) {
+        const nidx n = G.idx(q[0], q[1], qz);
+        w = nodes[n];
+        if (w & kZeta) v = phi[n];
+      }
+      wp[m] = w;
+      fp[m] = v;
+    }
+  };
+  // ghost means of plane z over the tile and its first halo layer in x, y.
+  // ghost_mean walks the 3x3x3 block with strides (1, LX, PL): planes z-1, z,
+  // z+1 must sit in consecutive slots, which the ring does not guarantee, so the
+  // block is gathered explicitly here.
+  auto fill_ghosts = [&](int z) {
+    const int sm = slot(z - 1) * PL, s0 = slot(z) * PL, sp = slot(z + 1) * PL;
+    for (int m = tid; m < 66 * (TY + 2); m += NT) {
+      const int lx = 1 + m % 66, ly = 1 + m / 66;
+      const int t = lx + LX * ly;
+      if (!(sw[s0 + t] & kGhost)) continue;
+      C num = C(0);
+      int den = 0;
+      const int base[3] = {sm, s0, sp};
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int t2 = base[dz] + t + dx + LX * dy;
+            if (sw[t2] & kZeta) {
+              num += sphi[t2];
+              ++den;
+            }
+          }
+      if (den > 0) sphi[s0 + t] = num / C(den);
+    }
+  };
+  for (int z = z0 - 2; z <= z0 + 1; ++z) load_plane(z);
+  __syncthreads();
+  fill_ghosts(z0 - 1);
+  fill_ghosts(z0);
+  __syncthreads();
+  for (int z = z0; z < z0 + TZ; ++z) {
+    load_plane(z + 2);
+    __syncthreads();
+    fill_ghosts(z + 1);
+    __syncthreads();
+    const int x = x0 + lane, y = y0 + ty;
+    if (x < G.PX && y < G.PY && z < G.PZ) {
+      const int t = (2 + lane) + LX * (2 + ty);
+      const int s0 = slot(z) * PL, sm = slot(z - 1) * PL, sp = slot(z + 1) * PL;
+      const uint32_t w = sw[s0 + t];
+      if (w & kZeta) {
+        const nidx n = G.idx(x, y, z);
+        nidx nb[Q];
+        neighbours<L>(G, x, y, z, nb);
+        C f[Q], g[Q];
+        f[0] = C(FS::load_rest(fsrc, n));
+        const double g0 = GS::load_rest(gsrc, n);
+        g[0] = C(0);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          f[i] = pull<L, FS>(fsrc, i, n, nb, w, G.NQ, P.scale_f);
+          g[i] = pull<L, GS>(gsrc, i, n, nb, w, G.NQ, P.scale_g);
+        }
+        // neighbour entry for lattice direction i
+        auto at = [&](int i) {
+          const int sl = L::cz(i) < 0 ? sm : (L::cz(i) > 0 ? sp : s0);
+          return sl + t + L::cx(i) + LX * L::cy(i);
+        };
+        // mu (same arithmetic as mu_at) and grad phi
+        const C ph = sphi[s0 + t];
+        C lap = C(0), ex = C(0), ey = C(0), ez = C(0);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          const int t2 = at(i);
+          const C wi = C(L::w(i));
+          lap += C(2) * wi * (sphi[t2] - ph);
+          const C e = (sw[t2] & kFluid) ? C(1) : C(0);
+          ex += wi * C(L::cx(i)) * e;
+          ey += wi * C(L::cy(i)) * e;
+          ez += wi * C(L::cz(i)) * e;
+        }
+        const C inv_cs2 = C(3);
+        lap *= inv_cs2;
+        ex *= inv_cs2;
+        ey *= inv_cs2;
+        ez *= inv_cs2;
+        const C av = sqrt(ex * ex + ey * ey + ez * ez);
+        const C m = C(4) * C(P.beta) * ph * (ph - C(1)) * (ph - C(0.5)) - C(P.kappa) * lap -
+                    av * C(P.wet) * (ph - ph * ph);
+        C gx, gy, gz;
+        grad_of<L, C>([&](int i) { return sphi[at(i)]; }, gx, gy, gz);
+        node_update<L, S, 0>(f, g0, g, ph, m, gx, gy, gz, n, fdst, gdst, sprev, nullptr,
+                             nullptr, G, P, P.nt_store);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <class L, int S, int TY, int TZ>
+__global__ __launch_bounds__(64 * TY) void k_stepC(
+    const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
+    const void* __restrict__ gsrc, void* __restrict__ fdst, void* __restrict__ gdst,
+    ComputeT<S>* __restrict__ sprev, const ComputeT<S>* __restrict__ phi, Geo G, Phys P) {
+  using T = ColumnTile<L, S, TY, TZ>;
+  __shared__ ComputeT<S> sphi[T::NL];
+  __shared__ uint32_t sw[T::NL];
+  const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY;
+  const int b = blockIdx.x;
+  stepC_tile<L, S, TY, TZ>((b % nbx) * 64, ((b / nbx) % nby) * TY, (b / (nbx * nby)) * TZ, nodes,
+                           fsrc, gsrc, fdst, gdst, sprev, phi, G, P, sphi, sw);
 }
 
 // ------------------------------------------------------------------ batched step
@@ -881,6 +1059,29 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_stepB_group(
     const int nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY;
     const int b = te.tile;
     stepB_tile<L, S, BY, BZ>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ,
+                             cd.nodes, cd.f[c], cd.g[c], cd.f[1 - c], cd.g[1 - c],
+                             static_cast<ComputeT<S>*>(cd.s),
+                             static_cast<const ComputeT<S>*>(cd.phi), G, cd.P, sphi, sw);
+    __syncthreads();
+  }
+}
+
+template <class L, int S, int TY, int TZ>
+__global__ __launch_bounds__(64 * TY) void k_stepC_group(
+    const TileEntry* __restrict__ table, const int* __restrict__ ntiles,
+    const CaseDesc* __restrict__ cases, int parity) {
+  using T = ColumnTile<L, S, TY, TZ>;
+  __shared__ ComputeT<S> sphi[T::NL];
+  __shared__ uint32_t sw[T::NL];
+  const int n = *ntiles;
+  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+    const TileEntry te = table[e];
+    const CaseDesc& cd = cases[te.case_id];
+    const Geo G = cd.G;
+    const int c = cd.cur0 ^ parity;
+    const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY;
+    const int b = te.tile;
+    stepC_tile<L, S, TY, TZ>((b % nbx) * 64, ((b / nbx) % nby) * TY, (b / (nbx * nby)) * TZ,
                              cd.nodes, cd.f[c], cd.g[c], cd.f[1 - c], cd.g[1 - c],
                              static_cast<ComputeT<S>*>(cd.s),
                              static_cast<const ComputeT<S>*>(cd.phi), G, cd.P, sphi, sw);
