@@ -44,6 +44,9 @@ def parse():
                     help="also run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 D3Q19 section")
+    ap.add_argument("--steps-3d", type=int, default=400)
+    ap.add_argument("--err-steps-3d", type=int, default=2000)
     ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-tol", type=float, default=1e-4)
@@ -91,6 +94,36 @@ def measured_traffic(name, nodes):
     fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"]) * 1024
     write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"]) * 1024
     return fetch + write, f"{(fetch + write) / nodes:.1f} B/node ({fetch / nodes:.1f} read, {write / nodes:.1f} write)"
+
+
+def inclined_3d(a, torch, P, workloads, stream):
+    """configs[2]: 256^3 D3Q19, 30-degree staircase wall, sphere R = 40, theta = 45;
+    FP32 against FP16-deviation storage (MLUPS, roofline at 313 / 165 B per node,
+    and the FP16 field error against FP32 after the same steps)."""
+    out = {}
+    fields = {}
+    for st, alg in (("f32", 313), ("f16dev", 165)):
+        c = workloads.config2(storage=st, n=256)
+        h = P.Case.from_case(c, st, stream=stream)
+        h.set_graph_chunk(20)
+        nodes = int((h.classes() & 1).sum())
+        ms = time_steps(torch, h, a.steps_3d, 20)
+        h.step(a.err_steps_3d - a.steps_3d - 20)
+        f = h.fields()
+        d = h.diagnostics()
+        fields[st] = f["phi"]
+        mlups = nodes * 1e3 / ms * a.steps_3d / 1e6
+        out[st] = {"MLUPS": round(mlups, 1), "ms_per_step": round(ms / a.steps_3d, 4),
+                   "hbm_roofline_pct": round(100 * mlups * 1e6 * alg / (HBM_PEAK_GBS * 1e9), 2),
+                   "alg_bytes_per_node": alg, "theta_deg": round(d["theta_deg"], 3),
+                   "mass": d["mass"]}
+        zeta = (h.classes() & 1).astype(bool)
+        h.close()
+    out["f16dev_vs_f32_max_abs_dphi"] = float(np.abs(fields["f16dev"] - fields["f32"])[zeta].max())
+    out["f16dev_vs_f32_rel_mass"] = abs(out["f16dev"]["mass"] - out["f32"]["mass"]) / out["f32"]["mass"]
+    out["workload"] = (f"D3Q19 256^3, inclined 30-deg staircase, sphere R=40, theta=45, W=5; "
+                       f"{nodes} fluid+boundary nodes; error after {a.err_steps_3d} steps")
+    return out
 
 
 def batched(a, torch, P, workloads, stream):
@@ -290,6 +323,8 @@ def run(a, torch, P, workloads, stream):
                              "k_step_ms": round(float(kb[3]), 4),
                              "k_step_GBps_alg": round(alg * nb / (float(kb[3]) / 1e3) / 1e9, 1)}
         cb.close()
+    if not a.no_3d:
+        line["inclined_3d"] = inclined_3d(a, torch, P, workloads, stream)
     if not a.no_batched:
         line["batched"] = batched(a, torch, P, workloads, stream)
     if a.copy_calibration:

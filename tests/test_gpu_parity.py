@@ -246,3 +246,39 @@ def test_fused_narrow_periodic_and_ragged(P):
         a.step(20)
         b.step(20)
         assert np.array_equal(a.fields()["phi"], b.fields()["phi"])
+
+
+def test_parity_d3q19_fp32_and_fp16dev_vs_oracle(P):
+    """D3Q19 inclined staircase, 300 steps: FP32 within 1e-5 of the FP64 oracle;
+    FP16-deviation storage (FP16 moving populations, FP32 compute) within 2e-4,
+    with its error printed."""
+    c = workloads.inclined_droplet_case_3d(n=24, radius=7.0, theta=60.0, width=4.0)
+    o = oracle_for(c)
+    o.step(300)
+    of = o.fields()
+    errs = {}
+    for st in ("f32", "f16dev"):
+        g = P.Case.from_case(c, st)
+        g.step(300)
+        zeta = _zeta(g)
+        errs[st] = maxdiff(g.fields()["phi"], of["phi"], zeta)
+    print(f"D3Q19 300 steps |dphi|_inf vs FP64 oracle: FP32 {errs['f32']:.2e}, "
+          f"FP16-dev {errs['f16dev']:.2e}")
+    assert errs["f32"] <= 1e-5
+    assert errs["f16dev"] <= 2e-4
+
+
+def test_fp16dev_config0_error_statement(P):
+    """configs[0] geometry in FP16-deviation storage, 5000 steps, against the
+    stored FP64 oracle run: error stated and bounded."""
+    gold = np.load(os.path.join(GOLDEN, "config0_fp64.npz"), allow_pickle=False)
+    c = workloads.config0()
+    g = P.Case.from_case(c, "f16dev")
+    zeta = _zeta(g)
+    g.step(int(gold["steps"]))
+    err = maxdiff(g.fields()["phi"], gold["phi"], zeta)
+    d = g.diagnostics()
+    print(f"FP16-dev |dphi|_inf after 5000 steps: {err:.3e}; theta {d['theta_deg']:.4f} "
+          f"vs {float(gold['theta']):.4f}")
+    assert err <= 1e-4
+    assert abs(d["theta_deg"] - float(gold["theta"])) <= 0.5

@@ -356,6 +356,10 @@ def test_equilibrium_cap_is_kept_and_approached():
     th_move = odiag.contact_angle(move.fields()["phi"], zk, wall, W)[0]
     assert abs(th_keep - 120.0) < 1.5, th_keep
     assert th_move > 95.0, th_move          # moved about a third of the way in 2500 steps
+    # cap shape: the kept cap keeps the equal-area radius of the 15-node semicircle
+    r_keep = odiag.contact_angle(keep.fields()["phi"], zk, wall, W)[2]
+    r_eq = odiag.cap_radius_2d(15.0, 120.0)
+    assert abs(r_keep - r_eq) < 0.02 * r_eq, (r_keep, r_eq)
 
 
 def test_contact_angle_ninety_keeps_semicircle():
