@@ -38,15 +38,16 @@ def parse():
     ap.add_argument("--chunk", type=int, default=100, help="steps per captured HIP graph")
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--variant", type=int, default=1, help="fused step tile variant")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the DRAM-bound twin")
+    ap.add_argument("--sections", default="main,twin,3d,batched,serve,cpu",
+                    help="comma list of: main (the 1024x512 line), twin (8192x4096), 3d "
+                         "(256^3 D3Q19), batched (64 cases), serve (Poisson serving), cpu "
+                         "(oracle baseline); the JSON line always carries the main figures")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
-    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
-    ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 D3Q19 section")
     ap.add_argument("--steps-3d", type=int, default=400)
     ap.add_argument("--err-steps-3d", type=int, default=2000)
+    ap.add_argument("--chunk-3d", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-tol", type=float, default=1e-4)
@@ -54,7 +55,9 @@ def parse():
     ap.add_argument("--serve-max-steps", type=int, default=20000)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--batch-steps", type=int, default=1000)
-    return ap.parse_args()
+    a = ap.parse_args()
+    a.sec = set(s.strip() for s in a.sections.split(",") if s.strip())
+    return a
 
 
 def time_steps(torch, case, steps, warmup):
@@ -105,7 +108,7 @@ def inclined_3d(a, torch, P, workloads, stream):
     for st, alg in (("f32", 313), ("f16dev", 165)):
         c = workloads.config2(storage=st, n=256)
         h = P.Case.from_case(c, st, stream=stream)
-        h.set_graph_chunk(20)
+        h.set_graph_chunk(a.chunk_3d)
         nodes = int((h.classes() & 1).sum())
         ms = time_steps(torch, h, a.steps_3d, 20)
         h.step(a.err_steps_3d - a.steps_3d - 20)
@@ -252,10 +255,10 @@ def main():
     stream = torch.cuda.Stream()          # default priority; the library launches on it
     with torch.cuda.stream(stream):
         line = run(a, torch, P, workloads, stream)
-    if not a.no_serve:
+    if "serve" in a.sec:
         with torch.cuda.stream(stream):
             line["served"] = served(a, torch, P, workloads)
-    if not a.no_cpu:
+    if "cpu" in a.sec:
         line["cpu_baseline"] = cpu_baseline(workloads.config1(theta=a.theta))
     print(json.dumps(line), flush=True)
 
@@ -307,7 +310,7 @@ def run(a, torch, P, workloads, stream):
                   "nonfinite": d["nonfinite"]},
     }
     case.close()
-    if not a.no_extra:
+    if "twin" in a.sec:
         # DRAM-bound twin: 8192 x 4096 (33.5 M nodes), same physics
         big = workloads.config1(theta=a.theta, nx=8192, ny=4096)
         cb = P.Case.from_case(big, "f32", stream=stream)
@@ -323,9 +326,9 @@ def run(a, torch, P, workloads, stream):
                              "k_step_ms": round(float(kb[3]), 4),
                              "k_step_GBps_alg": round(alg * nb / (float(kb[3]) / 1e3) / 1e9, 1)}
         cb.close()
-    if not a.no_3d:
+    if "3d" in a.sec:
         line["inclined_3d"] = inclined_3d(a, torch, P, workloads, stream)
-    if not a.no_batched:
+    if "batched" in a.sec:
         line["batched"] = batched(a, torch, P, workloads, stream)
     if a.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
