@@ -208,7 +208,9 @@ void pflbm_destroy(pflbm_handle h);
  * member is refused (PFLBM_ESTATE) while fields, diagnostics and state calls
  * on it stay valid.  hip_stream is borrowed (NULL: the group makes its own). */
 int pflbm_group_create(void* hip_stream, pflbm_group* out);
-/* Add a case (same lattice and storage as the other members, else EINVAL). */
+/* Add a case (same lattice and storage as the other members, else EINVAL; a
+ * case whose f or g buffer reaches 4 GiB is refused with EUNSUPPORTED, since
+ * the batched kernels address populations with 32-bit offsets). */
 int pflbm_group_add(pflbm_group g, pflbm_handle h);
 /* Remove a member (ESTATE if h is not a member). */
 int pflbm_group_remove(pflbm_group g, pflbm_handle h);

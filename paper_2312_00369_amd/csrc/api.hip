@@ -71,7 +71,7 @@ int validate_and_derive(const pflbm_params* p, Derived* d) {
   G.PX = P[0];
   G.PY = P[1];
   G.PZ = P[2];
-  G.SX = (int)round_up((size_t)P[0], 32);
+  G.SX = (int)round_up((size_t)P[0], kBlk);   // rows start on a population block
   d->N = (long long)G.SX * G.PY * G.PZ;
   if (d->N >= (1LL << 31))
     return set_error(PFLBM_EUNSUPPORTED, "padded grid of %lld nodes exceeds 2^31", d->N);
@@ -128,16 +128,21 @@ Layout make_layout(const Derived& d, int storage, dim3 tile) {
   const size_t NQ = (size_t)d.geo.NQ;
   const size_t cb = storage == PFLBM_FP64 ? 8 : 4;
   L.c_bytes = NQ * cb;
-  if (storage == PFLBM_FP64) {
-    L.f_bytes = Set<kF64, false>::bytes(NQ, d.Q);
-    L.g_bytes = Set<kF64, true>::bytes(NQ, d.Q);
-  } else if (storage == PFLBM_FP32) {
-    L.f_bytes = Set<kF32, false>::bytes(NQ, d.Q);
-    L.g_bytes = Set<kF32, true>::bytes(NQ, d.Q);
-  } else {
-    L.f_bytes = Set<kF16Dev, false>::bytes(NQ, d.Q);
-    L.g_bytes = Set<kF16Dev, true>::bytes(NQ, d.Q);
-  }
+  auto sizes = [&](auto q) {
+    constexpr int Q = decltype(q)::value;
+    if (storage == PFLBM_FP64) {
+      L.f_bytes = Set<kF64, false, Q>::bytes(NQ);
+      L.g_bytes = Set<kF64, true, Q>::bytes(NQ);
+    } else if (storage == PFLBM_FP32) {
+      L.f_bytes = Set<kF32, false, Q>::bytes(NQ);
+      L.g_bytes = Set<kF32, true, Q>::bytes(NQ);
+    } else {
+      L.f_bytes = Set<kF16Dev, false, Q>::bytes(NQ);
+      L.g_bytes = Set<kF16Dev, true, Q>::bytes(NQ);
+    }
+  };
+  if (d.Q == 9) sizes(std::integral_constant<int, 9>());
+  else sizes(std::integral_constant<int, 19>());
   const Geo& G = d.geo;
   L.nparts = (long long)((G.PX + tile.x - 1) / tile.x) * ((G.PY + tile.y - 1) / tile.y) *
              ((G.PZ + tile.z - 1) / tile.z);
@@ -311,6 +316,7 @@ int create_common(const pflbm_params* prm, const uint8_t* mask, const double* ph
   h->tile = default_tile(dv.D);
   h->variant = dv.D == 2 ? 1 : 7;
   h->lay = make_layout(dv, prm->storage, h->tile);
+  h->o32 = h->lay.f_bytes < (1ull << 32) && h->lay.g_bytes < (1ull << 32);
   auto fail = [&](int code) {
     pflbm_destroy(h);
     return code;

@@ -39,7 +39,7 @@ struct Derived {
   Geo geo;
   Phys phys;
   Wall wall;
-  long long N;        // SX * PY * PZ
+  long long N;        // SX * PY * PZ node slots
 };
 
 int validate_and_derive(const pflbm_params* prm, Derived* d);
@@ -78,6 +78,7 @@ struct pflbm_case_s {
   dim3 tile;
   int graph_chunk = 64;
   int variant = 1;                // fused step kernel variant; -1 = three-kernel path
+  bool o32 = false;               // f and g buffers below 4 GiB: 32-bit population offsets
   hipGraphExec_t gexec = nullptr;
   int gexec_steps = 0;
   pflbm_group_s* group = nullptr;
@@ -110,7 +111,7 @@ int run_step_group(const GroupLaunch& gl, int parity, int* occupancy_blocks);
 void group_member_changed(pflbm_case_s* h);
 // Batched phi + diagnostics reductions over a group's table: out[k * kRecN ..]
 // receives member k's record.
-int run_group_diag(const GroupLaunch& gl, int parity, int ty, int tz, double* partial,
+int run_group_diag(const GroupLaunch& gl, int parity, int tx, int ty, int tz, double* partial,
                    double* out, int ncases, int update_snap);
 // Contact-angle fit and flags from a reduction record.
 void finish_diag(const pflbm_case_s* h, const double* rec, pflbm_diag* d);

@@ -15,8 +15,12 @@ struct Engine {
 
   static int phi(pflbm_case_s* h) {
     const Geo& G = h->dv.geo;
-    hipLaunchKernelGGL((k_phi<L, S>), grid_of(G, h->tile), h->tile, 0, h->stream, h->nodes,
-                       h->g[h->cur], static_cast<C*>(h->phi), G, h->dv.phys);
+    if (h->o32)
+      hipLaunchKernelGGL((k_phi<L, S, true>), grid_of(G, h->tile), h->tile, 0, h->stream, h->nodes,
+                         h->g[h->cur], static_cast<C*>(h->phi), G, h->dv.phys);
+    else
+      hipLaunchKernelGGL((k_phi<L, S, false>), grid_of(G, h->tile), h->tile, 0, h->stream,
+                         h->nodes, h->g[h->cur], static_cast<C*>(h->phi), G, h->dv.phys);
     PFLBM_HIP(hipGetLastError());
     return PFLBM_OK;
   }
@@ -61,9 +65,13 @@ struct Engine {
     const dim3 grid(nbx * nby * nbz, 1, 1);
     const dim3 block(64, BY, (L::D == 3) ? BZ : 1);
     const int c = h->cur;
-    hipLaunchKernelGGL((k_step<L, S, BY, (L::D == 3) ? BZ : 1, KY, (L::D == 3) ? KZ : 1>), grid,
-                       block, 0, h->stream, h->nodes, h->f[c], h->g[c], h->f[1 - c], h->g[1 - c],
-                       static_cast<C*>(h->s), G, h->dv.phys);
+    constexpr int bz = (L::D == 3) ? BZ : 1, kz = (L::D == 3) ? KZ : 1;
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, grid, block, 0, h->stream, h->nodes, h->f[c], h->g[c], h->f[1 - c],
+                         h->g[1 - c], static_cast<C*>(h->s), G, h->dv.phys);
+    };
+    if (h->o32) go(k_step<L, S, BY, bz, KY, kz, true>);
+    else go(k_step<L, S, BY, bz, KY, kz, false>);
     PFLBM_HIP(hipGetLastError());
     return PFLBM_OK;
   }
@@ -76,9 +84,13 @@ struct Engine {
     constexpr int bz = (L::D == 3) ? BZ : 1;
     const unsigned nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY, nbz = (G.PZ + bz - 1) / bz;
     const int c = h->cur;
-    hipLaunchKernelGGL((k_stepB<L, S, BY, bz>), dim3(nbx * nby * nbz), dim3(64, BY, bz), 0,
-                       h->stream, h->nodes, h->f[c], h->g[c], h->f[1 - c], h->g[1 - c],
-                       static_cast<C*>(h->s), static_cast<const C*>(h->phi), G, h->dv.phys);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(nbx * nby * nbz), dim3(64, BY, bz), 0, h->stream, h->nodes,
+                         h->f[c], h->g[c], h->f[1 - c], h->g[1 - c], static_cast<C*>(h->s),
+                         static_cast<const C*>(h->phi), G, h->dv.phys);
+    };
+    if (h->o32) go(k_stepB<L, S, BY, bz, true>);
+    else go(k_stepB<L, S, BY, bz, false>);
     PFLBM_HIP(hipGetLastError());
     return PFLBM_OK;
   }
@@ -91,9 +103,13 @@ struct Engine {
       if (rc) return rc;
       const unsigned nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY, nbz = (G.PZ + TZ - 1) / TZ;
       const int c = h->cur;
-      hipLaunchKernelGGL((k_stepC<L, S, TY, TZ>), dim3(nbx * nby * nbz), dim3(64, TY), 0,
-                         h->stream, h->nodes, h->f[c], h->g[c], h->f[1 - c], h->g[1 - c],
-                         static_cast<C*>(h->s), static_cast<const C*>(h->phi), G, h->dv.phys);
+      auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(nbx * nby * nbz), dim3(64, TY), 0, h->stream, h->nodes,
+                           h->f[c], h->g[c], h->f[1 - c], h->g[1 - c], static_cast<C*>(h->s),
+                           static_cast<const C*>(h->phi), G, h->dv.phys);
+      };
+      if (h->o32) go(k_stepC<L, S, TY, TZ, true>);
+      else go(k_stepC<L, S, TY, TZ, false>);
       PFLBM_HIP(hipGetLastError());
       return PFLBM_OK;
     }
@@ -189,7 +205,7 @@ struct GroupEngine {
   static int launch_column(const GroupLaunch& gl, int parity) {
     if constexpr (L::D == 3) {
       hipLaunchKernelGGL((k_phi_group_all<L, S>), dim3(gl.grid), dim3(256), 0, gl.stream,
-                         gl.table, gl.ntiles, gl.cases, parity, TY, TZ);
+                         gl.table, gl.ntiles, gl.cases, parity, 64, TY, TZ);
       PFLBM_HIP(hipGetLastError());
       hipLaunchKernelGGL((k_stepC_group<L, S, TY, TZ>), dim3(gl.grid), dim3(64, TY), 0, gl.stream,
                          gl.table, gl.ntiles, gl.cases, parity);
@@ -294,14 +310,14 @@ int run_step_fused(pflbm_case_s* h) { return dispatch<DoStep>(h); }
 
 namespace {
 template <class L, int S>
-int group_diag_t(const GroupLaunch& gl, int parity, int ty, int tz, double* partial, double* out,
-                 int ncases, int update_snap) {
+int group_diag_t(const GroupLaunch& gl, int parity, int tx, int ty, int tz, double* partial,
+                 double* out, int ncases, int update_snap) {
   using C = ComputeT<S>;
   hipLaunchKernelGGL((k_phi_group_all<L, S>), dim3(gl.grid), dim3(256), 0, gl.stream, gl.table,
-                     gl.ntiles, gl.cases, parity, ty, tz);
+                     gl.ntiles, gl.cases, parity, tx, ty, tz);
   PFLBM_HIP(hipGetLastError());
   hipLaunchKernelGGL((k_reduce_group<L, C>), dim3(gl.grid), dim3(256), 0, gl.stream, gl.table,
-                     gl.ntiles, gl.cases, partial, ty, tz, update_snap);
+                     gl.ntiles, gl.cases, partial, tx, ty, tz, update_snap);
   PFLBM_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_reduce_final_group<kRecN>, dim3(ncases), dim3(256), 0, gl.stream, partial,
                      gl.cases, out);
@@ -310,10 +326,11 @@ int group_diag_t(const GroupLaunch& gl, int parity, int ty, int tz, double* part
 }
 }  // namespace
 
-int run_group_diag(const GroupLaunch& gl, int parity, int ty, int tz, double* partial,
+int run_group_diag(const GroupLaunch& gl, int parity, int tx, int ty, int tz, double* partial,
                    double* out, int ncases, int update_snap) {
   if (ncases <= 0) return PFLBM_OK;
-#define PFLBM_GD(LT, ST) return group_diag_t<LT, ST>(gl, parity, ty, tz, partial, out, ncases, update_snap)
+#define PFLBM_GD(LT, ST) \
+  return group_diag_t<LT, ST>(gl, parity, tx, ty, tz, partial, out, ncases, update_snap)
   if (gl.lattice == PFLBM_D2Q9) {
     if (gl.storage == PFLBM_FP64) PFLBM_GD(D2Q9, kF64);
     if (gl.storage == PFLBM_FP32) PFLBM_GD(D2Q9, kF32);

@@ -270,6 +270,9 @@ int pflbm_group_add(pflbm_group g, pflbm_handle h) {
   if (h->group) return set_error(PFLBM_ESTATE, "case already belongs to a group");
   if (!g->members.empty() && (h->prm.lattice != g->lattice || h->prm.storage != g->storage))
     return set_error(PFLBM_EINVAL, "group members must share lattice and storage");
+  if (!h->o32)
+    return set_error(PFLBM_EUNSUPPORTED,
+                     "case too large for a group (an f or g buffer of 4 GiB or more)");
   PFLBM_HIP(hipStreamSynchronize(h->stream));
   PFLBM_HIP(hipStreamSynchronize(g->stream));
   sync_members(g);
@@ -363,7 +366,7 @@ int pflbm_group_poll(pflbm_group g, pflbm_diag* d, int32_t* flags, int32_t capac
   int t[5];
   step_variant_tile(g->D, g->variant, t);
   const int nc = (int)g->members.size();
-  if ((rc = run_group_diag(launch_of(g), (int)(g->since_build & 1), t[3], t[4], g->d_partial,
+  if ((rc = run_group_diag(launch_of(g), (int)(g->since_build & 1), t[2], t[3], t[4], g->d_partial,
                            g->d_rec, nc, 1)))
     return rc;
   std::vector<double> rec((size_t)nc * kRecN);

@@ -1,8 +1,8 @@
 // Device kernels of one time step (templated on lattice and storage).
 //
 // State kept between steps: post-collision populations f*, g* (ping-pong
-// buffers, structure of arrays: population i of node n at i*NQ + n) and
-// s = u . grad(phi) of the previous step.  One step is
+// buffers in 64-node blocks, see Set) and s = u . grad(phi) of the previous
+// step (one array).  One step is
 //   k_phi      phi(x) = sum_i g_i(x), with g_i pulled from x - c_i     Eq. (order-parameter)
 //   k_mu       LDS tile with a two-node halo: ghost phi (Sec. 2.2.2), the isotropic
 //              Laplacian (Eq. Laplace), a_v = |grad eps| (Eq. avvv) and
@@ -33,10 +33,10 @@ using nidx = uint32_t;
 
 struct Geo {
   int PX, PY, PZ;    // padded extents: periodic axes as given, others + 2
-  int SX;            // x stride (>= PX); nodes x >= PX are dead
+  int SX;            // x stride (>= PX, a multiple of 64); nodes x >= PX are dead
   int per[3];        // periodic flags
   int pad[3];        // 0 periodic, 1 otherwise: domain x = padded x - pad
-  long long NQ;      // stride between populations (>= SX*PY*PZ)
+  long long NQ;      // node slots (>= SX*PY*PZ, a multiple of 256); stride of u components
   __host__ __device__ nidx idx(int x, int y, int z) const {
     return (nidx)x + (nidx)SX * ((nidx)y + (nidx)PY * (nidx)z);
   }
@@ -59,56 +59,88 @@ __device__ inline void st(T* p, T v, int nt) {
 }
 
 // ------------------------------------------------------------------ storage codec
-// One distribution set (f or g) in one buffer: the rest population (i = 0) in
-// the first NQ slots, then populations 1..Q-1, each NQ slots.  The rest
-// population of g carries phi (g_0 ~ phi - (1 - w_0) alpha mu) and changes by
-// far less than an FP32 ulp of 1 per step in bulk liquid, so it is always
-// stored in FP64; every other population is small and is stored in the case's
-// storage type.  FP16-deviation storage keeps value * scale (a power of two)
-// in FP16: the rest equilibrium of every FP16 population is 0 (f at p = 0,
-// u = 0; g_i, i > 0, at mu = 0), so these are deviations from it.
+// One distribution set (f or g) of Q populations in one buffer, laid out in
+// blocks of kBlk = 64 node slots: block b holds the rest population of nodes
+// 64b .. 64b+63, then population 1 of the same nodes, ..., population Q-1.
+// Rows start on a block boundary (the x stride is a multiple of 64), so the 64
+// nodes of one wavefront read and write one contiguous block per population
+// set; with one array per population the same accesses would land in Q
+// regions far apart, which costs HBM efficiency (DRAM page locality).
+// The rest population of g carries phi (g_0 ~ phi - (1 - w_0) alpha mu) and
+// changes by far less than an FP32 ulp of 1 per step in bulk liquid, so it is
+// always stored in FP64; every other population is small and is stored in the
+// case's storage type.  FP16-deviation storage keeps value * scale (a power
+// of two) in FP16: the rest equilibrium of every FP16 population is 0 (f at
+// p = 0, u = 0; g_i, i > 0, at mu = 0), so these are deviations from it.
 //   storage   f rest / moving      g rest / moving     compute
 //   kF64      f64 / f64            f64 / f64           f64
 //   kF32      f32 / f32            f64 / f32           f32
 //   kF16Dev   f32 / f16*scale      f64 / f16*scale     f32
+constexpr int kBlk = 64;
+
 template <int S> struct ComputeOf { using T = float; };
 template <> struct ComputeOf<kF64> { using T = double; };
 template <int S> using ComputeT = typename ComputeOf<S>::T;
 
-template <int S, bool G>
+// O: byte offsets within the buffer are formed in 32 bits (the buffer is
+// smaller than 4 GiB), which keeps a pulled address in one register.
+template <int S, bool G, int Q, bool O = false>
 struct Set {
   using C = ComputeT<S>;
   using R = typename std::conditional<G || S == kF64, double, float>::type;   // rest
   static constexpr bool kHalf = (S == kF16Dev);
   using M = typename std::conditional<S == kF64, double,
             typename std::conditional<kHalf, __half, float>::type>::type;   // moving
-  __host__ __device__ static size_t bytes(long long NQ, int Q) {
-    return (size_t)NQ * sizeof(R) + (size_t)(Q - 1) * (size_t)NQ * sizeof(M);
+  static constexpr size_t kRestBytes = kBlk * sizeof(R);
+  static constexpr size_t kBlockBytes = kBlk * (sizeof(R) + (Q - 1) * sizeof(M));
+  // buffer bytes for NQ node slots (NQ a multiple of kBlk)
+  __host__ __device__ static size_t bytes(long long NQ) {
+    return (size_t)(NQ / kBlk) * kBlockBytes;
   }
-  __device__ static R load_rest(const void* b, nidx n) { return static_cast<const R*>(b)[n]; }
+  // Loads address with a byte offset from the buffer base: 32-bit when O,
+  // which the compiler keeps in one register per pending load.
+  __device__ static R load_rest(const void* b, nidx n) {
+    const unsigned char* p = static_cast<const unsigned char*>(b);
+    if constexpr (O) {
+      return *reinterpret_cast<const R*>(
+          p + ((n / kBlk) * (unsigned)kBlockBytes + (n % kBlk) * (unsigned)sizeof(R)));
+    } else {
+      return *reinterpret_cast<const R*>(
+          p + ((size_t)(n / kBlk) * kBlockBytes + (size_t)(n % kBlk) * sizeof(R)));
+    }
+  }
+  // population i >= 1 of node n
+  __device__ static const M* at(const void* b, int i, nidx n) {
+    const unsigned char* p = static_cast<const unsigned char*>(b);
+    if constexpr (O) {
+      return reinterpret_cast<const M*>(
+          p + ((n / kBlk) * (unsigned)kBlockBytes + (unsigned)kRestBytes +
+               (unsigned)((i - 1) * kBlk * sizeof(M)) + (n % kBlk) * (unsigned)sizeof(M)));
+    } else {
+      return reinterpret_cast<const M*>(
+          p + ((size_t)(n / kBlk) * kBlockBytes + kRestBytes + (size_t)(i - 1) * kBlk * sizeof(M) +
+               (size_t)(n % kBlk) * sizeof(M)));
+    }
+  }
+  // stores: block base, then the element
   __device__ static void store_rest(void* b, nidx n, R v, int nt = 0) {
-    st(static_cast<R*>(b) + n, v, nt);
+    st(reinterpret_cast<R*>(static_cast<unsigned char*>(b) + (size_t)(n / kBlk) * kBlockBytes) +
+           n % kBlk, v, nt);
   }
-  __device__ static const M* moving(const void* b, long long NQ) {
-    return reinterpret_cast<const M*>(static_cast<const unsigned char*>(b) + NQ * sizeof(R));
-  }
-  __device__ static M* moving(void* b, long long NQ) {
-    return reinterpret_cast<M*>(static_cast<unsigned char*>(b) + NQ * sizeof(R));
+  __device__ static M* at(void* b, int i, nidx n) {
+    return reinterpret_cast<M*>(static_cast<unsigned char*>(b) + (size_t)(n / kBlk) * kBlockBytes +
+                                kRestBytes) +
+           (i - 1) * kBlk + n % kBlk;
   }
   __device__ static C decode(M v, float scale) {
     if constexpr (kHalf) return __half2float(v) * (1.0f / scale);
     else return C(v);
   }
-  // population i >= 1
-  __device__ static const M* pop(const void* b, int i, long long NQ) {
-    return moving(b, NQ) + (size_t)(i - 1) * (size_t)NQ;
+  __device__ static C load(const void* b, int i, nidx n, float scale) {
+    return decode(*at(b, i, n), scale);
   }
-  __device__ static C load(const void* b, int i, nidx n, long long NQ, float scale) {
-    return decode(pop(b, i, NQ)[n], scale);
-  }
-  __device__ static void store(void* b, int i, nidx n, long long NQ, C v, float scale,
-                               int nt = 0) {
-    M* p = moving(b, NQ) + (size_t)(i - 1) * (size_t)NQ + n;
+  __device__ static void store(void* b, int i, nidx n, C v, float scale, int nt = 0) {
+    M* p = at(b, i, n);
     if constexpr (kHalf) {
       const __half h = __float2half_rn(v * scale);
       if (nt) __builtin_nontemporal_store(*reinterpret_cast<const unsigned short*>(&h),
@@ -150,12 +182,9 @@ __device__ inline void neighbours(const Geo& G, int x, int y, int z, nidx nb[L::
 // rest population never moves.
 template <class L, class SetT>
 __device__ inline typename SetT::C pull(const void* buf, int i, nidx n, const nidx nb[L::Q],
-                                        uint32_t word, long long NQ, float scale) {
+                                        uint32_t word, float scale) {
   const bool bb = (word >> (kLinkShift + i)) & 1u;
-  const nidx src = bb ? n : nb[L::opp(i)];
-  // both population bases are uniform; each lane picks one
-  const typename SetT::M* p = bb ? SetT::pop(buf, L::opp(i), NQ) : SetT::pop(buf, i, NQ);
-  return SetT::decode(p[src], scale);
+  return bb ? SetT::load(buf, L::opp(i), n, scale) : SetT::load(buf, i, nb[L::opp(i)], scale);
 }
 
 __device__ inline bool node_coords(const Geo& G, int& x, int& y, int& z) {
@@ -166,7 +195,7 @@ __device__ inline bool node_coords(const Geo& G, int& x, int& y, int& z) {
 }
 
 // ------------------------------------------------------------------ k_phi
-template <class L, int S>
+template <class L, int S, bool O = false>
 __global__ void k_phi(const uint32_t* __restrict__ nodes, const void* __restrict__ gsrc,
                       ComputeT<S>* __restrict__ phi, Geo G, Phys P) {
   using C = ComputeT<S>;
@@ -177,12 +206,12 @@ __global__ void k_phi(const uint32_t* __restrict__ nodes, const void* __restrict
   if (!(word & kZeta)) return;
   nidx nb[L::Q];
   neighbours<L>(G, x, y, z, nb);
-  using GS = Set<S, true>;
+  using GS = Set<S, true, L::Q, O>;
   // g_0 carries phi; the moving populations are small.  Summing them first and
   // adding g_0 last rounds once, instead of dropping sub-ulp terms one by one.
   C small = C(0);
 #pragma unroll
-  for (int i = 1; i < L::Q; ++i) small += pull<L, GS>(gsrc, i, n, nb, word, G.NQ, P.scale_g);
+  for (int i = 1; i < L::Q; ++i) small += pull<L, GS>(gsrc, i, n, nb, word, P.scale_g);
   phi[n] = C(GS::load_rest(gsrc, n) + (double)small);
 }
 
@@ -317,63 +346,65 @@ __global__ void k_mu(const uint32_t* __restrict__ nodes, C* __restrict__ phi,
 }
 
 // ------------------------------------------------------------------ node update
-// From the pulled populations, phi, mu and grad phi of one zeta = 1 node: rho,
-// F = mu grad phi + F_b, u and p (Sec. 2.1.2), s = u . grad phi, then
-// MODE 0: collide both sets and store f*, g*, s.  MODE 1: store p and u.
-// MODE 2: store s only.  MODE 3: as MODE 0 with s_prev passed in.
-template <class L, int S, int MODE>
-__device__ inline void node_update(const ComputeT<S>* f, double g0, const ComputeT<S>* g,
-                                   ComputeT<S> ph, ComputeT<S> m, ComputeT<S> gx,
-                                   ComputeT<S> gy, ComputeT<S> gz, nidx n,
-                                   void* __restrict__ fdst, void* __restrict__ gdst,
-                                   ComputeT<S>* __restrict__ sprev, ComputeT<S>* __restrict__ out_p,
-                                   ComputeT<S>* __restrict__ out_u, const Geo& G, const Phys& P,
-                                   int nt = 0, ComputeT<S> sp_pre = ComputeT<S>(0)) {
+// Macroscopic quantities of one node from its pulled f, phi, mu and grad phi:
+// rho, F = mu grad phi + F_b, u and p (Sec. 2.1.2), s = u . grad phi.
+template <class L, int S>
+struct Macro {
   using C = ComputeT<S>;
-  using FS = Set<S, false>;
-  using GS = Set<S, true>;
+  C rho, rx, ry, rz, Fx, Fy, Fz, ux, uy, uz, uu, ugr, p, s;
+  __device__ Macro(const C* f, C ph, C m, C gx, C gy, C gz, const Phys& P) {
+    constexpr int Q = L::Q;
+    const C inv_cs2 = C(3);
+    const C drho = C(P.rho_l - P.rho_g);
+    rho = C(P.rho_g) + ph * drho;
+    rx = drho * gx;                                                // grad rho
+    ry = drho * gy;
+    rz = drho * gz;
+    Fx = m * gx + C(P.Fb[0]);
+    Fy = m * gy + C(P.Fb[1]);
+    Fz = (L::D == 3) ? m * gz + C(P.Fb[2]) : C(0);
+    C mx = C(0), my = C(0), mz = C(0), sumf = C(0);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      mx += C(L::cx(i)) * f[i];
+      my += C(L::cy(i)) * f[i];
+      mz += C(L::cz(i)) * f[i];
+      sumf += f[i];
+    }
+    const C inv_rho = C(1) / rho;
+    ux = (mx + C(0.5) * Fx) * inv_rho;
+    uy = (my + C(0.5) * Fy) * inv_rho;
+    uz = (mz + C(0.5) * Fz) * inv_rho;
+    uu = ux * ux + uy * uy + uz * uz;
+    ugr = ux * rx + uy * ry + uz * rz;                             // u . grad rho
+    const C w0 = C(L::w(0));
+    const C s0 = -w0 * uu * C(0.5) * inv_cs2;
+    p = (sumf + C(0.5) * ugr + rho * s0) / (inv_cs2 * (C(1) - w0));
+    s = ux * gx + uy * gy + uz * gz;                               // u . grad phi
+  }
+};
+
+// Collision of both sets at one node (sp = s of the previous step):
+// Eq. (BGK) with g_eq of Eq. (H_i) and G_i of Eq. (F_i) plus half its time
+// derivative, the latter a backward difference of s, so that
+// G_i + dG_i/2 = w_i k_i (1.5 s - 0.5 s_prev); Eq. (BGK-NS) with f_eq of
+// Eq. (feq_i) and F_i of Eq. (GGi).  get_sp() gives s_prev.  Each
+// post-collision value is handed to the sinks as soon as it is formed:
+// put_g0(g*_0), put_g(i, g*_i) for i >= 1, put_f(i, f*_i); returns
+// s = u . grad phi (the next step's s_prev).
+template <class L, int S, class GetSp, class PutG0, class PutG, class PutF>
+__device__ inline ComputeT<S> collide_post(const ComputeT<S>* f, double g0, const ComputeT<S>* g,
+                                           ComputeT<S> ph, ComputeT<S> m, ComputeT<S> gx,
+                                           ComputeT<S> gy, ComputeT<S> gz, const Phys& P,
+                                           GetSp&& get_sp, PutG0&& put_g0, PutG&& put_g,
+                                           PutF&& put_f) {
+  using C = ComputeT<S>;
   constexpr int Q = L::Q;
   const C inv_cs2 = C(3);
-  const C drho = C(P.rho_l - P.rho_g);
-  const C rho = C(P.rho_g) + ph * drho;
-  const C rx = drho * gx, ry = drho * gy, rz = drho * gz;           // grad rho
-  const C Fx = m * gx + C(P.Fb[0]), Fy = m * gy + C(P.Fb[1]),
-          Fz = (L::D == 3) ? m * gz + C(P.Fb[2]) : C(0);
-  C mx = C(0), my = C(0), mz = C(0), sumf = C(0);
-#pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    mx += C(L::cx(i)) * f[i];
-    my += C(L::cy(i)) * f[i];
-    mz += C(L::cz(i)) * f[i];
-    sumf += f[i];
-  }
-  const C inv_rho = C(1) / rho;
-  const C ux = (mx + C(0.5) * Fx) * inv_rho;
-  const C uy = (my + C(0.5) * Fy) * inv_rho;
-  const C uz = (mz + C(0.5) * Fz) * inv_rho;
-  const C uu = ux * ux + uy * uy + uz * uz;
-  const C ugr = ux * rx + uy * ry + uz * rz;                          // u . grad rho
+  const Macro<L, S> M(f, ph, m, gx, gy, gz, P);
   const C w0 = C(L::w(0));
-  const C s0 = -w0 * uu * C(0.5) * inv_cs2;
-  const C p = (sumf + C(0.5) * ugr + rho * s0) / (inv_cs2 * (C(1) - w0));
-  const C s = ux * gx + uy * gy + uz * gz;                            // u . grad phi
-
-  if (MODE == 1) {
-    out_p[n] = p;
-    out_u[n] = ux;
-    out_u[G.NQ + n] = uy;
-    if (L::D == 3) out_u[2 * G.NQ + n] = uz;
-    return;
-  }
-  if (MODE == 2) {
-    sprev[n] = s;
-    return;
-  }
-
-  // phase-field collision: Eq. (BGK) with the time derivative of G_i as a
-  // backward difference of s, G_i + dG_i/2 = w_i k_i (1.5 s - 0.5 s_prev)
-  const C sp = (MODE == 3) ? sp_pre : sprev[n];
-  const C srcf = C(1.5) * s - C(0.5) * sp;
+  const C sp = get_sp();
+  const C srcf = C(1.5) * M.s - C(0.5) * sp;
   const C itg = C(P.inv_tau_g);
   const C am = C(P.alpha) * m;
   // g_0 - g_0^eq = g_0 - phi + (1 - w_0) alpha mu = (1 - w_0) alpha mu - sum_{i>0} g_i,
@@ -384,35 +415,70 @@ __device__ inline void node_update(const ComputeT<S>* f, double g0, const Comput
   {
     const C d0 = (C(1) - w0) * am - gsmall;
     const C inc = w0 * C(L::k(0)) * srcf - d0 * itg;
-    GS::store_rest(gdst, n, g0 + (double)inc, nt);
+    put_g0(g0 + (double)inc);
   }
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     const C wi = C(L::w(i));
-    const C gp = g[i] - (g[i] - wi * am) * itg + wi * C(L::k(i)) * srcf;
-    GS::store(gdst, i, n, G.NQ, gp, P.scale_g, nt);
+    put_g(i, g[i] - (g[i] - wi * am) * itg + wi * C(L::k(i)) * srcf);
   }
   // hydrodynamic collision
   C tau = C(P.tau);
   if (P.visc_var) tau = (ph * C(P.nu_l - P.nu_g) + C(P.nu_g)) * inv_cs2 + C(0.5);
   const C itau = C(1) / tau;
   const C ffac = C(1) - C(0.5) * itau;
-  const C pc = p * inv_cs2;
+  const C pc = M.p * inv_cs2;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const C wi = C(L::w(i));
     const C cx = C(L::cx(i)), cy = C(L::cy(i)), cz = C(L::cz(i));
-    const C cu = cx * ux + cy * uy + cz * uz;
-    const C cF = cx * Fx + cy * Fy + cz * Fz;
-    const C cr = cx * rx + cy * ry + cz * rz;
-    const C si = wi * (cu * inv_cs2 + C(0.5) * cu * cu * inv_cs2 * inv_cs2 - C(0.5) * uu * inv_cs2);
-    const C feq = pc * (i == 0 ? wi - C(1) : wi) + rho * si;
+    const C cu = cx * M.ux + cy * M.uy + cz * M.uz;
+    const C cF = cx * M.Fx + cy * M.Fy + cz * M.Fz;
+    const C cr = cx * M.rx + cy * M.ry + cz * M.rz;
+    const C si = wi * (cu * inv_cs2 + C(0.5) * cu * cu * inv_cs2 * inv_cs2 -
+                       C(0.5) * M.uu * inv_cs2);
+    const C feq = pc * (i == 0 ? wi - C(1) : wi) + M.rho * si;
     // Eq. (GGi): u.grad rho + c.F/cs2 + [(c.u)(c.grad rho) - cs2 u.grad rho]/cs2
-    const C Fi = ffac * wi * (ugr + cF * inv_cs2 + (cu * cr - ugr * C(kCs2)) * inv_cs2);
-    const C fp = f[i] - (f[i] - feq) * itau + Fi;
-    if (i == 0) FS::store_rest(fdst, n, typename FS::R(fp), nt);
-    else FS::store(fdst, i, n, G.NQ, fp, P.scale_f, nt);
+    const C Fi = ffac * wi * (M.ugr + cF * inv_cs2 + (cu * cr - M.ugr * C(kCs2)) * inv_cs2);
+    put_f(i, f[i] - (f[i] - feq) * itau + Fi);
   }
+  return M.s;
+}
+
+// From the pulled populations, phi, mu and grad phi of one zeta = 1 node:
+// MODE 0: collide both sets and store f*, g*, s.  MODE 1: store p and u.
+// MODE 2: store s only.  MODE 3: as MODE 0 with s_prev passed in.
+template <class L, int S, int MODE, bool O = false>
+__device__ inline void node_update(const ComputeT<S>* f, double g0, const ComputeT<S>* g,
+                                   ComputeT<S> ph, ComputeT<S> m, ComputeT<S> gx,
+                                   ComputeT<S> gy, ComputeT<S> gz, nidx n,
+                                   void* __restrict__ fdst, void* __restrict__ gdst,
+                                   ComputeT<S>* __restrict__ sprev, ComputeT<S>* __restrict__ out_p,
+                                   ComputeT<S>* __restrict__ out_u, const Geo& G, const Phys& P,
+                                   int nt = 0, ComputeT<S> sp_pre = ComputeT<S>(0)) {
+  using C = ComputeT<S>;
+  using FS = Set<S, false, L::Q, O>;
+  using GS = Set<S, true, L::Q, O>;
+  if (MODE == 1 || MODE == 2) {
+    const Macro<L, S> M(f, ph, m, gx, gy, gz, P);
+    if (MODE == 1) {
+      out_p[n] = M.p;
+      out_u[n] = M.ux;
+      out_u[G.NQ + n] = M.uy;
+      if (L::D == 3) out_u[2 * G.NQ + n] = M.uz;
+    } else {
+      sprev[n] = M.s;
+    }
+    return;
+  }
+  const C s = collide_post<L, S>(
+      f, g0, g, ph, m, gx, gy, gz, P, [&]() { return (MODE == 3) ? sp_pre : sprev[n]; },
+      [&](double v) { GS::store_rest(gdst, n, v, nt); },
+      [&](int i, C v) { GS::store(gdst, i, n, v, P.scale_g, nt); },
+      [&](int i, C v) {
+        if (i == 0) FS::store_rest(fdst, n, typename FS::R(v), nt);
+        else FS::store(fdst, i, n, v, P.scale_f, nt);
+      });
   sprev[n] = s;
 }
 
@@ -433,16 +499,16 @@ __global__ void k_collide(const uint32_t* __restrict__ nodes, const void* __rest
   if (!(word & kZeta)) return;
   nidx nb[Q];
   neighbours<L>(G, x, y, z, nb);
-  using FS = Set<S, false>;
-  using GS = Set<S, true>;
+  using FS = Set<S, false, L::Q>;
+  using GS = Set<S, true, L::Q>;
   C f[Q], g[Q];
   f[0] = C(FS::load_rest(fsrc, n));
   const double g0 = GS::load_rest(gsrc, n);
   g[0] = C(0);
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
-    f[i] = pull<L, FS>(fsrc, i, n, nb, word, G.NQ, P.scale_f);
-    g[i] = pull<L, GS>(gsrc, i, n, nb, word, G.NQ, P.scale_g);
+    f[i] = pull<L, FS>(fsrc, i, n, nb, word, P.scale_f);
+    g[i] = pull<L, GS>(gsrc, i, n, nb, word, P.scale_g);
   }
   C gx, gy, gz;
   grad_of<L, C>([&](int i) { return phi[nb[i]]; }, gx, gy, gz);
@@ -472,15 +538,15 @@ struct StepTile {
 // Advance the tile with origin (x0, y0, z0) of one case by one step; sphi and
 // sw are LDS arrays of StepTile::NL entries.  Every thread of the workgroup
 // must call it (it synchronises the workgroup).
-template <class L, int S, int BY, int BZ, int KY, int KZ>
+template <class L, int S, int BY, int BZ, int KY, int KZ, bool O = false>
 __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restrict__ nodes,
                                  const void* __restrict__ fsrc, const void* __restrict__ gsrc,
                                  void* __restrict__ fdst, void* __restrict__ gdst,
                                  ComputeT<S>* __restrict__ sprev, const Geo& G, const Phys& P,
                                  ComputeT<S>* sphi, uint32_t* sw) {
   using C = ComputeT<S>;
-  using GS = Set<S, true>;
-  using FS = Set<S, false>;
+  using GS = Set<S, true, L::Q, O>;
+  using FS = Set<S, false, L::Q, O>;
   constexpr int Q = L::Q;
   constexpr bool D3 = (L::D == 3);
   constexpr int TX = 64, TY = BY * KY, TZ = D3 ? BZ * KZ : 1;
@@ -519,7 +585,7 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
     neighbours<L>(G, q[0], q[1], q[2], nb);
     C small = C(0);
 #pragma unroll
-    for (int i = 1; i < Q; ++i) small += pull<L, GS>(gsrc, i, n, nb, w, G.NQ, P.scale_g);
+    for (int i = 1; i < Q; ++i) small += pull<L, GS>(gsrc, i, n, nb, w, P.scale_g);
     return C(GS::load_rest(gsrc, n) + (double)small);
   };
 
@@ -556,7 +622,7 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
       C small = C(0);
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
-        gr[k][i] = pull<L, GS>(gsrc, i, n, nb, w, G.NQ, P.scale_g);
+        gr[k][i] = pull<L, GS>(gsrc, i, n, nb, w, P.scale_g);
         small += gr[k][i];
       }
       g0r[k] = GS::load_rest(gsrc, n);
@@ -618,12 +684,12 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
     C f[Q];
     f[0] = C(FS::load_rest(fsrc, n));
 #pragma unroll
-    for (int i = 1; i < Q; ++i) f[i] = pull<L, FS>(fsrc, i, n, nb, w, G.NQ, P.scale_f);
+    for (int i = 1; i < Q; ++i) f[i] = pull<L, FS>(fsrc, i, n, nb, w, P.scale_f);
     const C m = mu_at<L, C>(sphi, sw, t, SX, SXY, P);
     C gx, gy, gz;
     grad_of<L, C>([&](int i) { return sphi[t + L::cx(i) + SX * L::cy(i) + SXY * L::cz(i)]; },
                   gx, gy, gz);
-    node_update<L, S, 0>(f, g0r[k], gr[k], sphi[t], m, gx, gy, gz, n, fdst, gdst, sprev,
+    node_update<L, S, 0, O>(f, g0r[k], gr[k], sphi[t], m, gx, gy, gz, n, fdst, gdst, sprev,
                          nullptr, nullptr, G, P, P.nt_store);
   }
 }
@@ -632,7 +698,7 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
 // One launch per time step: workgroup b updates tile b (x-fastest order).
 // Workgroups are dealt to the 8 XCDs round-robin; with xcd_order each XCD
 // takes a contiguous run of tiles instead.
-template <class L, int S, int BY, int BZ, int KY, int KZ>
+template <class L, int S, int BY, int BZ, int KY, int KZ, bool O>
 __global__ __launch_bounds__(64 * BY * BZ) void k_step(
     const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
     const void* __restrict__ gsrc, void* __restrict__ fdst, void* __restrict__ gdst,
@@ -647,7 +713,7 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_step(
     const int per = nb / 8, rem = nb % 8, xcd = b % 8, k = b / 8;
     b = (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
   }
-  step_tile<L, S, BY, BZ, KY, KZ>((b % nbx) * T::TX, ((b / nbx) % nby) * T::TY,
+  step_tile<L, S, BY, BZ, KY, KZ, O>((b % nbx) * T::TX, ((b / nbx) % nby) * T::TY,
                                   (b / (nbx * nby)) * T::TZ, nodes, fsrc, gsrc, fdst, gdst, sprev,
                                   G, P, sphi, sw);
 }
@@ -659,7 +725,7 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_step(
 // collides.  One thread per node; workgroup (64, BY, BZ).  g is read twice per
 // step, but nothing is recomputed on the halo, which suits D3Q19 where a
 // one-node halo around a 64 x 4 x 4 tile already has 1.3 times its nodes.
-template <class L, int S, int BY, int BZ>
+template <class L, int S, int BY, int BZ, bool O = false>
 __device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __restrict__ nodes,
                                   const void* __restrict__ fsrc, const void* __restrict__ gsrc,
                                   void* __restrict__ fdst, void* __restrict__ gdst,
@@ -667,8 +733,8 @@ __device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __rest
                                   const ComputeT<S>* __restrict__ phi, const Geo& G,
                                   const Phys& P, ComputeT<S>* sphi, uint32_t* sw) {
   using C = ComputeT<S>;
-  using GS = Set<S, true>;
-  using FS = Set<S, false>;
+  using GS = Set<S, true, L::Q, O>;
+  using FS = Set<S, false, L::Q, O>;
   constexpr int Q = L::Q;
   constexpr bool D3 = (L::D == 3);
   constexpr int TX = 64, TY = BY, TZ = D3 ? BZ : 1;
@@ -741,18 +807,18 @@ __device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __rest
   g[0] = C(0);
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
-    f[i] = pull<L, FS>(fsrc, i, n, nb, w, G.NQ, P.scale_f);
-    g[i] = pull<L, GS>(gsrc, i, n, nb, w, G.NQ, P.scale_g);
+    f[i] = pull<L, FS>(fsrc, i, n, nb, w, P.scale_f);
+    g[i] = pull<L, GS>(gsrc, i, n, nb, w, P.scale_g);
   }
   const C m = mu_at<L, C>(sphi, sw, t, SX, SXY, P);
   C gx, gy, gz;
   grad_of<L, C>([&](int i) { return sphi[t + L::cx(i) + SX * L::cy(i) + SXY * L::cz(i)]; },
                 gx, gy, gz);
-  node_update<L, S, 0>(f, g0, g, sphi[t], m, gx, gy, gz, n, fdst, gdst, sprev, nullptr, nullptr,
+  node_update<L, S, 0, O>(f, g0, g, sphi[t], m, gx, gy, gz, n, fdst, gdst, sprev, nullptr, nullptr,
                        G, P, P.nt_store);
 }
 
-template <class L, int S, int BY, int BZ>
+template <class L, int S, int BY, int BZ, bool O>
 __global__ __launch_bounds__(64 * BY * BZ) void k_stepB(
     const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
     const void* __restrict__ gsrc, void* __restrict__ fdst, void* __restrict__ gdst,
@@ -769,17 +835,17 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_stepB(
     const int per = nb / 8, rem = nb % 8, xcd = b % 8, k = b / 8;
     b = (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
   }
-  stepB_tile<L, S, BY, BZ>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ, nodes,
+  stepB_tile<L, S, BY, BZ, O>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ, nodes,
                            fsrc, gsrc, fdst, gdst, sprev, phi, G, P, sphi, sw);
 }
 
 // phi of the tile nodes (64 x BY x BZ) from pulled g, same arithmetic as k_phi.
-template <class L, int S, int BY, int BZ>
+template <class L, int S, int BY, int BZ, bool O = false>
 __device__ inline void phi_tile(int x0, int y0, int z0, const uint32_t* __restrict__ nodes,
                                 const void* __restrict__ gsrc, ComputeT<S>* __restrict__ phi,
                                 const Geo& G, const Phys& P) {
   using C = ComputeT<S>;
-  using GS = Set<S, true>;
+  using GS = Set<S, true, L::Q, O>;
   const int x = x0 + threadIdx.x, y = y0 + threadIdx.y, z = z0 + ((L::D == 3) ? threadIdx.z : 0);
   if (x >= G.PX || y >= G.PY || z >= G.PZ) return;
   const nidx n = G.idx(x, y, z);
@@ -789,7 +855,7 @@ __device__ inline void phi_tile(int x0, int y0, int z0, const uint32_t* __restri
   neighbours<L>(G, x, y, z, nb);
   C small = C(0);
 #pragma unroll
-  for (int i = 1; i < L::Q; ++i) small += pull<L, GS>(gsrc, i, n, nb, w, G.NQ, P.scale_g);
+  for (int i = 1; i < L::Q; ++i) small += pull<L, GS>(gsrc, i, n, nb, w, P.scale_g);
   phi[n] = C(GS::load_rest(gsrc, n) + (double)small);
 }
 
@@ -806,7 +872,7 @@ struct ColumnTile {
   static constexpr int LX = 68, LY = TY + 4, PLANE = LX * LY, NL = 5 * PLANE;
 };
 
-template <class L, int S, int TY, int TZ>
+template <class L, int S, int TY, int TZ, bool O = false>
 __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __restrict__ nodes,
                                   const void* __restrict__ fsrc, const void* __restrict__ gsrc,
                                   void* __restrict__ fdst, void* __restrict__ gdst,
@@ -815,8 +881,8 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
                                   const Phys& P, ComputeT<S>* sphi, uint32_t* sw) {
   static_assert(L::D == 3, "z marching is for D3Q19");
   using C = ComputeT<S>;
-  using GS = Set<S, true>;
-  using FS = Set<S, false>;
+  using GS = Set<S, true, L::Q, O>;
+  using FS = Set<S, false, L::Q, O>;
   constexpr int Q = L::Q;
   constexpr int LX = 68, LY = TY + 4, PL = LX * LY;
   constexpr int NT = 64 * TY;
@@ -913,8 +979,8 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
         g[0] = C(0);
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-          f[i] = pull<L, FS>(fsrc, i, n, nb, w, G.NQ, P.scale_f);
-          g[i] = pull<L, GS>(gsrc, i, n, nb, w, G.NQ, P.scale_g);
+          f[i] = pull<L, FS>(fsrc, i, n, nb, w, P.scale_f);
+          g[i] = pull<L, GS>(gsrc, i, n, nb, w, P.scale_g);
         }
         // neighbour entry for lattice direction i
         auto at = [&](int i) {
@@ -944,7 +1010,7 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
                     av * C(P.wet) * (ph - ph * ph);
         C gx, gy, gz;
         grad_of<L, C>([&](int i) { return sphi[at(i)]; }, gx, gy, gz);
-        node_update<L, S, 0>(f, g0, g, ph, m, gx, gy, gz, n, fdst, gdst, sprev, nullptr,
+        node_update<L, S, 0, O>(f, g0, g, ph, m, gx, gy, gz, n, fdst, gdst, sprev, nullptr,
                              nullptr, G, P, P.nt_store);
       }
     }
@@ -952,7 +1018,7 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
   }
 }
 
-template <class L, int S, int TY, int TZ>
+template <class L, int S, int TY, int TZ, bool O>
 __global__ __launch_bounds__(64 * TY) void k_stepC(
     const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
     const void* __restrict__ gsrc, void* __restrict__ fdst, void* __restrict__ gdst,
@@ -962,7 +1028,7 @@ __global__ __launch_bounds__(64 * TY) void k_stepC(
   __shared__ uint32_t sw[T::NL];
   const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY;
   const int b = blockIdx.x;
-  stepC_tile<L, S, TY, TZ>((b % nbx) * 64, ((b / nbx) % nby) * TY, (b / (nbx * nby)) * TZ, nodes,
+  stepC_tile<L, S, TY, TZ, O>((b % nbx) * 64, ((b / nbx) % nby) * TY, (b / (nbx * nby)) * TZ, nodes,
                            fsrc, gsrc, fdst, gdst, sprev, phi, G, P, sphi, sw);
 }
 
@@ -1013,7 +1079,7 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_step_group(
     const int c = cd.cur0 ^ parity;
     const int nbx = (G.PX + T::TX - 1) / T::TX, nby = (G.PY + T::TY - 1) / T::TY;
     const int b = te.tile;
-    step_tile<L, S, BY, BZ, KY, KZ>((b % nbx) * T::TX, ((b / nbx) % nby) * T::TY,
+    step_tile<L, S, BY, BZ, KY, KZ, true>((b % nbx) * T::TX, ((b / nbx) % nby) * T::TY,
                                     (b / (nbx * nby)) * T::TZ, cd.nodes, cd.f[c], cd.g[c],
                                     cd.f[1 - c], cd.g[1 - c], static_cast<ComputeT<S>*>(cd.s), G,
                                     cd.P, sphi, sw);
@@ -1036,7 +1102,7 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_phi_group(
     const int c = cd.cur0 ^ parity;
     const int nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY;
     const int b = te.tile;
-    phi_tile<L, S, BY, BZ>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ,
+    phi_tile<L, S, BY, BZ, true>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ,
                            cd.nodes, cd.g[c], static_cast<ComputeT<S>*>(cd.phi), G, cd.P);
   }
 }
@@ -1058,7 +1124,7 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_stepB_group(
     const int c = cd.cur0 ^ parity;
     const int nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY;
     const int b = te.tile;
-    stepB_tile<L, S, BY, BZ>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ,
+    stepB_tile<L, S, BY, BZ, true>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ,
                              cd.nodes, cd.f[c], cd.g[c], cd.f[1 - c], cd.g[1 - c],
                              static_cast<ComputeT<S>*>(cd.s),
                              static_cast<const ComputeT<S>*>(cd.phi), G, cd.P, sphi, sw);
@@ -1081,7 +1147,7 @@ __global__ __launch_bounds__(64 * TY) void k_stepC_group(
     const int c = cd.cur0 ^ parity;
     const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY;
     const int b = te.tile;
-    stepC_tile<L, S, TY, TZ>((b % nbx) * 64, ((b / nbx) % nby) * TY, (b / (nbx * nby)) * TZ,
+    stepC_tile<L, S, TY, TZ, true>((b % nbx) * 64, ((b / nbx) % nby) * TY, (b / (nbx * nby)) * TZ,
                              cd.nodes, cd.f[c], cd.g[c], cd.f[1 - c], cd.g[1 - c],
                              static_cast<ComputeT<S>*>(cd.s),
                              static_cast<const ComputeT<S>*>(cd.phi), G, cd.P, sphi, sw);
@@ -1104,7 +1170,7 @@ __global__ void k_init_g(const uint32_t* __restrict__ nodes, void* __restrict__ 
   if (!(word & kZeta)) return;
   nidx nb[L::Q];
   neighbours<L>(G, x, y, z, nb);
-  using GS = Set<S, true>;
+  using GS = Set<S, true, L::Q>;
   const C am = C(P.alpha) * mu[n];
   GS::store_rest(gdst, n, (double)phi[n] - (1.0 - L::w(0)) * (double)am);
 #pragma unroll
@@ -1112,9 +1178,9 @@ __global__ void k_init_g(const uint32_t* __restrict__ nodes, void* __restrict__ 
     const C geq = C(L::w(i)) * am;
     const bool bb = (word >> (kLinkShift + i)) & 1u;
     if (bb)
-      GS::store(gdst, L::opp(i), n, G.NQ, geq, P.scale_g);
+      GS::store(gdst, L::opp(i), n, geq, P.scale_g);
     else
-      GS::store(gdst, i, nb[L::opp(i)], G.NQ, geq, P.scale_g);
+      GS::store(gdst, i, nb[L::opp(i)], geq, P.scale_g);
   }
 }
 
@@ -1260,14 +1326,14 @@ __global__ void k_reduce_final(const double* __restrict__ partial, long long npa
 // ------------------------------------------------------------------ batched diagnostics
 // For a group poll: phi of every member (same arithmetic as k_phi), then one
 // partial record per table entry, then per member a fixed-order sum of its
-// entries' partials.  Tiles are (64, ty, tz) nodes, walked by 256 threads.
+// entries' partials.  Tiles are (tx, ty, tz) nodes, walked by 256 threads.
 template <class L, int S>
 __global__ __launch_bounds__(256) void k_phi_group_all(const TileEntry* __restrict__ table,
                                                         const int* __restrict__ ntiles,
                                                         const CaseDesc* __restrict__ cases,
-                                                        int parity, int ty, int tz) {
+                                                        int parity, int tx, int ty, int tz) {
   using C = ComputeT<S>;
-  using GS = Set<S, true>;
+  using GS = Set<S, true, L::Q, true>;
   const int n = *ntiles;
   const int tid = threadIdx.x;
   for (int e = blockIdx.x; e < n; e += gridDim.x) {
@@ -1276,11 +1342,11 @@ __global__ __launch_bounds__(256) void k_phi_group_all(const TileEntry* __restri
     const Geo G = cd.G;
     const void* gsrc = cd.g[cd.cur0 ^ parity];
     C* phi = static_cast<C*>(cd.phi);
-    const int nbx = (G.PX + 63) / 64, nby = (G.PY + ty - 1) / ty;
+    const int nbx = (G.PX + tx - 1) / tx, nby = (G.PY + ty - 1) / ty;
     const int b = te.tile;
-    const int x0 = (b % nbx) * 64, y0 = ((b / nbx) % nby) * ty, z0 = (b / (nbx * nby)) * tz;
-    for (int m = tid; m < 64 * ty * tz; m += 256) {
-      const int x = x0 + m % 64, y = y0 + (m / 64) % ty, z = z0 + m / (64 * ty);
+    const int x0 = (b % nbx) * tx, y0 = ((b / nbx) % nby) * ty, z0 = (b / (nbx * nby)) * tz;
+    for (int m = tid; m < tx * ty * tz; m += 256) {
+      const int x = x0 + m % tx, y = y0 + (m / tx) % ty, z = z0 + m / (tx * ty);
       if (x >= G.PX || y >= G.PY || z >= G.PZ) continue;
       const nidx nn = G.idx(x, y, z);
       const uint32_t w = cd.nodes[nn];
@@ -1289,7 +1355,7 @@ __global__ __launch_bounds__(256) void k_phi_group_all(const TileEntry* __restri
       neighbours<L>(G, x, y, z, nb);
       C small = C(0);
 #pragma unroll
-      for (int i = 1; i < L::Q; ++i) small += pull<L, GS>(gsrc, i, nn, nb, w, G.NQ, cd.P.scale_g);
+      for (int i = 1; i < L::Q; ++i) small += pull<L, GS>(gsrc, i, nn, nb, w, cd.P.scale_g);
       phi[nn] = C(GS::load_rest(gsrc, nn) + (double)small);
     }
   }
@@ -1299,22 +1365,22 @@ template <class L, class C>
 __global__ __launch_bounds__(256) void k_reduce_group(const TileEntry* __restrict__ table,
                                                        const int* __restrict__ ntiles,
                                                        const CaseDesc* __restrict__ cases,
-                                                       double* __restrict__ partial, int ty,
-                                                       int tz, int update_snap) {
+                                                       double* __restrict__ partial, int tx,
+                                                       int ty, int tz, int update_snap) {
   const int n = *ntiles;
   const int tid = threadIdx.x;
   for (int e = blockIdx.x; e < n; e += gridDim.x) {
     const TileEntry te = table[e];
     const CaseDesc& cd = cases[te.case_id];
     const Geo G = cd.G;
-    const int nbx = (G.PX + 63) / 64, nby = (G.PY + ty - 1) / ty;
+    const int nbx = (G.PX + tx - 1) / tx, nby = (G.PY + ty - 1) / ty;
     const int b = te.tile;
-    const int x0 = (b % nbx) * 64, y0 = ((b / nbx) % nby) * ty, z0 = (b / (nbx * nby)) * tz;
+    const int x0 = (b % nbx) * tx, y0 = ((b / nbx) % nby) * ty, z0 = (b / (nbx * nby)) * tz;
     double acc[kRecN];
 #pragma unroll
     for (int k = 0; k < kRecN; ++k) acc[k] = 0.0;
-    for (int m = tid; m < 64 * ty * tz; m += 256) {
-      const int x = x0 + m % 64, y = y0 + (m / 64) % ty, z = z0 + m / (64 * ty);
+    for (int m = tid; m < tx * ty * tz; m += 256) {
+      const int x = x0 + m % tx, y = y0 + (m / tx) % ty, z = z0 + m / (tx * ty);
       if (x >= G.PX || y >= G.PY || z >= G.PZ) continue;
       node_contrib<L, C>(acc, cd.nodes, static_cast<const C*>(cd.phi),
                          static_cast<const C*>(cd.s), static_cast<C*>(cd.snap), x, y, z, G,

@@ -60,10 +60,13 @@ def test_group_alone_vs_mix_bitwise_3d(P, variant):
         assert np.array_equal(m.fields()["phi"], ref["phi"])
 
 
-def test_group_split_variant_2d(P):
+@pytest.mark.parametrize("variant", [0, 6])
+def test_group_other_variants_2d(P, variant):
+    """Fused 64 x 4 (0) and split (6) batched kernels against the default fused
+    kernel run alone."""
     cs = _cases2d()[:4]
     g = P.Group()
-    g.set_tile(6)
+    g.set_tile(variant)
     members = [P.Case.from_case(c, "f32") for c in cs]
     for m in members:
         g.add(m)

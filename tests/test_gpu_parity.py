@@ -236,16 +236,22 @@ def test_fused_step_equals_three_kernel_path_bitwise(P, lattice, storage):
             assert np.array_equal(f[k], fr[k]), (v, k)
 
 
-def test_fused_narrow_periodic_and_ragged(P):
-    """Tiles wider than a 5-node periodic domain and ragged tile edges."""
-    for shape in ((5, 40), (70, 13)):
+@pytest.mark.parametrize("variant", [1, 3, 6])
+def test_fused_narrow_periodic_and_ragged(P, variant):
+    """Tiles wider than a 3- or 5-node periodic domain, ragged tile edges and a
+    domain closed in x (fused 64 x 8 (1) and 64 x 16 (3) tiles, split step (6))."""
+    for shape, per_x in (((5, 40), True), ((3, 24), True), ((70, 13), True), ((70, 13), False),
+                         ((133, 21), False)):
         c = workloads.flat_droplet_case(shape[0], shape[1], 4.0, 70.0, 4.0)
+        c["periodic"] = (per_x, False)
         a = P.Case.from_case(c, "f64")
         a.set_step_kernel(-1)
         b = P.Case.from_case(c, "f64")
+        b.set_step_kernel(variant)
         a.step(20)
         b.step(20)
-        assert np.array_equal(a.fields()["phi"], b.fields()["phi"])
+        assert np.array_equal(a.fields()["phi"], b.fields()["phi"]), (shape, per_x)
+        assert np.array_equal(a.get_state(), b.get_state()), (shape, per_x)
 
 
 def test_parity_d3q19_fp32_and_fp16dev_vs_oracle(P):
