@@ -48,11 +48,12 @@ def parse():
     ap.add_argument("--steps-3d", type=int, default=400)
     ap.add_argument("--err-steps-3d", type=int, default=2000)
     ap.add_argument("--chunk-3d", type=int, default=20)
-    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=20.0)
-    ap.add_argument("--serve-tol", type=float, default=1e-4)
-    ap.add_argument("--serve-chunk", type=int, default=500)
-    ap.add_argument("--serve-max-steps", type=int, default=20000)
+    ap.add_argument("--serve-tol", type=float, default=1e-3)
+    ap.add_argument("--serve-chunk", type=int, default=1000)
+    ap.add_argument("--serve-alone-sample", type=int, default=3000)
+    ap.add_argument("--serve-util70", type=int, default=1)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--batch-steps", type=int, default=1000)
     a = ap.parse_args()
@@ -170,53 +171,81 @@ def batched(a, torch, P, workloads, stream):
             "nonfinite_cases": int(sum(1 for f in flags if f & 2))}
 
 
+def progress(msg):
+    """One line per finished stage on stderr (the JSON result goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def served(a, torch, P, workloads):
-    """Continuous batching over Poisson arrivals of mixed 2D / 3D cases (the
-    serving workload at reduced sizes), then the same requests one at a time on
-    the plain solver for the same step counts."""
+    """Continuous batching over Poisson arrivals of mixed 2D / 3D wetting cases
+    (the serving workload at reduced grid sizes): an overloaded run at the
+    given arrival rate, then a run at about 70 % of the capacity the first run
+    measured.  A case is steady when max |phi(t) - phi(t - 1000)| <= serve_tol
+    at a poll every 1000 steps; caps are 2e5 steps (2D) and 1e5 (3D).  The
+    one-case-at-a-time reference is the plain solver (graph replay, the same
+    poll cadence) timed on a sample of each served case and scaled to the
+    case's step count."""
     from paper_2312_00369_amd.serve import GpuExecutor, Server
-    reqs = workloads.config4(seed=4, n_requests=a.serve_requests, rate=a.serve_rate,
-                             nx_range=(128, 384), n3_range=(32, 64))
-    for r in reqs:
-        r["steady_tol"] = a.serve_tol
-    ex = GpuExecutor()
-    srv = Server(ex, budget_bytes=a.serve_budget_gb * 2 ** 30, max_slots=64,
-                 chunk_steps=a.serve_chunk, max_steps=a.serve_max_steps)
-    rec, summ = srv.run(reqs)
-    # one case at a time: same requests, same step counts, plain solver + graphs
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    node_steps = 0
+
+    def requests(n, rate, seed):
+        reqs = workloads.config4(seed=seed, n_requests=n, rate=rate, nx_range=(128, 256),
+                                 n3_range=(48, 48))
+        for r in reqs:
+            r["steady_tol"] = a.serve_tol
+            r["max_steps"] = 200000 if r["lattice"] == "D2Q9" else 100000
+        return reqs
+
+    def run_once(reqs):
+        ex = GpuExecutor()
+        srv = Server(ex, budget_bytes=a.serve_budget_gb * 2 ** 30, max_slots=64,
+                     chunk_steps=a.serve_chunk)
+        rec, summ = srv.run(reqs)
+        ex.close()
+        torch.cuda.synchronize()
+        keep = ("requests", "served", "steady", "wall_s", "gpu_busy_s", "utilisation",
+                "cases_per_s", "aggregate_MLUPS", "p50_time_to_steady_s", "p99_time_to_steady_s",
+                "p50_time_to_result_s", "p99_time_to_result_s", "offered_rate_per_s", "by_lattice")
+        return rec, {k: (round(summ[k], 4) if isinstance(summ[k], float) else summ[k]) for k in keep}
+
+    reqs = requests(a.serve_requests, a.serve_rate, 4)
+    rec, s1 = run_once(reqs)
+    progress(f"served (overloaded): {s1['served']} cases in {s1['wall_s']} s")
+    # one case at a time: per-step time of each served case alone, scaled to its steps
+    t_alone = 0.0
     for r in rec:
-        if "steps" not in r:
+        if not r.get("steps"):
             continue
         c = reqs[r["index"]]
         h = P.Case.from_case(c, "f32", steady_tol=a.serve_tol)
         h.set_graph_chunk(100)
+        h.step(200)
+        h.diagnostics()
+        torch.cuda.synchronize()
+        k = min(int(r["steps"]), a.serve_alone_sample)
+        t0 = time.perf_counter()
         done = 0
-        while done < r["steps"]:
-            k = min(a.serve_chunk, r["steps"] - done)
-            h.step(k)
-            h.diagnostics()            # the same poll cadence as the server
-            done += k
-        node_steps += done * int(np.prod(c["shape"]))
+        while done < k:
+            n = min(a.serve_chunk, k - done)
+            h.step(n)
+            h.diagnostics()
+            done += n
+        torch.cuda.synchronize()
+        t_alone += (time.perf_counter() - t0) / k * int(r["steps"])
         h.close()
-    torch.cuda.synchronize()
-    t_alone = time.perf_counter() - t0
-    nodes_served = sum(int(r.get("steps", 0)) * int(np.prod(reqs[r["index"]]["shape"]))
-                       for r in rec)
-    out = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
-    out.update({"workload": f"{len(reqs)} Poisson arrivals at {a.serve_rate}/s: 2D 128x64..384x192, "
-                            f"3D 32^3..64^3, flat/inclined/curved, theta U[30,150], FP32; steady = "
-                            f"max|dphi| <= {a.serve_tol} over {a.serve_chunk} steps, cap "
-                            f"{a.serve_max_steps}",
-                "one_at_a_time_wall_s": round(t_alone, 3),
-                "one_at_a_time_MLUPS": round(node_steps / t_alone / 1e6, 1),
-                "served_MLUPS_busy": round(nodes_served / summ["gpu_busy_s"] / 1e6, 1)
-                if summ["gpu_busy_s"] else None,
-                "throughput_vs_one_at_a_time": round(t_alone / summ["wall_s"], 2),
-                "status": {s: sum(1 for r in rec if r.get("status") == s)
-                           for s in ("steady", "step cap", "nonfinite")}})
+    out = {"workload": f"Poisson arrivals of mixed D2Q9 128x64..256x128 and D3Q19 48^3 "
+                       f"flat/inclined/curved wetting cases, theta U[30,150], FP32; steady = "
+                       f"max|dphi| <= {a.serve_tol} over {a.serve_chunk} steps, caps 2e5 (2D) / "
+                       f"1e5 (3D) steps",
+           "overloaded": s1,
+           "one_at_a_time_s_est": round(t_alone, 2),
+           "throughput_vs_one_at_a_time": round(t_alone / s1["wall_s"], 2)}
+    if a.serve_util70 and s1["gpu_busy_s"]:
+        cap = s1["served"] / s1["gpu_busy_s"]            # cases per second of busy GPU
+        rate = 0.7 * cap
+        n2 = max(4, a.serve_requests // 2)
+        _, s2 = run_once(requests(n2, rate, 5))
+        progress(f"served (70% utilisation): {s2['served']} cases in {s2['wall_s']} s")
+        out["util70"] = dict(s2, target_rate_per_s=round(rate, 4))
     return out
 
 
@@ -260,6 +289,7 @@ def main():
             line["served"] = served(a, torch, P, workloads)
     if "cpu" in a.sec:
         line["cpu_baseline"] = cpu_baseline(workloads.config1(theta=a.theta))
+        progress("cpu baseline done")
     print(json.dumps(line), flush=True)
 
 
@@ -310,6 +340,7 @@ def run(a, torch, P, workloads, stream):
                   "nonfinite": d["nonfinite"]},
     }
     case.close()
+    progress("main done")
     if "twin" in a.sec:
         # DRAM-bound twin: 8192 x 4096 (33.5 M nodes), same physics
         big = workloads.config1(theta=a.theta, nx=8192, ny=4096)
@@ -326,10 +357,13 @@ def run(a, torch, P, workloads, stream):
                              "k_step_ms": round(float(kb[3]), 4),
                              "k_step_GBps_alg": round(alg * nb / (float(kb[3]) / 1e3) / 1e9, 1)}
         cb.close()
+        progress("twin done")
     if "3d" in a.sec:
         line["inclined_3d"] = inclined_3d(a, torch, P, workloads, stream)
+        progress("3d done")
     if "batched" in a.sec:
         line["batched"] = batched(a, torch, P, workloads, stream)
+        progress("batched done")
     if a.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)

@@ -6,12 +6,14 @@ budget and a slot is free; admitted cases join the running group of their
 lattice and storage at the next chunk boundary and advance together with the
 cases already resident.  After every chunk the groups are polled: cases that
 are steady (max |phi(t) - phi(t - chunk)| <= steady_tol), non-finite, or at
-their step cap leave, their memory is freed and waiting requests are admitted.
+their step cap (the request's "max_steps", else the server's) leave, their
+memory is freed and waiting requests are admitted.
 
 The executor is an interface (`Executor`): `GpuExecutor` drives the HIP
 library; tests drive the same scheduler with a fake executor and clock.
 Time-to-steady is measured from a request's arrival to the poll that found it
-steady.
+steady; time-to-result from arrival to the poll at which the case left
+(steady, non-finite or capped).
 """
 import collections
 import time
@@ -106,6 +108,16 @@ class GpuExecutor(Executor):
                                            mass=d["mass"], residual=d["steady_residual"])
         return out
 
+    def close(self):
+        """Destroy the remaining cases and the groups."""
+        for key in list(self.cases):
+            case, gk = self.cases.pop(key)
+            self.groups[gk].remove(case)
+            case.close()
+        for g in self.groups.values():
+            g.close()
+        self.groups = {}
+
     def release(self, key):
         case, gk = self.cases.pop(key)
         d = case.diagnostics()
@@ -136,7 +148,8 @@ class Server:
         active = {}             # key -> request index
         used = 0
         fps = {}
-        rec = [dict(index=i, arrival_s=requests[i]["arrival_s"]) for i in range(len(requests))]
+        rec = [dict(index=i, arrival_s=requests[i]["arrival_s"],
+                lattice=requests[i].get("lattice", "D2Q9")) for i in range(len(requests))]
         t0 = ex.now()
         busy = 0.0
 
@@ -177,7 +190,8 @@ class Server:
                 i = active.get(key)
                 if i is None:
                     continue
-                finished = st["steady"] or st["nonfinite"] or st["steps"] >= self.max_steps
+                cap = int(requests[i].get("max_steps", self.max_steps))
+                finished = st["steady"] or st["nonfinite"] or st["steps"] >= cap
                 if not finished:
                     continue
                 r = ex.release(key)
@@ -185,6 +199,7 @@ class Server:
                 used -= fps.pop(key)
                 rec[i].update(r)
                 rec[i]["done_s"] = done_t
+                rec[i]["time_to_result_s"] = done_t - rec[i]["arrival_s"]
                 rec[i]["steady"] = bool(st["steady"])
                 rec[i]["status"] = ("steady" if st["steady"] else
                                     "nonfinite" if st["nonfinite"] else "step cap")
@@ -214,14 +229,29 @@ def _nodes(req):
 
 def summarize(rec, wall, busy, requests):
     tts = [r["time_to_steady_s"] for r in rec if "time_to_steady_s" in r]
+    ttr = [r["time_to_result_s"] for r in rec if "time_to_result_s" in r]
     served = [r for r in rec if "done_s" in r]
     node_steps = sum(int(r.get("steps", 0)) * _nodes(requests[r["index"]]) for r in served)
-    span = max(requests[-1]["arrival_s"], 1e-9) if requests else 0.0
+    span = max(max(q["arrival_s"] for q in requests), 1e-9) if requests else 0.0
+    by_lattice = {}
+    for r in rec:
+        b = by_lattice.setdefault(r["lattice"], dict(requests=0, steady=0, capped=0, nonfinite=0))
+        b["requests"] += 1
+        st = r.get("status")
+        if st == "steady":
+            b["steady"] += 1
+        elif st == "step cap":
+            b["capped"] += 1
+        elif st == "nonfinite":
+            b["nonfinite"] += 1
     return dict(requests=len(rec), served=len(served), steady=len(tts),
                 refused=sum(1 for r in rec if "refused" in r),
-                wall_s=wall, gpu_busy_s=busy,
+                wall_s=wall, gpu_busy_s=busy, utilisation=busy / wall if wall > 0 else None,
                 cases_per_s=len(served) / wall if wall > 0 else None,
                 aggregate_MLUPS=node_steps / wall / 1e6 if wall > 0 else None,
                 p50_time_to_steady_s=percentile(tts, 50),
                 p99_time_to_steady_s=percentile(tts, 99),
-                offered_rate_per_s=(len(requests) / span) if span else None)
+                p50_time_to_result_s=percentile(ttr, 50),
+                p99_time_to_result_s=percentile(ttr, 99),
+                offered_rate_per_s=(len(requests) / span) if span else None,
+                by_lattice=by_lattice)

@@ -11,7 +11,7 @@ def _requests():
     rng = np.random.default_rng(21)
     reqs = []
     t = 0.0
-    for k in range(6):
+    for k in range(8):
         t += float(rng.exponential(0.02))
         if k % 3 == 2:
             c = workloads.inclined_droplet_case_3d(n=20, radius=5.0, theta=float(rng.uniform(40, 140)),

@@ -105,3 +105,25 @@ def test_percentile():
     assert percentile([1, 2, 3, 4], 50) == 2.5
     assert percentile([5], 99) == 5
     assert percentile([], 50) is None
+
+
+def test_per_request_cap_and_time_to_result():
+    """A request's own max_steps overrides the server cap; time-to-result covers
+    every case that left, time-to-steady only the steady ones; per-lattice
+    counts split steady from capped."""
+    reqs = [_req(0, 0.0, 1, 10 ** 9), _req(1, 0.0, 1, 2000), _req(2, 0.0, 1, 10 ** 9)]
+    reqs[0]["max_steps"] = 3000
+    reqs[2]["lattice"] = "D3Q19"
+    ex = FakeExecutor()
+    rec, summ = Server(ex, budget_bytes=10, max_slots=4, chunk_steps=1000,
+                       max_steps=6000).run(reqs)
+    assert rec[0]["status"] == "step cap" and rec[0]["steps"] == 3000
+    assert rec[1]["status"] == "steady" and rec[1]["steps"] == 2000
+    assert rec[2]["status"] == "step cap" and rec[2]["steps"] == 6000
+    assert rec[0]["time_to_result_s"] == pytest.approx(3.0)
+    assert rec[1]["time_to_result_s"] == pytest.approx(rec[1]["time_to_steady_s"])
+    assert "time_to_steady_s" not in rec[0]
+    assert summ["p99_time_to_result_s"] == pytest.approx(percentile([3.0, 2.0, 6.0], 99))
+    assert summ["by_lattice"]["D2Q9"] == dict(requests=2, steady=1, capped=1, nonfinite=0)
+    assert summ["by_lattice"]["D3Q19"] == dict(requests=1, steady=0, capped=1, nonfinite=0)
+    assert summ["utilisation"] == pytest.approx(1.0)
