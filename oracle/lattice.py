@@ -11,6 +11,10 @@ D3Q19 plus the eight body diagonals.
 
 Weights and c_s^2 = 1/3 are the ones printed after Eq. (Siu).  The phase-source
 coefficient k_i = -1 + I:(c_i c_i - c_s^2 I) / (2 c_s^2) comes from Eq. (F_i).
+
+D3Q7 is the three-dimensional velocity set Sec. 2.1.3 names for the
+Cahn-Hilliard equation: the rest vector and the six axis vectors in the order
+of the printed 3 x 7 matrix, weights 1/4 and 1/8, c_s^2 = 1/4.
 """
 import itertools
 import math
@@ -65,12 +69,23 @@ def _d3q19():
     return Lattice("D3Q19", c, w, 1 / 3)
 
 
+def _d3q7():
+    # columns of the printed matrix: rest, +x, -x, +y, -y, +z, -z
+    rows = [[0, 1, -1, 0, 0, 0, 0],
+            [0, 0, 0, 1, -1, 0, 0],
+            [0, 0, 0, 0, 0, 1, -1]]
+    c = [tuple(rows[d][i] for d in range(3)) for i in range(7)]
+    w = [1 / 4] + [1 / 8] * 6
+    return Lattice("D3Q7", c, w, 1 / 4)
+
+
 D2Q9 = _d2q9()
 D3Q19 = _d3q19()
+D3Q7 = _d3q7()
 
 
 def by_name(name):
-    return {"D2Q9": D2Q9, "D3Q19": D3Q19}[name]
+    return {"D2Q9": D2Q9, "D3Q19": D3Q19, "D3Q7": D3Q7}[name]
 
 
 def ghost_neighbourhood(D):

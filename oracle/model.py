@@ -45,6 +45,7 @@ def beta_kappa(sigma, width):
 @dataclass
 class Params:
     lattice: str = "D2Q9"
+    phase_lattice: str = ""           # velocity set of g; "" = same as `lattice`
     shape: tuple = (128, 64)          # (nx, ny) or (nx, ny, nz)
     periodic: tuple = (True, False)   # per axis
     tau: float = 0.8                  # tau_f when nu_l = nu_g = 0
@@ -245,25 +246,34 @@ class Oracle:
         self.L = lat.by_name(params.lattice)
         if self.L.D != len(params.shape):
             raise ValueError("lattice dimension does not match the grid")
+        # velocity set of the phase-field LBE (Sec. 2.1.3 names D2Q9 and D3Q7);
+        # node classes and the phi stencils stay on the hydrodynamic set
+        self.Lg = lat.by_name(params.phase_lattice) if params.phase_lattice else self.L
+        if self.Lg.D != self.L.D:
+            raise ValueError("phase lattice dimension does not match the grid")
         self.grid = Grid(params.shape, params.periodic)
         self.zeta, self.eps, self.ghost, self.boundary = classify(
             self.grid, self.L, solid_mask)
         self.a_v = effective_area(self.grid, self.L, self.eps, self.zeta)
         self.tau_g = params.tau_phi if params.tau_phi > 0 else params.tau
-        # Eq. (mobility): M = c_s^2 alpha (tau_g - 1/2).  READING: tau_g is the
-        # given relaxation time and alpha follows from it.
-        self.alpha = params.mobility / (self.L.cs2 * (self.tau_g - 0.5))
+        # Eq. (mobility): M = c_s^2 alpha (tau_g - 1/2), c_s^2 of the phase
+        # lattice.  READING: tau_g is the given relaxation time and alpha
+        # follows from it.
+        self.alpha = params.mobility / (self.Lg.cs2 * (self.tau_g - 0.5))
         phi = np.where(self.zeta, self.grid.from_domain(np.asarray(phi0, np.float64)), 0.0)
         mu, _, _ = self._mu(phi)
-        self.g = np.where(self.zeta, g_equilibrium(self.L, phi, self.alpha, mu), 0.0)
+        self.g = np.where(self.zeta, g_equilibrium(self.Lg, phi, self.alpha, mu), 0.0)
         self.f = np.zeros((self.L.Q, self.grid.N))   # p = 0, u = 0
         self.s_prev = None                           # unset until the first step
         self.t = 0
-        # pull maps with bounce-back, built once
-        self._pull = []
-        for i in range(self.L.Q):
-            nb, ok = self.grid.shift(-self.L.c[i])
-            self._pull.append((nb, ok & self.zeta[nb]))
+        # pull maps with bounce-back, built once per velocity set
+        self._pull = {}
+        for Lx in {self.L.name: self.L, self.Lg.name: self.Lg}.values():
+            maps = []
+            for i in range(Lx.Q):
+                nb, ok = self.grid.shift(-Lx.c[i])
+                maps.append((nb, ok & self.zeta[nb]))
+            self._pull[Lx.name] = maps
 
     # --------------------------------------------------------- pieces
     def tau_f(self, phi):
@@ -316,8 +326,9 @@ class Oracle:
         s_before = self.s_prev
         # Eq. (BGK) with the time derivative of G_i taken as a backward difference.
         # READING: G_i + (1/2) dG_i/dt ~ w_i k_i (s(t) + (s(t) - s(t-1))/2).
-        geq = g_equilibrium(L, m["phi"], self.alpha, m["mu"])
-        src = phase_source(L, s) + 0.5 * (phase_source(L, s) - phase_source(L, self.s_prev))
+        Lg = self.Lg
+        geq = g_equilibrium(Lg, m["phi"], self.alpha, m["mu"])
+        src = phase_source(Lg, s) + 0.5 * (phase_source(Lg, s) - phase_source(Lg, self.s_prev))
         g_post = self.g - (self.g - geq) / self.tau_g + src
         tau_f = self.tau_f(m["phi"])
         feq = f_equilibrium(L, m["p"], m["rho"], m["u"])
@@ -326,21 +337,21 @@ class Oracle:
         g_post[:, ~z] = 0.0
         f_post[:, ~z] = 0.0
         self.s_prev = s
-        self.g = self._stream(g_post)
-        self.f = self._stream(f_post)
+        self.g = self._stream(g_post, self.Lg)
+        self.f = self._stream(f_post, self.L)
         self.t += 1
         self.last = dict(s=s, s_before=s_before, **m)
 
-    def _stream(self, post):
+    def _stream(self, post, Lx):
         """Pull streaming; a link whose source is a zeta = 0 node bounces back.
 
         READING: the paper's modified bounce-back (Sec. 2.2.2) is taken as the
         halfway rule in pull form: f_i(x, t+1) = f*_{i'}(x, t) when x - c_i is a
         zeta = 0 node; the wall sits halfway along that link."""
         out = np.zeros_like(post)
-        for i in range(self.L.Q):
-            nb, take = self._pull[i]
-            out[i] = np.where(take, post[i][nb], post[self.L.opp[i]])
+        for i in range(Lx.Q):
+            nb, take = self._pull[Lx.name][i]
+            out[i] = np.where(take, post[i][nb], post[Lx.opp[i]])
         out[:, ~self.zeta] = 0.0
         return out
 

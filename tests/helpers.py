@@ -10,7 +10,8 @@ def oracle_for(c, **over):
     beta, kappa = beta_kappa(c["sigma"], c["width"])
     kw = dict(lattice=c["lattice"], shape=tuple(c["shape"]), periodic=tuple(c["periodic"]),
               tau=c.get("tau", 0.8), mobility=c.get("mobility", 0.1), beta=beta, kappa=kappa,
-              rho_l=c.get("rho_l", 10.0), rho_g=c.get("rho_g", 1.0), theta_deg=c["theta_deg"])
+              rho_l=c.get("rho_l", 10.0), rho_g=c.get("rho_g", 1.0), theta_deg=c["theta_deg"],
+              phase_lattice=c.get("phase_lattice", ""))
     kw.update(over)
     return Oracle(Params(**kw), c["mask"], c["phi0"])
 

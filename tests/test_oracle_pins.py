@@ -17,6 +17,7 @@ from oracle import model as om
 from tests.helpers import oracle_for
 
 LATTICES = [lat.D2Q9, lat.D3Q19]
+PHASE_LATTICES = [lat.D2Q9, lat.D3Q19, lat.D3Q7]
 
 
 # ---------------------------------------------------------------- P1 lattice
@@ -47,9 +48,25 @@ def test_lattice_paper_d2q9_order():
     assert [tuple(v) for v in lat.D2Q9.c[5:9]] == [(1, 1), (-1, 1), (-1, -1), (1, -1)]
 
 
+def test_lattice_d3q7_as_printed():
+    """Sec. 2.1.3: the columns of the printed 3 x 7 matrix, w_0 = 1/4, w_1-6 = 1/8,
+    c_s^2 = 1/4, and isotropy of the second moment with that c_s^2."""
+    L = lat.D3Q7
+    assert [tuple(v) for v in L.c] == [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0),
+                                       (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    assert L.w[0] == 0.25 and np.all(L.w[1:] == 0.125) and L.cs2 == 0.25
+    c = L.c.astype(float)
+    assert abs(L.w.sum() - 1.0) < 1e-15
+    assert np.abs(L.w @ c).max() < 1e-15
+    assert np.abs(np.einsum("q,qa,qb->ab", L.w, c, c) - np.eye(3) / 4).max() < 1e-15
+    assert np.abs(np.einsum("q,qa,qb,qc->abc", L.w, c, c, c)).max() < 1e-15
+    assert np.array_equal(L.c[L.opp], -L.c)
+
+
 @pytest.mark.parametrize("L,expect", [(lat.D2Q9, {0: -2.0, 1: -0.5, 2: 1.0}),
-                                      (lat.D3Q19, {0: -2.5, 1: -1.0, 2: 0.5})],
-                         ids=["D2Q9", "D3Q19"])
+                                      (lat.D3Q19, {0: -2.5, 1: -1.0, 2: 0.5}),
+                                      (lat.D3Q7, {0: -2.5, 1: -0.5})],
+                         ids=["D2Q9", "D3Q19", "D3Q7"])
 def test_source_coefficients(L, expect):
     """Eq. (F_i) bracket, evaluated by hand per speed class |c|^2."""
     c2 = (L.c ** 2).sum(axis=1)
@@ -79,9 +96,10 @@ def test_f_equilibrium_moments(L):
     assert np.abs(P2 - want).max() < 1e-15
 
 
-@pytest.mark.parametrize("L", LATTICES, ids=lambda L: L.name)
+@pytest.mark.parametrize("L", PHASE_LATTICES, ids=lambda L: L.name)
 def test_g_equilibrium_moments(L):
-    """Eq. (H_i): sum g_eq = phi, sum c g_eq = 0, sum c c g_eq = alpha mu c_s^2 I."""
+    """Eq. (H_i): sum g_eq = phi, sum c g_eq = 0, sum c c g_eq = alpha mu c_s^2 I
+    (c_s^2 = 1/3, and 1/4 for D3Q7)."""
     rng = np.random.default_rng(1)
     phi = rng.uniform(0, 1, 5)
     mu = rng.normal(0, 1e-3, 5)
@@ -89,22 +107,27 @@ def test_g_equilibrium_moments(L):
     c = L.c.astype(float)
     assert np.abs(geq.sum(axis=0) - phi).max() < 1e-15
     assert np.abs(np.einsum("qa,qn->an", c, geq)).max() < 1e-18
-    want = 1.7 * mu / 3.0
+    want = 1.7 * mu * (0.25 if L.name == "D3Q7" else 1.0 / 3.0)
     got = np.einsum("qa,qb,qn->abn", c, c, geq)
     for a in range(L.D):
         assert np.abs(got[a, a] - want).max() < 1e-17
     assert np.abs(got - got * np.eye(L.D)[:, :, None]).max() < 1e-18
 
 
-@pytest.mark.parametrize("L", LATTICES, ids=lambda L: L.name)
+@pytest.mark.parametrize("L", PHASE_LATTICES, ids=lambda L: L.name)
 def test_phase_source_moments(L):
-    """Eq. (F_i): sum G_i = -u.grad(phi); first and second moments vanish."""
+    """Eq. (F_i): sum G_i = -u.grad(phi) and the first moment vanishes.  The
+    second moment is sum_i w_i k_i c_i c_i = 0 for D2Q9 and D3Q19; for D3Q7 the
+    bracket gives, per axis, 2 (1/8)(-1/2) = -1/8, so sum c c G = -(s/8) I."""
     s = np.array([0.3, -1.2, 2e-4])
     G = om.phase_source(L, s)
     c = L.c.astype(float)
     assert np.abs(G.sum(axis=0) + s).max() < 1e-15
     assert np.abs(np.einsum("qa,qn->an", c, G)).max() < 1e-16
-    assert np.abs(np.einsum("qa,qb,qn->abn", c, c, G)).max() < 1e-15
+    second = np.einsum("qa,qb,qn->abn", c, c, G)
+    want = -s / 8.0 if L.name == "D3Q7" else 0.0 * s
+    want = np.eye(L.D)[:, :, None] * want[None, None, :]
+    assert np.abs(second - want).max() < 1e-15
 
 
 @pytest.mark.parametrize("L", LATTICES, ids=lambda L: L.name)
@@ -240,6 +263,35 @@ def test_mass_budget_identity():
         m0 = o.mass()
         o.step()
         assert abs(o.mass() - m0 + o.source_sum()) < 1e-12 * m0
+
+
+def test_mass_budget_identity_d3q7():
+    """The same budget with D3Q7 for g on a 3D staircase wall (sum_i w_i k_i = -1
+    holds for D3Q7 as well)."""
+    c = workloads.inclined_droplet_case_3d(n=14, radius=4.0, theta=60.0, width=4.0)
+    c["phase_lattice"] = "D3Q7"
+    o = oracle_for(c)
+    assert o.g.shape[0] == 7
+    for _ in range(20):
+        m0 = o.mass()
+        o.step()
+        assert abs(o.mass() - m0 + o.source_sum()) < 1e-12 * m0
+
+
+def test_hemisphere_ninety_d3q7():
+    """cos(theta) = 0 in 3D with D3Q7 for g: a hemisphere centred on the wall plane
+    stays a hemisphere at 90 degrees."""
+    n, R = 28, 8.0
+    mask = workloads.flat_walls((n, n, 16), bottom=True, top=False)
+    phi0 = workloads.droplet((n, n, 16), (n / 2, n / 2, -0.5), R, 4.0)
+    c = workloads._case("D3Q19", (n, n, 16), (True, True, False), mask, phi0, 90.0, 1e-3, 4.0,
+                        dict(kind="plane", point=(0.0, 0.0, -0.5), normal=(0.0, 0.0, 1.0)))
+    c["phase_lattice"] = "D3Q7"
+    o = oracle_for(c)
+    o.step(400)
+    th, centre, Rf, npts = odiag.contact_angle(o.fields()["phi"], o.domain(o.zeta), c["wall"], 4.0)
+    assert abs(th - 90.0) < 1.0, th
+    assert abs(Rf - R) < 0.6, Rf
 
 
 def test_mass_exact_without_flow():
@@ -439,3 +491,43 @@ def test_beta_kappa_from_sigma_width():
         b, k = om.beta_kappa(sigma, W)
         assert abs(math.sqrt(8 * k / b) - W) < 1e-12
         assert abs(math.sqrt(2 * k * b) / 6 - sigma) < 1e-15
+
+
+# ---------------------------------------------------------------- linear Cahn-Hilliard relaxation
+@pytest.mark.parametrize("lattice,phase", [("D2Q9", ""), ("D3Q19", ""), ("D3Q19", "D3Q7")],
+                         ids=["D2Q9", "D3Q19", "D3Q19-D3Q7"])
+def test_linear_cahn_hilliard_decay_rate(lattice, phase):
+    """Eq. (mobility) with the phase lattice's c_s^2.  A small periodic mode
+    phi = phi0 + A cos(k x) about a stable bulk value obeys the linearised CH
+    equation dA/dt = -M k^2 (psi''(phi0) + kappa K) A, psi = beta phi^2 (phi - 1)^2,
+    psi'' = beta (12 phi0^2 - 12 phi0 + 2), with K = 2 (1 - cos k) the eigenvalue of
+    the discrete Laplacian inside mu (Eq. Laplace).  The measured decay rate
+    matches this closed form within 2 % (a wrong c_s^2 in alpha would be 33 % off
+    for D3Q7, 25 % for the others)."""
+    nx = 32
+    shape = (nx, 4) if lattice == "D2Q9" else (nx, 4, 4)
+    beta, kappa, M, phi0, A0 = 0.03, 0.06, 0.1, 0.1, 1e-3
+    x = np.arange(nx, dtype=float)
+    k = 2 * math.pi / nx
+    prof = phi0 + A0 * np.cos(k * x)
+    phi = np.broadcast_to(prof, shape[::-1]).copy()
+    mask = np.zeros(shape[::-1], dtype=np.uint8)
+    prm = om.Params(lattice=lattice, phase_lattice=phase, shape=shape,
+                    periodic=(True,) * len(shape), tau=0.8, mobility=M, beta=beta,
+                    kappa=kappa, rho_l=1.0, rho_g=1.0, theta_deg=90.0)
+    o = om.Oracle(prm, mask, phi)
+
+    def amplitude():
+        f = o.fields()["phi"]
+        line = f.reshape(-1, nx).mean(axis=0)
+        return 2.0 * (line * np.cos(k * x)).mean()
+
+    o.step(200)
+    a1 = amplitude()
+    T = 3000
+    o.step(T)
+    a2 = amplitude()
+    rate = -math.log(a2 / a1) / T
+    K = 2 * (1 - math.cos(k))
+    theory = M * k * k * (beta * (12 * phi0 ** 2 - 12 * phi0 + 2) + kappa * K)
+    assert abs(rate / theory - 1) < 0.02, (rate, theory)
