@@ -23,7 +23,9 @@ sys.path.insert(0, ROOT)
 # Algorithmic bytes per node update (persistent state read once and written
 # once plus one class byte): D2Q9 FP32 153, D3Q19 FP32 313, D3Q19 FP16-dev 165.
 ALG_BYTES = {("D2Q9", "f32"): 153, ("D2Q9", "f64"): 305, ("D3Q19", "f32"): 313,
-             ("D3Q19", "f16dev"): 165}
+             ("D3Q19", "f16dev"): 165,
+             # D3Q19 f with D3Q7 g: (f 76 + g 28 + s 4) x 2 + 1 in FP32; (38 + 12 + 4 + 4) x 2 + 1
+             ("D3Q19/D3Q7", "f32"): 217, ("D3Q19/D3Q7", "f16dev"): 117}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -48,6 +50,8 @@ def parse():
     ap.add_argument("--steps-3d", type=int, default=400)
     ap.add_argument("--err-steps-3d", type=int, default=2000)
     ap.add_argument("--chunk-3d", type=int, default=20)
+    ap.add_argument("--variant-d3q7", default="7,8",
+                    help="step variants (FP32,FP16-dev) for the 3D workload with D3Q7 for g")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-tol", type=float, default=1e-3)
@@ -127,6 +131,23 @@ def inclined_3d(a, torch, P, workloads, stream):
     out["f16dev_vs_f32_rel_mass"] = abs(out["f16dev"]["mass"] - out["f32"]["mass"]) / out["f32"]["mass"]
     out["workload"] = (f"D3Q19 256^3, inclined 30-deg staircase, sphere R=40, theta=45, W=5; "
                        f"{nodes} fluid+boundary nodes; error after {a.err_steps_3d} steps")
+    # the same workload with D3Q7 for g (Sec. 2.1.3), another model: timed only
+    d7 = {}
+    v7 = dict(zip(("f32", "f16dev"), (int(v) for v in str(a.variant_d3q7).split(","))))
+    for st in ("f32", "f16dev"):
+        c = workloads.config2(storage=st, n=256)
+        c["phase_lattice"] = "D3Q7"
+        h = P.Case.from_case(c, st, stream=stream)
+        h.set_graph_chunk(a.chunk_3d)
+        h.set_step_kernel(v7[st])
+        ms = time_steps(torch, h, a.steps_3d, 20)
+        alg = ALG_BYTES[("D3Q19/D3Q7", st)]
+        mlups = nodes * 1e3 / ms * a.steps_3d / 1e6
+        d7[st] = {"MLUPS": round(mlups, 1), "ms_per_step": round(ms / a.steps_3d, 4),
+                  "hbm_roofline_pct": round(100 * mlups * 1e6 * alg / (HBM_PEAK_GBS * 1e9), 2),
+                  "alg_bytes_per_node": alg, "variant": v7[st]}
+        h.close()
+    out["d3q7_phase"] = d7
     return out
 
 

@@ -45,7 +45,11 @@ extern "C" {
 #define PFLBM_EUNSUPPORTED (-6) /* lattice / storage combination not provided          */
 
 /* ---------------------------------------------------------------- enums */
-enum { PFLBM_D2Q9 = 0, PFLBM_D3Q19 = 1 };                 /* Sec. 2.1.2, Eq. ci / 3ci */
+/* Case lattices: D2Q9 for both sets; D3Q19 for both sets; D3Q19 for f and the
+ * phi stencils with D3Q7 for g (Sec. 2.1.3: w_0 = 1/4, w_1-6 = 1/8,
+ * c_s^2 = 1/4, and alpha = M / (c_s^2 (tau_g - 1/2)) with that c_s^2).
+ * PFLBM_D3Q7 names the phase set alone (pflbm_lattice_table only). */
+enum { PFLBM_D2Q9 = 0, PFLBM_D3Q19 = 1, PFLBM_D3Q19_D3Q7 = 2, PFLBM_D3Q7 = 3 };  /* Eq. ci / 3ci */
 enum { PFLBM_FP64 = 0, PFLBM_FP32 = 1, PFLBM_FP16_DEV = 2 }; /* distribution storage   */
 enum { PFLBM_WALL_NONE = 0, PFLBM_WALL_PLANE = 1, PFLBM_WALL_BALL = 2 };
 
@@ -71,7 +75,7 @@ enum { PFLBM_WALL_NONE = 0, PFLBM_WALL_PLANE = 1, PFLBM_WALL_BALL = 2 };
  */
 typedef struct pflbm_params {
   uint32_t struct_size;          /* = sizeof(pflbm_params) */
-  int32_t lattice;               /* PFLBM_D2Q9 or PFLBM_D3Q19 */
+  int32_t lattice;               /* PFLBM_D2Q9, PFLBM_D3Q19 or PFLBM_D3Q19_D3Q7 */
   int32_t storage;               /* PFLBM_FP64 / FP32 / FP16_DEV */
   int32_t nx, ny, nz;            /* nz = 1 for D2Q9 */
   int32_t periodic[3];           /* nonzero = periodic axis; others get bounce-back walls */
@@ -108,7 +112,8 @@ int pflbm_classify(const pflbm_params* prm, const uint8_t* solid_mask, uint8_t* 
 
 /* Velocity set of a lattice as used by the kernels: c[3*i + a], w[i], opp[i]
  * and the phase-source coefficient k[i] (any pointer may be NULL).  Returns Q
- * (9 or 19) or a negative error code.  (no device work) */
+ * (9, 19, or 7 for PFLBM_D3Q7; PFLBM_D3Q19_D3Q7 gives its D3Q19 set) or a
+ * negative error code.  (no device work) */
 int pflbm_lattice_table(int32_t lattice, int32_t* c, double* w, int32_t* opp, double* k);
 
 /* ---------------------------------------------------------------- single case */

@@ -6,7 +6,8 @@ name, so that `paper_2312_00369_amd.build` can run before anything is built.
 """
 _PUBLIC = ("Case", "Group", "PflbmError", "beta_kappa", "classify", "footprint",
            "lattice_table", "lib", "step_variants", "make_params", "params_from_case",
-           "pflbm_diag", "pflbm_params", "EXPORTED", "LIB_PATH")
+           "pflbm_diag", "pflbm_params", "EXPORTED", "LIB_PATH", "case_lattice",
+           "D2Q9", "D3Q19", "D3Q19_D3Q7", "D3Q7", "FP64", "FP32", "FP16_DEV")
 
 
 def __getattr__(name):

@@ -33,7 +33,8 @@ def shape_class(shape):
 
 
 def cache_key(arch, lattice, storage, shape):
-    lat = {_p.D2Q9: "D2Q9", _p.D3Q19: "D3Q19"}.get(lattice, str(lattice))
+    lat = {_p.D2Q9: "D2Q9", _p.D3Q19: "D3Q19", _p.D3Q19_D3Q7: "D3Q19-D3Q7"}.get(lattice,
+                                                                             str(lattice))
     st = {_p.FP64: "f64", _p.FP32: "f32", _p.FP16_DEV: "f16dev"}.get(storage, str(storage))
     return f"{arch}/{lat}/{st}/{shape_class(shape)}"
 

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpflbm.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "engine.hip", "group.hip"]
+SOURCES = ["engine_d3q19.hip", "engine_d3q19g7.hip", "engine_d2q9.hip", "api.hip", "engine.hip",
+           "group.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

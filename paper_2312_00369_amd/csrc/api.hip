@@ -34,7 +34,7 @@ int validate_and_derive(const pflbm_params* p, Derived* d) {
   if (!p) return set_error(PFLBM_EINVAL, "params is NULL");
   if (p->struct_size != sizeof(pflbm_params))
     return set_error(PFLBM_EINVAL, "struct_size %u != %zu", p->struct_size, sizeof(pflbm_params));
-  if (p->lattice != PFLBM_D2Q9 && p->lattice != PFLBM_D3Q19)
+  if (p->lattice != PFLBM_D2Q9 && p->lattice != PFLBM_D3Q19 && p->lattice != PFLBM_D3Q19_D3Q7)
     return set_error(PFLBM_EUNSUPPORTED, "unknown lattice %d", p->lattice);
   if (p->storage < PFLBM_FP64 || p->storage > PFLBM_FP16_DEV)
     return set_error(PFLBM_EUNSUPPORTED, "unknown storage %d", p->storage);
@@ -59,6 +59,7 @@ int validate_and_derive(const pflbm_params* p, Derived* d) {
 
   d->D = D;
   d->Q = D == 2 ? 9 : 19;
+  d->Qg = p->lattice == PFLBM_D3Q19_D3Q7 ? 7 : d->Q;   // populations of g
   Geo& G = d->geo;
   const int n[3] = {p->nx, p->ny, p->nz};
   int P[3];
@@ -81,7 +82,9 @@ int validate_and_derive(const pflbm_params* p, Derived* d) {
   // nu = c_s^2 (tau_f - 1/2) (Sec. 2.1.2); M = c_s^2 alpha (tau_g - 1/2) (Eq. mobility)
   ph.tau = p->tau;
   ph.inv_tau_g = 1.0 / tau_g;
-  ph.alpha = p->mobility / (kCs2 * (tau_g - 0.5));
+  // c_s^2 of the velocity set of g: 1/3, or 1/4 for D3Q7 (Sec. 2.1.3)
+  const double cs2_g = p->lattice == PFLBM_D3Q19_D3Q7 ? D3Q7::cs2 : kCs2;
+  ph.alpha = p->mobility / (cs2_g * (tau_g - 0.5));
   ph.beta = p->beta;
   ph.kappa = p->kappa;
   // wall coefficient of Eq. (chemical_potencial2): sqrt(2 kappa beta) cos(theta)
@@ -128,21 +131,25 @@ Layout make_layout(const Derived& d, int storage, dim3 tile) {
   const size_t NQ = (size_t)d.geo.NQ;
   const size_t cb = storage == PFLBM_FP64 ? 8 : 4;
   L.c_bytes = NQ * cb;
-  auto sizes = [&](auto q) {
-    constexpr int Q = decltype(q)::value;
+  auto sizes = [&](auto qf, auto qg) {
+    constexpr int Qf = decltype(qf)::value, Qg = decltype(qg)::value;
     if (storage == PFLBM_FP64) {
-      L.f_bytes = Set<kF64, false, Q>::bytes(NQ);
-      L.g_bytes = Set<kF64, true, Q>::bytes(NQ);
+      L.f_bytes = Set<kF64, false, Qf>::bytes(NQ);
+      L.g_bytes = Set<kF64, true, Qg>::bytes(NQ);
     } else if (storage == PFLBM_FP32) {
-      L.f_bytes = Set<kF32, false, Q>::bytes(NQ);
-      L.g_bytes = Set<kF32, true, Q>::bytes(NQ);
+      L.f_bytes = Set<kF32, false, Qf>::bytes(NQ);
+      L.g_bytes = Set<kF32, true, Qg>::bytes(NQ);
     } else {
-      L.f_bytes = Set<kF16Dev, false, Q>::bytes(NQ);
-      L.g_bytes = Set<kF16Dev, true, Q>::bytes(NQ);
+      L.f_bytes = Set<kF16Dev, false, Qf>::bytes(NQ);
+      L.g_bytes = Set<kF16Dev, true, Qg>::bytes(NQ);
     }
   };
-  if (d.Q == 9) sizes(std::integral_constant<int, 9>());
-  else sizes(std::integral_constant<int, 19>());
+  using I9 = std::integral_constant<int, 9>;
+  using I19 = std::integral_constant<int, 19>;
+  using I7 = std::integral_constant<int, 7>;
+  if (d.Q == 9) sizes(I9(), I9());
+  else if (d.Qg == 7) sizes(I19(), I7());
+  else sizes(I19(), I19());
   const Geo& G = d.geo;
   L.nparts = (long long)((G.PX + tile.x - 1) / tile.x) * ((G.PY + tile.y - 1) / tile.y) *
              ((G.PZ + tile.z - 1) / tile.z);
@@ -426,7 +433,8 @@ int pflbm_classify(const pflbm_params* prm, const uint8_t* mask, uint8_t* classe
 
 int pflbm_lattice_table(int32_t lattice, int32_t* c, double* w, int32_t* opp, double* k) {
   clear_error();
-  if (lattice != PFLBM_D2Q9 && lattice != PFLBM_D3Q19)
+  if (lattice != PFLBM_D2Q9 && lattice != PFLBM_D3Q19 && lattice != PFLBM_D3Q19_D3Q7 &&
+      lattice != PFLBM_D3Q7)
     return set_error(PFLBM_EUNSUPPORTED, "unknown lattice %d", lattice);
   auto fill = [&](auto L) {
     using LT = decltype(L);
@@ -438,7 +446,9 @@ int pflbm_lattice_table(int32_t lattice, int32_t* c, double* w, int32_t* opp, do
     }
     return LT::Q;
   };
-  return lattice == PFLBM_D2Q9 ? fill(D2Q9{}) : fill(D3Q19{});
+  if (lattice == PFLBM_D2Q9) return fill(D2Q9{});
+  if (lattice == PFLBM_D3Q7) return fill(D3Q7{});
+  return fill(D3Q19{});     // PFLBM_D3Q19, and the hydrodynamic set of PFLBM_D3Q19_D3Q7
 }
 
 int pflbm_create(const pflbm_params* prm, const uint8_t* mask, const double* phi0, void* stream,
@@ -825,7 +835,7 @@ int pflbm_set_step_options(pflbm_handle h, int32_t xcd_order, int32_t nontempora
 
 int pflbm_step_variants(int32_t lattice, int32_t* tiles, int32_t capacity) {
   clear_error();
-  if (lattice != PFLBM_D2Q9 && lattice != PFLBM_D3Q19)
+  if (lattice != PFLBM_D2Q9 && lattice != PFLBM_D3Q19 && lattice != PFLBM_D3Q19_D3Q7)
     return set_error(PFLBM_EUNSUPPORTED, "unknown lattice %d", lattice);
   const int D = lattice == PFLBM_D2Q9 ? 2 : 3;
   const int count = step_variant_count(D);

@@ -35,7 +35,8 @@ struct Layout {
 
 // Geometry, physics constants and node classes derived on the host.
 struct Derived {
-  int D, Q;
+  int D, Q;           // dimension; populations of f (and of the stencils' set)
+  int Qg;             // populations of g (7 with D3Q7, else Q)
   Geo geo;
   Phys phys;
   Wall wall;
@@ -113,6 +114,18 @@ void group_member_changed(pflbm_case_s* h);
 // receives member k's record.
 int run_group_diag(const GroupLaunch& gl, int parity, int tx, int ty, int tz, double* partial,
                    double* out, int ncases, int update_snap);
+
+// Launchers of one lattice for every storage type (engine_<lattice>.hip).
+struct LatticeEntry {
+  int (*phi)(pflbm_case_s*);
+  int (*mu)(pflbm_case_s*);
+  int (*collide)(pflbm_case_s*, int, void*, void*);
+  int (*step)(pflbm_case_s*);
+  int (*init_g)(pflbm_case_s*);
+  int (*reduce)(pflbm_case_s*, int);
+  int (*group_step)(const GroupLaunch&, int, int*);
+  int (*group_diag)(const GroupLaunch&, int, int, int, int, double*, double*, int, int);
+};
 // Contact-angle fit and flags from a reduction record.
 void finish_diag(const pflbm_case_s* h, const double* rec, pflbm_diag* d);
 }  // namespace pflbm

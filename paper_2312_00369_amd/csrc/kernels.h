@@ -206,12 +206,12 @@ __global__ void k_phi(const uint32_t* __restrict__ nodes, const void* __restrict
   if (!(word & kZeta)) return;
   nidx nb[L::Q];
   neighbours<L>(G, x, y, z, nb);
-  using GS = Set<S, true, L::Q, O>;
+  using GS = Set<S, true, L::G::Q, O>;
   // g_0 carries phi; the moving populations are small.  Summing them first and
   // adding g_0 last rounds once, instead of dropping sub-ulp terms one by one.
   C small = C(0);
 #pragma unroll
-  for (int i = 1; i < L::Q; ++i) small += pull<L, GS>(gsrc, i, n, nb, word, P.scale_g);
+  for (int i = 1; i < L::G::Q; ++i) small += pull<typename L::G, GS>(gsrc, i, n, nb, word, P.scale_g);
   phi[n] = C(GS::load_rest(gsrc, n) + (double)small);
 }
 
@@ -402,7 +402,8 @@ __device__ inline ComputeT<S> collide_post(const ComputeT<S>* f, double g0, cons
   constexpr int Q = L::Q;
   const C inv_cs2 = C(3);
   const Macro<L, S> M(f, ph, m, gx, gy, gz, P);
-  const C w0 = C(L::w(0));
+  using LG = typename L::G;          // velocity set of g
+  const C w0 = C(LG::w(0));
   const C sp = get_sp();
   const C srcf = C(1.5) * M.s - C(0.5) * sp;
   const C itg = C(P.inv_tau_g);
@@ -411,16 +412,16 @@ __device__ inline ComputeT<S> collide_post(const ComputeT<S>* f, double g0, cons
   // formed from small terms only so that g_0 (about phi) is rounded once.
   C gsmall = C(0);
 #pragma unroll
-  for (int i = 1; i < Q; ++i) gsmall += g[i];
+  for (int i = 1; i < LG::Q; ++i) gsmall += g[i];
   {
     const C d0 = (C(1) - w0) * am - gsmall;
-    const C inc = w0 * C(L::k(0)) * srcf - d0 * itg;
+    const C inc = w0 * C(LG::k(0)) * srcf - d0 * itg;
     put_g0(g0 + (double)inc);
   }
 #pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const C wi = C(L::w(i));
-    put_g(i, g[i] - (g[i] - wi * am) * itg + wi * C(L::k(i)) * srcf);
+  for (int i = 1; i < LG::Q; ++i) {
+    const C wi = C(LG::w(i));
+    put_g(i, g[i] - (g[i] - wi * am) * itg + wi * C(LG::k(i)) * srcf);
   }
   // hydrodynamic collision
   C tau = C(P.tau);
@@ -458,7 +459,7 @@ __device__ inline void node_update(const ComputeT<S>* f, double g0, const Comput
                                    int nt = 0, ComputeT<S> sp_pre = ComputeT<S>(0)) {
   using C = ComputeT<S>;
   using FS = Set<S, false, L::Q, O>;
-  using GS = Set<S, true, L::Q, O>;
+  using GS = Set<S, true, L::G::Q, O>;
   if (MODE == 1 || MODE == 2) {
     const Macro<L, S> M(f, ph, m, gx, gy, gz, P);
     if (MODE == 1) {
@@ -500,15 +501,15 @@ __global__ void k_collide(const uint32_t* __restrict__ nodes, const void* __rest
   nidx nb[Q];
   neighbours<L>(G, x, y, z, nb);
   using FS = Set<S, false, L::Q>;
-  using GS = Set<S, true, L::Q>;
-  C f[Q], g[Q];
+  using GS = Set<S, true, L::G::Q>;
+  C f[Q], g[L::G::Q];
   f[0] = C(FS::load_rest(fsrc, n));
   const double g0 = GS::load_rest(gsrc, n);
   g[0] = C(0);
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     f[i] = pull<L, FS>(fsrc, i, n, nb, word, P.scale_f);
-    g[i] = pull<L, GS>(gsrc, i, n, nb, word, P.scale_g);
+    if (i < L::G::Q) g[i] = pull<typename L::G, GS>(gsrc, i, n, nb, word, P.scale_g);
   }
   C gx, gy, gz;
   grad_of<L, C>([&](int i) { return phi[nb[i]]; }, gx, gy, gz);
@@ -545,7 +546,7 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
                                  ComputeT<S>* __restrict__ sprev, const Geo& G, const Phys& P,
                                  ComputeT<S>* sphi, uint32_t* sw) {
   using C = ComputeT<S>;
-  using GS = Set<S, true, L::Q, O>;
+  using GS = Set<S, true, L::G::Q, O>;
   using FS = Set<S, false, L::Q, O>;
   constexpr int Q = L::Q;
   constexpr bool D3 = (L::D == 3);
@@ -585,7 +586,7 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
     neighbours<L>(G, q[0], q[1], q[2], nb);
     C small = C(0);
 #pragma unroll
-    for (int i = 1; i < Q; ++i) small += pull<L, GS>(gsrc, i, n, nb, w, P.scale_g);
+    for (int i = 1; i < L::G::Q; ++i) small += pull<typename L::G, GS>(gsrc, i, n, nb, w, P.scale_g);
     return C(GS::load_rest(gsrc, n) + (double)small);
   };
 
@@ -605,7 +606,7 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
 
   // 2. own tile nodes: pull g, keep it, phi into LDS
   double g0r[KN];
-  C gr[KN][Q];
+  C gr[KN][L::G::Q];
 #pragma unroll
   for (int k = 0; k < KN; ++k) {
     const int ky = k % KY, kz = k / KY;
@@ -621,8 +622,8 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
       neighbours<L>(G, q[0], q[1], q[2], nb);
       C small = C(0);
 #pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        gr[k][i] = pull<L, GS>(gsrc, i, n, nb, w, P.scale_g);
+      for (int i = 1; i < L::G::Q; ++i) {
+        gr[k][i] = pull<typename L::G, GS>(gsrc, i, n, nb, w, P.scale_g);
         small += gr[k][i];
       }
       g0r[k] = GS::load_rest(gsrc, n);
@@ -733,7 +734,7 @@ __device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __rest
                                   const ComputeT<S>* __restrict__ phi, const Geo& G,
                                   const Phys& P, ComputeT<S>* sphi, uint32_t* sw) {
   using C = ComputeT<S>;
-  using GS = Set<S, true, L::Q, O>;
+  using GS = Set<S, true, L::G::Q, O>;
   using FS = Set<S, false, L::Q, O>;
   constexpr int Q = L::Q;
   constexpr bool D3 = (L::D == 3);
@@ -801,14 +802,14 @@ __device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __rest
   const nidx n = G.idx(x, y, z);
   nidx nb[Q];
   neighbours<L>(G, x, y, z, nb);
-  C f[Q], g[Q];
+  C f[Q], g[L::G::Q];
   f[0] = C(FS::load_rest(fsrc, n));
   const double g0 = GS::load_rest(gsrc, n);
   g[0] = C(0);
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     f[i] = pull<L, FS>(fsrc, i, n, nb, w, P.scale_f);
-    g[i] = pull<L, GS>(gsrc, i, n, nb, w, P.scale_g);
+    if (i < L::G::Q) g[i] = pull<typename L::G, GS>(gsrc, i, n, nb, w, P.scale_g);
   }
   const C m = mu_at<L, C>(sphi, sw, t, SX, SXY, P);
   C gx, gy, gz;
@@ -845,7 +846,7 @@ __device__ inline void phi_tile(int x0, int y0, int z0, const uint32_t* __restri
                                 const void* __restrict__ gsrc, ComputeT<S>* __restrict__ phi,
                                 const Geo& G, const Phys& P) {
   using C = ComputeT<S>;
-  using GS = Set<S, true, L::Q, O>;
+  using GS = Set<S, true, L::G::Q, O>;
   const int x = x0 + threadIdx.x, y = y0 + threadIdx.y, z = z0 + ((L::D == 3) ? threadIdx.z : 0);
   if (x >= G.PX || y >= G.PY || z >= G.PZ) return;
   const nidx n = G.idx(x, y, z);
@@ -855,7 +856,7 @@ __device__ inline void phi_tile(int x0, int y0, int z0, const uint32_t* __restri
   neighbours<L>(G, x, y, z, nb);
   C small = C(0);
 #pragma unroll
-  for (int i = 1; i < L::Q; ++i) small += pull<L, GS>(gsrc, i, n, nb, w, P.scale_g);
+  for (int i = 1; i < L::G::Q; ++i) small += pull<typename L::G, GS>(gsrc, i, n, nb, w, P.scale_g);
   phi[n] = C(GS::load_rest(gsrc, n) + (double)small);
 }
 
@@ -881,7 +882,7 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
                                   const Phys& P, ComputeT<S>* sphi, uint32_t* sw) {
   static_assert(L::D == 3, "z marching is for D3Q19");
   using C = ComputeT<S>;
-  using GS = Set<S, true, L::Q, O>;
+  using GS = Set<S, true, L::G::Q, O>;
   using FS = Set<S, false, L::Q, O>;
   constexpr int Q = L::Q;
   constexpr int LX = 68, LY = TY + 4, PL = LX * LY;
@@ -973,14 +974,14 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
         const nidx n = G.idx(x, y, z);
         nidx nb[Q];
         neighbours<L>(G, x, y, z, nb);
-        C f[Q], g[Q];
+        C f[Q], g[L::G::Q];
         f[0] = C(FS::load_rest(fsrc, n));
         const double g0 = GS::load_rest(gsrc, n);
         g[0] = C(0);
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
           f[i] = pull<L, FS>(fsrc, i, n, nb, w, P.scale_f);
-          g[i] = pull<L, GS>(gsrc, i, n, nb, w, P.scale_g);
+          if (i < L::G::Q) g[i] = pull<typename L::G, GS>(gsrc, i, n, nb, w, P.scale_g);
         }
         // neighbour entry for lattice direction i
         auto at = [&](int i) {
@@ -1170,17 +1171,18 @@ __global__ void k_init_g(const uint32_t* __restrict__ nodes, void* __restrict__ 
   if (!(word & kZeta)) return;
   nidx nb[L::Q];
   neighbours<L>(G, x, y, z, nb);
-  using GS = Set<S, true, L::Q>;
+  using GS = Set<S, true, L::G::Q>;
+  using LG = typename L::G;          // velocity set of g
   const C am = C(P.alpha) * mu[n];
-  GS::store_rest(gdst, n, (double)phi[n] - (1.0 - L::w(0)) * (double)am);
+  GS::store_rest(gdst, n, (double)phi[n] - (1.0 - LG::w(0)) * (double)am);
 #pragma unroll
-  for (int i = 1; i < L::Q; ++i) {
-    const C geq = C(L::w(i)) * am;
+  for (int i = 1; i < LG::Q; ++i) {
+    const C geq = C(LG::w(i)) * am;
     const bool bb = (word >> (kLinkShift + i)) & 1u;
     if (bb)
-      GS::store(gdst, L::opp(i), n, geq, P.scale_g);
+      GS::store(gdst, LG::opp(i), n, geq, P.scale_g);
     else
-      GS::store(gdst, i, nb[L::opp(i)], geq, P.scale_g);
+      GS::store(gdst, i, nb[LG::opp(i)], geq, P.scale_g);
   }
 }
 
@@ -1333,7 +1335,7 @@ __global__ __launch_bounds__(256) void k_phi_group_all(const TileEntry* __restri
                                                         const CaseDesc* __restrict__ cases,
                                                         int parity, int tx, int ty, int tz) {
   using C = ComputeT<S>;
-  using GS = Set<S, true, L::Q, true>;
+  using GS = Set<S, true, L::G::Q, true>;
   const int n = *ntiles;
   const int tid = threadIdx.x;
   for (int e = blockIdx.x; e < n; e += gridDim.x) {
@@ -1355,7 +1357,7 @@ __global__ __launch_bounds__(256) void k_phi_group_all(const TileEntry* __restri
       neighbours<L>(G, x, y, z, nb);
       C small = C(0);
 #pragma unroll
-      for (int i = 1; i < L::Q; ++i) small += pull<L, GS>(gsrc, i, nn, nb, w, cd.P.scale_g);
+      for (int i = 1; i < L::G::Q; ++i) small += pull<typename L::G, GS>(gsrc, i, nn, nb, w, cd.P.scale_g);
       phi[nn] = C(GS::load_rest(gsrc, nn) + (double)small);
     }
   }

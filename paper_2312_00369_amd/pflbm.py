@@ -14,12 +14,23 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpflbm.so")
 
-D2Q9, D3Q19 = 0, 1
+D2Q9, D3Q19, D3Q19_D3Q7, D3Q7 = 0, 1, 2, 3
 FP64, FP32, FP16_DEV = 0, 1, 2
 WALL_NONE, WALL_PLANE, WALL_BALL = 0, 1, 2
 STORAGE = {"f64": FP64, "f32": FP32, "f16dev": FP16_DEV, "fp64": FP64, "fp32": FP32,
            "fp16dev": FP16_DEV, FP64: FP64, FP32: FP32, FP16_DEV: FP16_DEV}
-LATTICE = {"D2Q9": D2Q9, "D3Q19": D3Q19, D2Q9: D2Q9, D3Q19: D3Q19}
+LATTICE = {"D2Q9": D2Q9, "D3Q19": D3Q19, "D3Q19/D3Q7": D3Q19_D3Q7, "D3Q7": D3Q7,
+           D2Q9: D2Q9, D3Q19: D3Q19, D3Q19_D3Q7: D3Q19_D3Q7, D3Q7: D3Q7}
+
+
+def case_lattice(c):
+    """Lattice id of a `workloads` case dict: its "lattice", with D3Q7 for g when
+    c["phase_lattice"] == "D3Q7" (Sec. 2.1.3)."""
+    if c.get("phase_lattice") == "D3Q7":
+        if c["lattice"] != "D3Q19":
+            raise ValueError("D3Q7 for g goes with D3Q19")
+        return D3Q19_D3Q7
+    return LATTICE[c["lattice"]]
 ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE",
           -5: "ESTATE", -6: "EUNSUPPORTED"}
 
@@ -171,7 +182,8 @@ def params_from_case(c, storage=None, **over):
               mobility=c.get("mobility", 0.1), rho_l=c.get("rho_l", 10.0),
               rho_g=c.get("rho_g", 1.0), wall=c.get("wall"), diag_width=c["width"])
     kw.update(over)
-    return make_params(c["lattice"], c["shape"], c["periodic"], c["theta_deg"], beta, kappa, **kw)
+    return make_params(case_lattice(c), c["shape"], c["periodic"], c["theta_deg"], beta, kappa,
+                       **kw)
 
 
 def footprint(params):
@@ -188,7 +200,7 @@ def classify(params, mask):
 
 
 def lattice_table(lattice):
-    Q = 9 if LATTICE[lattice] == D2Q9 else 19
+    Q = {D2Q9: 9, D3Q7: 7}.get(LATTICE[lattice], 19)
     c = np.zeros((Q, 3), dtype=np.int32)
     w = np.zeros(Q)
     opp = np.zeros(Q, dtype=np.int32)

@@ -57,7 +57,7 @@ class GpuExecutor(Executor):
         self.groups = {}
         self.cases = {}
         self.keep_fields = keep_fields
-        self.variants = {P.D2Q9: variant_2d, P.D3Q19: variant_3d}
+        self.variants = {P.D2Q9: variant_2d, P.D3Q19: variant_3d, P.D3Q19_D3Q7: variant_3d}
         self.stream = stream
         self._next = 0
 

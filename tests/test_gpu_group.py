@@ -60,6 +60,24 @@ def test_group_alone_vs_mix_bitwise_3d(P, variant):
         assert np.array_equal(m.fields()["phi"], ref["phi"])
 
 
+@pytest.mark.parametrize("variant", [3, 7, 8])
+def test_group_alone_vs_mix_bitwise_d3q7(P, variant):
+    """D3Q7 for g: batched fused (3), split (7) and z-marching (8) kernels."""
+    cs = [workloads.inclined_droplet_case_3d(n=n, radius=0.25 * n, theta=th, width=4.0)
+          for n, th in ((18, 60.0), (26, 120.0))]
+    for c in cs:
+        c["phase_lattice"] = "D3Q7"
+    g = P.Group()
+    g.set_tile(variant)
+    members = [P.Case.from_case(c, "f32") for c in cs]
+    for m in members:
+        g.add(m)
+    g.step(21)
+    for c, m in zip(cs, members):
+        ref = _alone(P, c, "f32", 21, variant)
+        assert np.array_equal(m.fields()["phi"], ref["phi"])
+
+
 @pytest.mark.parametrize("variant", [0, 6])
 def test_group_other_variants_2d(P, variant):
     """Fused 64 x 4 (0) and split (6) batched kernels against the default fused

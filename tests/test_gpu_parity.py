@@ -110,6 +110,36 @@ def test_parity_d3q19_fp64(P):
         _compare(g.fields(), o.fields(), zeta, 1e-12, 1e-12)
 
 
+def test_parity_d3q19_d3q7_fp64(P):
+    """D3Q19 for f and the stencils, D3Q7 for g (Sec. 2.1.3), staircase inclined
+    wall: 40 steps against the FP64 oracle with the same lattices."""
+    c = workloads.inclined_droplet_case_3d(n=24, radius=7.0, theta=45.0, width=4.0)
+    c["phase_lattice"] = "D3Q7"
+    g = P.Case.from_case(c, "f64")
+    o = oracle_for(c)
+    assert o.g.shape[0] == 7
+    zeta = _zeta(g)
+    assert np.array_equal(zeta, o.domain(o.zeta))
+    _compare(g.fields(), o.fields(), zeta, 1e-13, 1e-13)
+    for k in range(2):
+        g.step(20)
+        o.step(20)
+        _compare(g.fields(), o.fields(), zeta, 1e-12, 1e-12)
+
+
+def test_mass_budget_identity_d3q7(P):
+    """The mass budget with D3Q7 for g, FP64 on the GPU."""
+    c = workloads.inclined_droplet_case_3d(n=20, radius=6.0, theta=60.0, width=4.0)
+    c["phase_lattice"] = "D3Q7"
+    g = P.Case.from_case(c, "f64")
+    g.step(50)
+    d0 = g.diagnostics()
+    g.step(1)
+    d1 = g.diagnostics()
+    resid = d1["mass"] - d0["mass"] + 1.5 * d1["s_sum"] - 0.5 * d0["s_sum"]
+    assert abs(resid) <= 1e-12 * d0["mass"], resid
+
+
 def test_parity_d3q19_periodic_fp32(P):
     c = workloads.inclined_droplet_case_3d(n=20, radius=6.0, theta=120.0, width=4.0)
     c["periodic"] = (False, True, False)
@@ -212,12 +242,15 @@ def _geom(lattice):
     else:
         c = workloads.inclined_droplet_case_3d(n=22, radius=6.0, theta=50.0, width=4.0)
         c["periodic"] = (False, True, False)
+        if lattice == "D3Q19/D3Q7":
+            c["phase_lattice"] = "D3Q7"
     return c
 
 
 @pytest.mark.parametrize("lattice,storage", [("D2Q9", "f64"), ("D2Q9", "f32"), ("D2Q9", "f16dev"),
                                              ("D3Q19", "f64"), ("D3Q19", "f32"),
-                                             ("D3Q19", "f16dev")])
+                                             ("D3Q19", "f16dev"), ("D3Q19/D3Q7", "f64"),
+                                             ("D3Q19/D3Q7", "f32"), ("D3Q19/D3Q7", "f16dev")])
 def test_fused_step_equals_three_kernel_path_bitwise(P, lattice, storage):
     """The one-kernel step (every tile variant) and the phi / mu / collide kernels
     give bit-identical fields; the geometry has ghost nodes inside the domain."""
@@ -254,11 +287,14 @@ def test_fused_narrow_periodic_and_ragged(P, variant):
         assert np.array_equal(a.get_state(), b.get_state()), (shape, per_x)
 
 
-def test_parity_d3q19_fp32_and_fp16dev_vs_oracle(P):
-    """D3Q19 inclined staircase, 300 steps: FP32 within 1e-5 of the FP64 oracle;
-    FP16-deviation storage (FP16 moving populations, FP32 compute) within 2e-4,
-    with its error printed."""
+@pytest.mark.parametrize("phase", ["", "D3Q7"])
+def test_parity_d3q19_fp32_and_fp16dev_vs_oracle(P, phase):
+    """D3Q19 inclined staircase, 300 steps (g on D3Q19, or on D3Q7): FP32 within
+    1e-5 of the FP64 oracle; FP16-deviation storage (FP16 moving populations,
+    FP32 compute) within 2e-4, with its error printed."""
     c = workloads.inclined_droplet_case_3d(n=24, radius=7.0, theta=60.0, width=4.0)
+    if phase:
+        c["phase_lattice"] = phase
     o = oracle_for(c)
     o.step(300)
     of = o.fields()
@@ -268,7 +304,8 @@ def test_parity_d3q19_fp32_and_fp16dev_vs_oracle(P):
         g.step(300)
         zeta = _zeta(g)
         errs[st] = maxdiff(g.fields()["phi"], of["phi"], zeta)
-    print(f"D3Q19 300 steps |dphi|_inf vs FP64 oracle: FP32 {errs['f32']:.2e}, "
+    print(f"D3Q19{'/' + phase if phase else ''} 300 steps |dphi|_inf vs FP64 oracle: "
+          f"FP32 {errs['f32']:.2e}, "
           f"FP16-dev {errs['f16dev']:.2e}")
     assert errs["f32"] <= 1e-5
     assert errs["f16dev"] <= 2e-4

@@ -33,14 +33,16 @@ def test_every_declared_symbol_is_exported(P):
     assert set(names) <= set(P.EXPORTED), set(names) - set(P.EXPORTED)
 
 
-@pytest.mark.parametrize("name,L", [("D2Q9", olat.D2Q9), ("D3Q19", olat.D3Q19)])
+@pytest.mark.parametrize("name,L", [("D2Q9", olat.D2Q9), ("D3Q19", olat.D3Q19),
+                                    ("D3Q19/D3Q7", olat.D3Q19), ("D3Q7", olat.D3Q7)])
 def test_library_lattice_tables(P, name, L):
     t = P.lattice_table(name)
     D = L.D
+    assert len(t["w"]) == L.Q
     c = t["c"][:, :D].astype(float)
     w = t["w"]
     assert abs(w.sum() - 1) < 1e-15
-    assert np.abs(np.einsum("q,qa,qb->ab", w, c, c) - np.eye(D) / 3).max() < 1e-15
+    assert np.abs(np.einsum("q,qa,qb->ab", w, c, c) - np.eye(D) * L.cs2).max() < 1e-15
     assert np.array_equal(t["c"][t["opp"]], -t["c"])
     # same velocity set and weights as the oracle (built from the paper's formulas)
     lib_set = {tuple(v[:D]): (wi, ki) for v, wi, ki in zip(t["c"], w, t["k"])}
@@ -128,3 +130,23 @@ def test_footprint_scales_with_storage(P):
     c2 = workloads.flat_droplet_case(512, 256, 20.0, 60.0)
     r = P.footprint(P.params_from_case(c2, "f32")) / P.footprint(P.params_from_case(c, "f32"))
     assert 3.9 < r < 4.1
+
+
+def test_d3q7_phase_lattice_params_and_footprint(P):
+    """D3Q7 for g (Sec. 2.1.3) shrinks each g buffer from 19 to 7 populations per
+    node slot: 12 x 4 B fewer per buffer in FP32, two buffers."""
+    c = workloads.inclined_droplet_case_3d(n=24, radius=6.0, width=4.0)
+    a = P.params_from_case(c, "f32")
+    c7 = dict(c, phase_lattice="D3Q7")
+    b = P.params_from_case(c7, "f32")
+    assert a.lattice == P.D3Q19 and b.lattice == P.D3Q19_D3Q7
+    fa, fb = P.footprint(a), P.footprint(b)
+    slots = fa - fb
+    assert slots > 0 and slots % (2 * 12 * 4) == 0
+    nslots = slots // (2 * 12 * 4)
+    assert 26 ** 3 <= nslots <= 64 * 26 * 26 + 256
+    # classes do not depend on the phase lattice
+    assert np.array_equal(P.classify(a, c["mask"]), P.classify(b, c["mask"]))
+    with pytest.raises(ValueError):
+        P.params_from_case(dict(workloads.flat_droplet_case(32, 16, 5.0, 60.0),
+                                phase_lattice="D3Q7"), "f32")
