@@ -169,6 +169,18 @@ int pflbm_set_step_options(pflbm_handle h, int32_t xcd_order, int32_t nontempora
  * work) */
 int pflbm_step_variants(int32_t lattice, int32_t* tiles, int32_t capacity);
 
+/* FP16-deviation storage keeps value * 2^k per distribution set.  The current
+ * scales of f and g (1 for other storage).  (no device work) */
+int pflbm_fp16_scales(pflbm_handle h, double* scale_f, double* scale_g);
+
+/* Sets the FP16 scales (powers of two within 2^-60 .. 2^60) and rescales the
+ * stored state to them, exactly unless a stored value leaves the FP16 range.
+ * FP16-deviation storage only (else EUNSUPPORTED); refused for a group member
+ * (ESTATE).  pflbm_diagnostics and pflbm_group_poll move a scale by themselves
+ * when the largest stored magnitude of a set leaves [2^11, 2^14].  Drops any
+ * captured graph.  (sync) */
+int pflbm_set_fp16_scales(pflbm_handle h, double scale_f, double scale_g);
+
 /* Current fields as FP64 host arrays of nx*ny*nz (u: D arrays, component-major).
  * Any pointer may be NULL.  phi holds the ghost value on ghost nodes and 0 on
  * other solid nodes; p, u and mu are 0 on zeta = 0 nodes.  (sync) */

@@ -172,6 +172,7 @@ Layout make_layout(const Derived& d, int storage, dim3 tile) {
   const size_t max_parts = (size_t)((G.PX + 63) / 64) * G.PY * G.PZ;
   L.partial = take(max_parts * kRecN * sizeof(double));
   L.rec = take(kRecN * sizeof(double) * 2);
+  L.popmax = take(2 * kPopmaxBlocks * sizeof(float));
   L.total = off;
   return L;
 }
@@ -364,6 +365,7 @@ int create_common(const pflbm_params* prm, const uint8_t* mask, const double* ph
   h->snap = h->base + L.snap;
   h->partial = reinterpret_cast<double*>(h->base + L.partial);
   h->rec = reinterpret_cast<double*>(h->base + L.rec);
+  h->popmax = reinterpret_cast<float*>(h->base + L.popmax);
 
   std::vector<uint32_t> words;
   h->classes.assign((size_t)prm->nx * prm->ny * prm->nz, 0);
@@ -392,6 +394,36 @@ int check_handle(pflbm_handle h) {
 }
 
 }  // namespace
+
+namespace pflbm {
+int fp16_upkeep(pflbm_case_s* h, int* changed) {
+  if (changed) *changed = 0;
+  if (h->prm.storage != PFLBM_FP16_DEV) return PFLBM_OK;
+  float m[2];
+  int rc = run_popmax(h, m);
+  if (rc) return rc;
+  float* scale[2] = {&h->dv.phys.scale_f, &h->dv.phys.scale_g};
+  bool moved = false;
+  for (int k = 0; k < 2; ++k) {
+    // keep the largest stored magnitude in [2^11, 2^14] (the FP16 maximum is
+    // 65504); an all-zero set or a non-finite value (flagged by the
+    // diagnostics record) leaves the scale alone
+    if (!(m[k] > 0.0f) || !std::isfinite(m[k])) continue;
+    if (m[k] >= 2048.0f && m[k] <= 16384.0f) continue;
+    const int e = (int)std::floor(std::log2(8192.0 / (double)m[k]));
+    if (e == 0) continue;
+    const float factor = std::ldexp(1.0f, e);
+    if ((rc = run_rescale(h, k, factor))) return rc;
+    *scale[k] *= factor;
+    moved = true;
+  }
+  if (moved) {
+    drop_graph(h);
+    if (changed) *changed = 1;
+  }
+  return PFLBM_OK;
+}
+}  // namespace pflbm
 
 extern "C" {
 
@@ -679,6 +711,43 @@ int pflbm_diagnostics(pflbm_handle h, pflbm_diag* d) {
   if ((rc = run_reduce(h, 1, rec))) return rc;
   finish_diag(h, rec, d);
   h->snap_valid = true;
+  if (!h->group && (rc = fp16_upkeep(h, nullptr))) return rc;
+  return PFLBM_OK;
+}
+
+
+int pflbm_fp16_scales(pflbm_handle h, double* scale_f, double* scale_g) {
+  clear_error();
+  if (int rc = check_handle(h)) return rc;
+  const bool half = h->prm.storage == PFLBM_FP16_DEV;
+  if (scale_f) *scale_f = half ? h->dv.phys.scale_f : 1.0;
+  if (scale_g) *scale_g = half ? h->dv.phys.scale_g : 1.0;
+  return PFLBM_OK;
+}
+
+int pflbm_set_fp16_scales(pflbm_handle h, double scale_f, double scale_g) {
+  clear_error();
+  if (int rc = check_handle(h)) return rc;
+  if (h->prm.storage != PFLBM_FP16_DEV)
+    return set_error(PFLBM_EUNSUPPORTED, "scales exist for FP16-deviation storage only");
+  if (h->group) return set_error(PFLBM_ESTATE, "case is a group member");
+  const double want[2] = {scale_f, scale_g};
+  for (int k = 0; k < 2; ++k) {
+    int e;
+    if (!(want[k] > 0.0) || !std::isfinite(want[k]) || std::frexp(want[k], &e) != 0.5 ||
+        e < -60 || e > 60)
+      return set_error(PFLBM_EINVAL, "scales must be powers of two (got %g)", want[k]);
+  }
+  float* scale[2] = {&h->dv.phys.scale_f, &h->dv.phys.scale_g};
+  for (int k = 0; k < 2; ++k) {
+    const double factor = want[k] / (double)*scale[k];
+    if (factor == 1.0) continue;
+    int rc = run_rescale(h, k, (float)factor);
+    if (rc) return rc;
+    *scale[k] = (float)want[k];
+  }
+  PFLBM_HIP(hipStreamSynchronize(h->stream));
+  drop_graph(h);
   return PFLBM_OK;
 }
 

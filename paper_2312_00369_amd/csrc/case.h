@@ -27,7 +27,7 @@ void clear_error();
   } while (0)
 
 struct Layout {
-  size_t nodes, f[2], g[2], s, phi, mu, snap, partial, rec, total;
+  size_t nodes, f[2], g[2], s, phi, mu, snap, partial, rec, popmax, total;
   size_t f_bytes, g_bytes;   // one f buffer, one g buffer
   size_t c_bytes;     // one compute-type field
   long long nparts;   // reduction partial records
@@ -72,6 +72,7 @@ struct pflbm_case_s {
   void* snap = nullptr;
   double* partial = nullptr;
   double* rec = nullptr;
+  float* popmax = nullptr;        // kPopmaxBlocks (f, g) pairs
   std::vector<uint8_t> classes;   // host copy of the domain classes
   int cur = 0;                    // buffer holding the current post-collision state
   int64_t step = 0;
@@ -125,7 +126,16 @@ struct LatticeEntry {
   int (*reduce)(pflbm_case_s*, int);
   int (*group_step)(const GroupLaunch&, int, int*);
   int (*group_diag)(const GroupLaunch&, int, int, int, int, double*, double*, int, int);
+  int (*popmax)(pflbm_case_s*);
+  int (*rescale)(pflbm_case_s*, int, float);
 };
+constexpr int kPopmaxBlocks = 64;   // workgroups of the stored-magnitude reduction
+// FP16-deviation storage: keeps each set's largest stored magnitude in a safe
+// band by moving its scale by a power of two (rescaling the current buffer);
+// *changed (may be NULL) is set when a scale moved.  No-op for other storage.
+int fp16_upkeep(pflbm_case_s* h, int* changed);
+int run_popmax(pflbm_case_s* h, float out[2]);
+int run_rescale(pflbm_case_s* h, int set_g, float factor);
 // Contact-angle fit and flags from a reduction record.
 void finish_diag(const pflbm_case_s* h, const double* rec, pflbm_diag* d);
 }  // namespace pflbm

@@ -1,5 +1,7 @@
 // Kernel launchers for one case or a group, dispatched on the lattice (each
 // lattice's launchers live in engine_<lattice>.hip) and the storage type.
+#include <algorithm>
+
 #include "case.h"
 
 namespace pflbm {
@@ -38,6 +40,25 @@ int run_group_diag(const GroupLaunch& gl, int parity, int tx, int ty, int tz, do
 
 int run_step_group(const GroupLaunch& gl, int parity, int* occupancy_blocks) {
   PFLBM_ENTRY(gl.lattice) return e->group_step(gl, parity, occupancy_blocks);
+}
+
+int run_popmax(pflbm_case_s* h, float out[2]) {
+  PFLBM_ENTRY(h->prm.lattice)
+  int rc = e->popmax(h);
+  if (rc) return rc;
+  float part[2 * kPopmaxBlocks];
+  PFLBM_HIP(hipMemcpyAsync(part, h->popmax, sizeof part, hipMemcpyDeviceToHost, h->stream));
+  PFLBM_HIP(hipStreamSynchronize(h->stream));
+  out[0] = out[1] = 0.0f;
+  for (int b = 0; b < kPopmaxBlocks; ++b) {
+    out[0] = std::max(out[0], part[2 * b]);
+    out[1] = std::max(out[1], part[2 * b + 1]);
+  }
+  return PFLBM_OK;
+}
+
+int run_rescale(pflbm_case_s* h, int set_g, float factor) {
+  PFLBM_ENTRY(h->prm.lattice) return e->rescale(h, set_g, factor);
 }
 
 #undef PFLBM_ENTRY

@@ -338,8 +338,30 @@ struct LatticeImpl {
     return by_storage<GDiag>(gl.storage, &gl, parity, tx, ty, tz, partial, out, ncases,
                              update_snap);
   }
+  // FP16-deviation storage: per-workgroup maxima of the stored magnitudes
+  // (kPopmaxBlocks pairs in h->popmax), and the in-place rescale of one set.
+  static int popmax(pflbm_case_s* h) {
+    const int c = h->cur;
+    hipLaunchKernelGGL((k_popmax<L>), dim3(kPopmaxBlocks), dim3(256), 0, h->stream, h->nodes,
+                       h->f[c], h->g[c], h->dv.N, h->popmax);
+    PFLBM_HIP(hipGetLastError());
+    return PFLBM_OK;
+  }
+  static int rescale(pflbm_case_s* h, int set_g, float factor) {
+    const long long nblocks = h->dv.geo.NQ / kBlk;
+    void* buf = set_g ? h->g[h->cur] : h->f[h->cur];
+    if (set_g)
+      hipLaunchKernelGGL((k_rescale_half<L::G::Q, true>), dim3(1024), dim3(256), 0, h->stream, buf,
+                         nblocks, factor);
+    else
+      hipLaunchKernelGGL((k_rescale_half<L::Q, false>), dim3(1024), dim3(256), 0, h->stream, buf,
+                         nblocks, factor);
+    PFLBM_HIP(hipGetLastError());
+    return PFLBM_OK;
+  }
   static const LatticeEntry* entry() {
-    static const LatticeEntry e = {phi, mu, collide, step, init_g, reduce, group_step, group_diag};
+    static const LatticeEntry e = {phi, mu, collide, step, init_g, reduce, group_step, group_diag,
+                                   popmax, rescale};
     return &e;
   }
 };

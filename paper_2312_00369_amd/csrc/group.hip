@@ -382,6 +382,13 @@ int pflbm_group_poll(pflbm_group g, pflbm_diag* d, int32_t* flags, int32_t capac
     if (d) d[k] = tmp;
     if (flags) flags[k] = (tmp.steady ? 1 : 0) | (tmp.nonfinite ? 2 : 0);
   }
+  // FP16 scale upkeep per member; a moved scale reaches the kernels through the
+  // member descriptors, which the next step rebuilds
+  for (int k = 0; k < nc; ++k) {
+    int changed = 0;
+    if ((rc = fp16_upkeep(g->members[k], &changed))) return rc;
+    if (changed) g->dirty = true;
+  }
   return PFLBM_OK;
 }
 

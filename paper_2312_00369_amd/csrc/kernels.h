@@ -1325,6 +1325,62 @@ __global__ void k_reduce_final(const double* __restrict__ partial, long long npa
 }
 
 
+// ------------------------------------------------------------------ FP16 scale upkeep
+// FP16-deviation storage keeps value * 2^k.  At diagnostics the host checks the
+// largest stored magnitude of each set and, when it leaves a safe band, moves
+// the scale by a power of two and rescales the stored populations in place.
+
+// Largest stored magnitude |h| of the moving populations of f and of g over
+// zeta = 1 nodes; one (f, g) pair per workgroup of 256 (grid-stride over the
+// node slots).  Non-finite values are reported by the diagnostics record.
+template <class L>
+__global__ __launch_bounds__(256) void k_popmax(const uint32_t* __restrict__ nodes,
+                                                const void* __restrict__ fbuf,
+                                                const void* __restrict__ gbuf, long long nslots,
+                                                float* __restrict__ partial) {
+  using FS = Set<kF16Dev, false, L::Q>;
+  using GS = Set<kF16Dev, true, L::G::Q>;
+  double mf = 0.0, mg = 0.0;
+  for (long long n = blockIdx.x * 256LL + threadIdx.x; n < nslots; n += 256LL * gridDim.x) {
+    if (!(nodes[n] & kZeta)) continue;
+    for (int i = 1; i < L::Q; ++i)
+      mf = fmax(mf, (double)fabsf(__half2float(*FS::at(fbuf, i, (nidx)n))));
+    for (int i = 1; i < L::G::Q; ++i)
+      mg = fmax(mg, (double)fabsf(__half2float(*GS::at(gbuf, i, (nidx)n))));
+  }
+  mf = wave_max(mf);
+  mg = wave_max(mg);
+  __shared__ double red[4][2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wv][0] = mf;
+    red[wv][1] = mg;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double v = red[0][threadIdx.x];
+    for (int j = 1; j < 4; ++j) v = fmax(v, red[j][threadIdx.x]);
+    partial[2 * blockIdx.x + threadIdx.x] = (float)v;
+  }
+}
+
+// Multiplies every stored moving population of one FP16 set of Q populations
+// (g set when G) by factor, a power of two: exact unless the result leaves the
+// FP16 normal range.
+template <int Q, bool G>
+__global__ __launch_bounds__(256) void k_rescale_half(void* __restrict__ buf, long long nblocks,
+                                                      float factor) {
+  using SetT = Set<kF16Dev, G, Q>;
+  const long long per = (long long)(Q - 1) * kBlk;
+  const long long total = nblocks * per;
+  for (long long j = blockIdx.x * 256LL + threadIdx.x; j < total; j += 256LL * gridDim.x) {
+    const long long b = j / per, r = j % per;
+    __half* p = reinterpret_cast<__half*>(static_cast<unsigned char*>(buf) +
+                                          b * (long long)SetT::kBlockBytes + SetT::kRestBytes) + r;
+    *p = __float2half_rn(__half2float(*p) * factor);
+  }
+}
+
 // ------------------------------------------------------------------ batched diagnostics
 // For a group poll: phi of every member (same arithmetic as k_phi), then one
 // partial record per table entry, then per member a fixed-order sum of its

@@ -93,6 +93,8 @@ def _load():
         "pflbm_set_step_kernel": (ct.c_int, [vp, i32]),
         "pflbm_step_variants": (ct.c_int, [i32, vp, i32]),
         "pflbm_set_step_options": (ct.c_int, [vp, i32, i32]),
+        "pflbm_fp16_scales": (ct.c_int, [vp, vp, vp]),
+        "pflbm_set_fp16_scales": (ct.c_int, [vp, ct.c_double, ct.c_double]),
         "pflbm_fields": (ct.c_int, [vp, vp, vp, vp, vp]),
         "pflbm_node_classes": (ct.c_int, [vp, vp]),
         "pflbm_diagnostics": (ct.c_int, [vp, P(pflbm_diag)]),
@@ -266,6 +268,16 @@ class Case:
 
     def set_tile(self, tx, ty, tz=1):
         _check(lib.pflbm_set_tile(self.h, tx, ty, tz), "pflbm_set_tile")
+
+    def fp16_scales(self):
+        """(scale_f, scale_g) of FP16-deviation storage (1, 1 otherwise)."""
+        sf, sg = ct.c_double(0), ct.c_double(0)
+        _check(lib.pflbm_fp16_scales(self.h, ct.byref(sf), ct.byref(sg)), "pflbm_fp16_scales")
+        return sf.value, sg.value
+
+    def set_fp16_scales(self, scale_f, scale_g):
+        _check(lib.pflbm_set_fp16_scales(self.h, float(scale_f), float(scale_g)),
+               "pflbm_set_fp16_scales")
 
     def set_step_options(self, xcd_order=True, nontemporal=False):
         _check(lib.pflbm_set_step_options(self.h, int(bool(xcd_order)), int(bool(nontemporal))),

@@ -3,6 +3,7 @@
 Tolerances: FP64 storage |dphi|_inf <= 1e-10 (rounding order only); FP32 storage
 |dphi|_inf <= 1e-5 against the FP64 oracle; contact angle within 0.5 degrees.
 """
+import math
 import os
 
 import numpy as np
@@ -325,3 +326,38 @@ def test_fp16dev_config0_error_statement(P):
           f"vs {float(gold['theta']):.4f}")
     assert err <= 1e-4
     assert abs(d["theta_deg"] - float(gold["theta"])) <= 0.5
+
+
+def test_fp16_scale_rescale_and_upkeep(P):
+    """FP16-deviation scales (powers of two per set): raising a scale rescales the
+    stored state exactly; scales pushed out of band are moved back into it by
+    diagnostics without changing the fields; the run then continues within the
+    FP16 error of an untouched run.  Bad scales and other storage are refused."""
+    c = workloads.inclined_droplet_case_3d(n=20, radius=6.0, theta=60.0, width=4.0)
+    a = P.Case.from_case(c, "f16dev")
+    b = P.Case.from_case(c, "f16dev")
+    a.step(40)
+    b.step(40)
+    sf, sg = a.fp16_scales()
+    f0 = a.fields()
+    a.set_fp16_scales(2 * sf, 2 * sg)               # exact
+    assert a.fp16_scales() == (2 * sf, 2 * sg)
+    assert np.array_equal(a.fields()["phi"], f0["phi"])
+    a.set_fp16_scales(sf / 64, sg / 64)              # largest stored magnitude far below band
+    f1 = a.fields()
+    assert maxdiff(f1["phi"], f0["phi"]) < 1e-5
+    a.diagnostics()                                   # moves both scales up by a power of two
+    sf2, sg2 = a.fp16_scales()
+    assert sf2 > sf / 64 and sg2 > sg / 64
+    assert math.log2(sf2).is_integer() and math.log2(sg2).is_integer()
+    assert np.array_equal(a.fields()["phi"], f1["phi"])
+    a.step(100)
+    b.step(100)
+    zeta = _zeta(a)
+    err = maxdiff(a.fields()["phi"], b.fields()["phi"], zeta)
+    print(f"FP16 rescaled run vs untouched run after 100 steps: |dphi|_inf {err:.2e}")
+    assert err < 1e-4
+    with pytest.raises(P.PflbmError):
+        a.set_fp16_scales(3.0, sg2)
+    with pytest.raises(P.PflbmError):
+        P.Case.from_case(c, "f32").set_fp16_scales(1.0, 1.0)
