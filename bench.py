@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--sections", default="main,twin,3d,batched,serve,cpu",
                     help="comma list of: main (the 1024x512 line), twin (8192x4096), 3d "
                          "(256^3 D3Q19), batched (64 cases), serve (Poisson serving), cpu "
-                         "(oracle baseline); the JSON line always carries the main figures")
+                         "(oracle baseline), table1 (the Sec. 3.1 angle sweep, not in the "
+                         "default); the JSON line always carries the main figures")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
@@ -59,6 +60,7 @@ def parse():
     ap.add_argument("--serve-alone-sample", type=int, default=3000)
     ap.add_argument("--serve-util70", type=int, default=1)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--table1-max-steps", type=int, default=3000000)
     ap.add_argument("--batch-steps", type=int, default=1000)
     a = ap.parse_args()
     a.sec = set(s.strip() for s in a.sections.split(",") if s.strip())
@@ -192,6 +194,48 @@ def batched(a, torch, P, workloads, stream):
             "nonfinite_cases": int(sum(1 for f in flags if f & 2))}
 
 
+def table1(a, torch, P, workloads):
+    """The flat-plate test of Sec. 3.1 in 2D: the eleven prescribed angles of
+    Table 1 advance together as one group until every theta has moved less than
+    0.02 degrees over the last 100k steps (or the step cap); reports the
+    measured equilibrium angles next to the paper's."""
+    import json as _json
+    paper = _json.load(open(os.path.join(ROOT, "tests", "golden", "table1_2d_paper.json")))
+    cs = [workloads.table1_case(t) for t in workloads.TABLE1_ANGLES]
+    g = P.Group()
+    ms = [P.Case.from_case(c, "f32") for c in cs]
+    for m in ms:
+        g.add(m)
+    g.set_graph_chunk(1000)
+    chunk, hist, steps = 50000, [], 0
+    t0 = time.perf_counter()
+    while steps < a.table1_max_steps:
+        g.step(chunk)
+        steps += chunk
+        diags, _ = g.poll()
+        hist.append([d["theta_deg"] for d in diags])
+        if len(hist) >= 3 and all(abs(x - y) < 0.02 for x, y in zip(hist[-1], hist[-3])):
+            break
+        if steps % 250000 == 0:
+            progress(f"table1: {steps} steps")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nodes = sum(int((m.classes() & 1).sum()) for m in ms)
+    rows = []
+    for th, got, pap in zip(workloads.TABLE1_ANGLES, hist[-1], paper["paper_2d_deg"]):
+        rows.append({"prescribed": th, "measured": round(got, 2), "error": round(got - th, 2),
+                     "paper": pap, "paper_error": round(pap - th, 2)})
+    for m in ms:
+        g.remove(m)
+        m.close()
+    g.close()
+    return {"workload": "Sec. 3.1 flat plate, D2Q9 FP32 256x128, eleven angles in one group",
+            "steps": steps, "wall_s": round(wall, 1),
+            "group_MLUPS": round(nodes * steps / wall / 1e6, 1), "angles": rows,
+            "max_abs_error_10_to_160": round(max(abs(r["error"]) for r in rows
+                                                 if r["prescribed"] <= 160), 2)}
+
+
 def progress(msg):
     """One line per finished stage on stderr (the JSON result goes to stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -308,6 +352,10 @@ def main():
     if "serve" in a.sec:
         with torch.cuda.stream(stream):
             line["served"] = served(a, torch, P, workloads)
+    if "table1" in a.sec:
+        with torch.cuda.stream(stream):
+            line["table1_2d"] = table1(a, torch, P, workloads)
+        progress("table1 done")
     if "cpu" in a.sec:
         line["cpu_baseline"] = cpu_baseline(workloads.config1(theta=a.theta))
         progress("cpu baseline done")

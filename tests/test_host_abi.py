@@ -150,3 +150,19 @@ def test_d3q7_phase_lattice_params_and_footprint(P):
     with pytest.raises(ValueError):
         P.params_from_case(dict(workloads.flat_droplet_case(32, 16, 5.0, 60.0),
                                 phase_lattice="D3Q7"), "f32")
+
+
+def test_table1_case_geometry():
+    """The Sec. 3.1 flat-plate input: a plate 0.25 Ny thick, 0.05 Ny above the
+    lower edge, periodic everywhere, droplet centred on the wall plane (one node
+    inside the plate's top surface) with R = 50, 40 at 20 deg and 30 at 10 deg."""
+    import json
+    c = workloads.table1_case(60.0)
+    rows = np.where(c["mask"].any(axis=1))[0]
+    assert rows.min() == 6 and rows.max() == 37 and c["mask"][6:38].all()
+    assert c["periodic"] == (True, True) and c["wall"]["point"][1] == 36.5
+    assert c["mobility"] == 0.01 and c["sigma"] == 0.005 and c["width"] == 4.0
+    assert [workloads.table1_case(t)["radius"] for t in (10.0, 20.0, 30.0)] == [30.0, 40.0, 50.0]
+    paper = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                        "table1_2d_paper.json")))
+    assert paper["prescribed_deg"] == [int(t) for t in workloads.TABLE1_ANGLES]

@@ -164,6 +164,27 @@ def config3(seed=3, n_cases=64):
     return out
 
 
+TABLE1_ANGLES = (10.0, 20.0, 30.0, 40.0, 60.0, 90.0, 120.0, 140.0, 150.0, 160.0, 170.0)
+
+
+def table1_case(theta, nx=256, ny=128):
+    """The flat-plate test of Sec. 3.1 (Table 1, 2D): nx x ny, periodic on all
+    sides, a solid plate 0.25 ny thick whose bottom lies 0.05 ny above the
+    lower edge, a semicircular droplet of radius 50 (40 at 20 deg, 30 at 10 deg)
+    centred on the plate's wall plane; rho 10/1, nu 0.1 (tau 0.8), sigma 0.005,
+    M 0.01, W 4."""
+    y_lo, thick = round(0.05 * ny), round(0.25 * ny)
+    mask = np.zeros((ny, nx), dtype=np.uint8)
+    mask[y_lo:y_lo + thick, :] = 1
+    y_wall = y_lo + thick - 1.5          # the top solid row moved half a node into the solid
+    R = {10.0: 30.0, 20.0: 40.0}.get(float(theta), 50.0) * ny / 128.0
+    phi0 = droplet((nx, ny), (nx / 2.0, y_wall), R, 4.0)
+    wall = dict(kind="plane", point=(0.0, y_wall), normal=(0.0, 1.0))
+    c = _case("D2Q9", (nx, ny), (True, True), mask, phi0, theta, 0.005, 4.0, wall)
+    c.update(mobility=0.01, storage="f32", radius=R, name=f"table1-{int(theta)}")
+    return c
+
+
 def serving_request(rng, idx, nx_range=(256, 1024), n3_range=(64, 192)):
     """One request of the serving workload: 2D (256x128 .. 1024x512) or 3D
     (64^3 .. 192^3), geometry flat / inclined / curved, theta ~ U[30, 150]."""
