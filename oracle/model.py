@@ -304,6 +304,12 @@ class Oracle:
         F = mu[None, :] * grad_phi + Fb
         mom = np.einsum("qd,qn->dn", L.c.astype(np.float64), self.f) + 0.5 * F
         u = np.where(self.zeta, mom / np.where(self.zeta, rho, 1.0), 0.0)
+        # READING: a boundary node is a solid node (Sec. 2.2.2): it collides and
+        # streams, but its velocity is the wall's, so u = 0 there wherever u
+        # enters (f_eq, F_i, p, s).  With the fluid velocity at these nodes
+        # instead, a row-alternating momentum mode along the wall grows slowly
+        # at sigma = 0.005 (the Sec. 3.1 parameters) until it breaks the drop.
+        u[:, self.boundary] = 0.0
         uu = (u ** 2).sum(axis=0)
         s0 = -L.w[0] * uu / (2.0 * L.cs2)
         pres = L.cs2 / (1.0 - L.w[0]) * (self.f[1:].sum(axis=0)

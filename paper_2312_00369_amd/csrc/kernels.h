@@ -347,12 +347,15 @@ __global__ void k_mu(const uint32_t* __restrict__ nodes, C* __restrict__ phi,
 
 // ------------------------------------------------------------------ node update
 // Macroscopic quantities of one node from its pulled f, phi, mu and grad phi:
-// rho, F = mu grad phi + F_b, u and p (Sec. 2.1.2), s = u . grad phi.
+// rho, F = mu grad phi + F_b, u and p (Sec. 2.1.2), s = u . grad phi; u = 0 on
+// boundary nodes (they lie in the solid: no slip).
 template <class L, int S>
 struct Macro {
   using C = ComputeT<S>;
   C rho, rx, ry, rz, Fx, Fy, Fz, ux, uy, uz, uu, ugr, p, s;
-  __device__ Macro(const C* f, C ph, C m, C gx, C gy, C gz, const Phys& P) {
+  // wall: a boundary node (zeta = 1, not fluid).  It lies in the solid, so its
+  // velocity is the wall's: u = 0 wherever u enters (f_eq, F_i, p, s).
+  __device__ Macro(const C* f, C ph, C m, C gx, C gy, C gz, bool wall, const Phys& P) {
     constexpr int Q = L::Q;
     const C inv_cs2 = C(3);
     const C drho = C(P.rho_l - P.rho_g);
@@ -372,9 +375,9 @@ struct Macro {
       sumf += f[i];
     }
     const C inv_rho = C(1) / rho;
-    ux = (mx + C(0.5) * Fx) * inv_rho;
-    uy = (my + C(0.5) * Fy) * inv_rho;
-    uz = (mz + C(0.5) * Fz) * inv_rho;
+    ux = wall ? C(0) : (mx + C(0.5) * Fx) * inv_rho;
+    uy = wall ? C(0) : (my + C(0.5) * Fy) * inv_rho;
+    uz = wall ? C(0) : (mz + C(0.5) * Fz) * inv_rho;
     uu = ux * ux + uy * uy + uz * uz;
     ugr = ux * rx + uy * ry + uz * rz;                             // u . grad rho
     const C w0 = C(L::w(0));
@@ -395,13 +398,13 @@ struct Macro {
 template <class L, int S, class GetSp, class PutG0, class PutG, class PutF>
 __device__ inline ComputeT<S> collide_post(const ComputeT<S>* f, double g0, const ComputeT<S>* g,
                                            ComputeT<S> ph, ComputeT<S> m, ComputeT<S> gx,
-                                           ComputeT<S> gy, ComputeT<S> gz, const Phys& P,
-                                           GetSp&& get_sp, PutG0&& put_g0, PutG&& put_g,
+                                           ComputeT<S> gy, ComputeT<S> gz, bool wall,
+                                           const Phys& P, GetSp&& get_sp, PutG0&& put_g0, PutG&& put_g,
                                            PutF&& put_f) {
   using C = ComputeT<S>;
   constexpr int Q = L::Q;
   const C inv_cs2 = C(3);
-  const Macro<L, S> M(f, ph, m, gx, gy, gz, P);
+  const Macro<L, S> M(f, ph, m, gx, gy, gz, wall, P);
   using LG = typename L::G;          // velocity set of g
   const C w0 = C(LG::w(0));
   const C sp = get_sp();
@@ -452,7 +455,7 @@ __device__ inline ComputeT<S> collide_post(const ComputeT<S>* f, double g0, cons
 template <class L, int S, int MODE, bool O = false>
 __device__ inline void node_update(const ComputeT<S>* f, double g0, const ComputeT<S>* g,
                                    ComputeT<S> ph, ComputeT<S> m, ComputeT<S> gx,
-                                   ComputeT<S> gy, ComputeT<S> gz, nidx n,
+                                   ComputeT<S> gy, ComputeT<S> gz, uint32_t word, nidx n,
                                    void* __restrict__ fdst, void* __restrict__ gdst,
                                    ComputeT<S>* __restrict__ sprev, ComputeT<S>* __restrict__ out_p,
                                    ComputeT<S>* __restrict__ out_u, const Geo& G, const Phys& P,
@@ -461,7 +464,7 @@ __device__ inline void node_update(const ComputeT<S>* f, double g0, const Comput
   using FS = Set<S, false, L::Q, O>;
   using GS = Set<S, true, L::G::Q, O>;
   if (MODE == 1 || MODE == 2) {
-    const Macro<L, S> M(f, ph, m, gx, gy, gz, P);
+    const Macro<L, S> M(f, ph, m, gx, gy, gz, !(word & kFluid), P);
     if (MODE == 1) {
       out_p[n] = M.p;
       out_u[n] = M.ux;
@@ -473,7 +476,8 @@ __device__ inline void node_update(const ComputeT<S>* f, double g0, const Comput
     return;
   }
   const C s = collide_post<L, S>(
-      f, g0, g, ph, m, gx, gy, gz, P, [&]() { return (MODE == 3) ? sp_pre : sprev[n]; },
+      f, g0, g, ph, m, gx, gy, gz, !(word & kFluid), P,
+      [&]() { return (MODE == 3) ? sp_pre : sprev[n]; },
       [&](double v) { GS::store_rest(gdst, n, v, nt); },
       [&](int i, C v) { GS::store(gdst, i, n, v, P.scale_g, nt); },
       [&](int i, C v) {
@@ -513,7 +517,7 @@ __global__ void k_collide(const uint32_t* __restrict__ nodes, const void* __rest
   }
   C gx, gy, gz;
   grad_of<L, C>([&](int i) { return phi[nb[i]]; }, gx, gy, gz);
-  node_update<L, S, MODE>(f, g0, g, phi[n], mu[n], gx, gy, gz, n, fdst, gdst, sprev, out_p,
+  node_update<L, S, MODE>(f, g0, g, phi[n], mu[n], gx, gy, gz, word, n, fdst, gdst, sprev, out_p,
                           out_u, G, P);
 }
 
@@ -690,7 +694,7 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
     C gx, gy, gz;
     grad_of<L, C>([&](int i) { return sphi[t + L::cx(i) + SX * L::cy(i) + SXY * L::cz(i)]; },
                   gx, gy, gz);
-    node_update<L, S, 0, O>(f, g0r[k], gr[k], sphi[t], m, gx, gy, gz, n, fdst, gdst, sprev,
+    node_update<L, S, 0, O>(f, g0r[k], gr[k], sphi[t], m, gx, gy, gz, w, n, fdst, gdst, sprev,
                          nullptr, nullptr, G, P, P.nt_store);
   }
 }
@@ -815,7 +819,7 @@ __device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __rest
   C gx, gy, gz;
   grad_of<L, C>([&](int i) { return sphi[t + L::cx(i) + SX * L::cy(i) + SXY * L::cz(i)]; },
                 gx, gy, gz);
-  node_update<L, S, 0, O>(f, g0, g, sphi[t], m, gx, gy, gz, n, fdst, gdst, sprev, nullptr, nullptr,
+  node_update<L, S, 0, O>(f, g0, g, sphi[t], m, gx, gy, gz, w, n, fdst, gdst, sprev, nullptr, nullptr,
                        G, P, P.nt_store);
 }
 
@@ -1011,7 +1015,7 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
                     av * C(P.wet) * (ph - ph * ph);
         C gx, gy, gz;
         grad_of<L, C>([&](int i) { return sphi[at(i)]; }, gx, gy, gz);
-        node_update<L, S, 0, O>(f, g0, g, ph, m, gx, gy, gz, n, fdst, gdst, sprev, nullptr,
+        node_update<L, S, 0, O>(f, g0, g, ph, m, gx, gy, gz, w, n, fdst, gdst, sprev, nullptr,
                              nullptr, G, P, P.nt_store);
       }
     }

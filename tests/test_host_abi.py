@@ -154,8 +154,9 @@ def test_d3q7_phase_lattice_params_and_footprint(P):
 
 def test_table1_case_geometry():
     """The Sec. 3.1 flat-plate input: a plate 0.25 Ny thick, 0.05 Ny above the
-    lower edge, periodic everywhere, droplet centred on the wall plane (one node
-    inside the plate's top surface) with R = 50, 40 at 20 deg and 30 at 10 deg."""
+    lower edge, periodic everywhere, a semicircular droplet centred on the wall
+    plane (half a node below the plate's top row) with R = 50, 40 at 20 deg and
+    30 at 10 deg."""
     import json
     c = workloads.table1_case(60.0)
     rows = np.where(c["mask"].any(axis=1))[0]
@@ -163,6 +164,12 @@ def test_table1_case_geometry():
     assert c["periodic"] == (True, True) and c["wall"]["point"][1] == 36.5
     assert c["mobility"] == 0.01 and c["sigma"] == 0.005 and c["width"] == 4.0
     assert [workloads.table1_case(t)["radius"] for t in (10.0, 20.0, 30.0)] == [30.0, 40.0, 50.0]
+    # a semicircle: nothing below the plate's top row (its underside boundary
+    # nodes and the gas under the plate start dry); the top row and above hold
+    # the circle's upper half
+    phi0 = c["phi0"]
+    assert phi0[:37].max() == 0.0
+    assert phi0[37, 128] > 0.99 and phi0[37 + 49, 128] > 0.5 > phi0[37 + 52, 128]
     paper = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
                                         "table1_2d_paper.json")))
     assert paper["prescribed_deg"] == [int(t) for t in workloads.TABLE1_ANGLES]

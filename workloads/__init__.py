@@ -179,6 +179,10 @@ def table1_case(theta, nx=256, ny=128):
     y_wall = y_lo + thick - 1.5          # the top solid row moved half a node into the solid
     R = {10.0: 30.0, 20.0: 40.0}.get(float(theta), 50.0) * ny / 128.0
     phi0 = droplet((nx, ny), (nx / 2.0, y_wall), R, 4.0)
+    # a semicircle: every row below the plate's top row is cleared, so that the
+    # lower half of the circle puts no liquid on the plate's underside boundary
+    # nodes or in the gas below the plate
+    phi0[:y_lo + thick - 1, :] = 0.0
     wall = dict(kind="plane", point=(0.0, y_wall), normal=(0.0, 1.0))
     c = _case("D2Q9", (nx, ny), (True, True), mask, phi0, theta, 0.005, 4.0, wall)
     c.update(mobility=0.01, storage="f32", radius=R, name=f"table1-{int(theta)}")
