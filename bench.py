@@ -43,8 +43,9 @@ def parse():
     ap.add_argument("--sections", default="main,twin,3d,batched,serve,cpu",
                     help="comma list of: main (the 1024x512 line), twin (8192x4096), 3d "
                          "(256^3 D3Q19), batched (64 cases), serve (Poisson serving), cpu "
-                         "(oracle baseline), table1 (the Sec. 3.1 angle sweep, not in the "
-                         "default); the JSON line always carries the main figures")
+                         "(oracle baseline); not in the default: table1 (the Sec. 3.1 angle "
+                         "sweep), appendixA (the chi cases of Table A1); the JSON line always "
+                         "carries the main figures")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
@@ -61,6 +62,8 @@ def parse():
     ap.add_argument("--serve-util70", type=int, default=1)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--table1-max-steps", type=int, default=12000000)
+    ap.add_argument("--appendix-a-marks", type=lambda v: [int(x) for x in v.split(",")],
+                    default=[100000, 300000, 1000000, 3000000, 6000000])
     ap.add_argument("--batch-steps", type=int, default=1000)
     a = ap.parse_args()
     a.sec = set(s.strip() for s in a.sections.split(",") if s.strip())
@@ -241,6 +244,47 @@ def table1(a, torch, P, workloads):
                                                  if r["prescribed"] <= 160), 2)}
 
 
+def appendix_a(a, torch, P, workloads):
+    """Appendix A, Fig. A1: the drop of Sec. 3.1 spreading under the three
+    (chi, mu) pairs of Table A1 at theta = 60 and 120 degrees, six cases in one
+    group; reports theta at a few times for each pair (the paper's claim is
+    that the three pairs evolve alike)."""
+    combos = [(th, k) for th in (60.0, 120.0) for k in (1, 2, 3)]
+    ms = []
+    g = P.Group()
+    for th, k in combos:
+        c = workloads.table1_case(th)
+        c["chi_case"] = k
+        m = P.Case.from_case(c, "f32")
+        g.add(m)
+        ms.append(m)
+    g.set_graph_chunk(1000)
+    marks, steps, t0 = {}, 0, time.perf_counter()
+    for target in a.appendix_a_marks:
+        g.step(target - steps)
+        steps = target
+        diags, _ = g.poll()
+        marks[str(steps)] = [round(d["theta_deg"], 2) for d in diags]
+        progress(f"appendix A: {steps} steps")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for m in ms:
+        g.remove(m)
+        m.close()
+    g.close()
+    out = {"workload": "Sec. 3.1 plate 256x128 D2Q9 FP32, theta 60 and 120, chi cases 1/2/3 "
+                       "of Table A1 in one group", "wall_s": round(wall, 1), "theta": {}}
+    for j, (th, k) in enumerate(combos):
+        out["theta"][f"theta{int(th)}_case{k}"] = {s_: v[j] for s_, v in marks.items()}
+    spread = {}
+    for th in (60.0, 120.0):
+        idx = [j for j, (t_, _) in enumerate(combos) if t_ == th]
+        spread[f"theta{int(th)}"] = {s_: round(max(v[j] for j in idx) - min(v[j] for j in idx), 2)
+                                     for s_, v in marks.items()}
+    out["spread_across_cases_deg"] = spread
+    return out
+
+
 def progress(msg):
     """One line per finished stage on stderr (the JSON result goes to stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -361,6 +405,10 @@ def main():
         with torch.cuda.stream(stream):
             line["table1_2d"] = table1(a, torch, P, workloads)
         progress("table1 done")
+    if "appendixA" in a.sec:
+        with torch.cuda.stream(stream):
+            line["appendix_a"] = appendix_a(a, torch, P, workloads)
+        progress("appendix A done")
     if "cpu" in a.sec:
         line["cpu_baseline"] = cpu_baseline(workloads.config1(theta=a.theta))
         progress("cpu baseline done")

@@ -72,6 +72,13 @@ enum { PFLBM_WALL_NONE = 0, PFLBM_WALL_PLANE = 1, PFLBM_WALL_BALL = 2 };
  *                 (centre + radius); interface points closer than diag_width to
  *                 it are left out of the fit
  *  steady_tol     max |phi(t) - phi(t_prev_diag)| below which a case is steady
+ *  chi_case       the (chi, mu) pairs of Appendix A, Table A1, with
+ *                 chi(phi) = c sqrt(2 beta/kappa) cos(theta) (phi - phi^2) in the
+ *                 ghost rule n_w . grad phi = chi (Eq. cubicc) and the wall term of mu
+ *                 scaled by (1 + c): case 1 c = -1, case 2 (or 0) c = 0, case 3
+ *                 c = +1.  Cases 1 and 3 need every ghost node to face the fluid
+ *                 along one lattice axis (flat axis-aligned walls); pflbm_create
+ *                 returns PFLBM_EUNSUPPORTED otherwise.
  */
 typedef struct pflbm_params {
   uint32_t struct_size;          /* = sizeof(pflbm_params) */
@@ -84,6 +91,8 @@ typedef struct pflbm_params {
   int32_t wall_kind;             /* PFLBM_WALL_* */
   double wall_point[3], wall_normal[3], wall_radius, diag_width;
   double steady_tol;
+  int32_t chi_case;              /* Appendix A, Table A1: 0 or 2 = the method (chi = 0),
+                                    1 = cubic Robin ghost rule, 3 = its opposite */
 } pflbm_params;
 
 /* Diagnostics record (all reductions in FP64 over zeta = 1 nodes). */

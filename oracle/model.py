@@ -58,6 +58,7 @@ class Params:
     nu_l: float = 0.0
     nu_g: float = 0.0
     theta_deg: float = 60.0
+    chi_case: int = 2                 # Appendix A, Table A1: 1, 2 (the method) or 3
     body_force: tuple = (0.0, 0.0, 0.0)
     extra: dict = field(default_factory=dict)
 
@@ -173,10 +174,20 @@ def effective_area(grid, L, eps, zeta):
     return np.where(zeta, np.sqrt((g ** 2).sum(axis=0)), 0.0)
 
 
-def ghost_fill(grid, phi, zeta, ghost):
+def ghost_fill(grid, phi, zeta, ghost, chi_a=0.0):
     """Sec. 2.2.2: phi at a ghost node is the mean of phi over the zeta = 1 nodes
     of its 3^D neighbourhood (9 offsets in 2D, 27 in 3D).  Only zeta = 1 values
-    enter, so the fill order does not matter."""
+    enter, so the fill order does not matter.
+
+    chi_a != 0 (Appendix A, cases 1 and 3): the ghost instead satisfies
+    Eq. (cubicc), n_w . grad phi = chi(phi_w) with chi(phi) = chi_a (phi - phi^2),
+    as a central difference across the wall.  READING: the mean above stands for
+    phi at the ghost's mirror node (one lattice spacing away along an axis-aligned
+    normal; ghost_normals checks that), and phi_w is the mean of the two values.
+    With m the mirror value and g the ghost value, m - g = chi((m + g)/2); in
+    terms of phi_w = (m + g)/2 this is
+        chi_a phi_w^2 - (chi_a + 2) phi_w + 2 m = 0,
+    whose root that tends to m as chi_a -> 0 is taken; then g = 2 phi_w - m."""
     num = np.zeros(grid.N)
     den = np.zeros(grid.N)
     for c in lat.ghost_neighbourhood(grid.D):
@@ -186,8 +197,34 @@ def ghost_fill(grid, phi, zeta, ghost):
         den += z
     out = np.where(zeta, phi, 0.0)
     sel = ghost & (den > 0)
-    out[sel] = num[sel] / den[sel]
+    m = num[sel] / den[sel]
+    if chi_a != 0.0:
+        a = chi_a
+        phi_w = ((a + 2.0) - np.sqrt((a + 2.0) ** 2 - 8.0 * a * m)) / (2.0 * a)
+        m = 2.0 * phi_w - m
+    out[sel] = m
     return out
+
+
+def ghost_normals(grid, zeta, ghost):
+    """Direction from each ghost node into the fluid: the sum of the offsets of
+    the zeta = 1 nodes in its 3^D neighbourhood (zero rows for non-ghosts)."""
+    n = np.zeros((grid.D, grid.N))
+    for c in lat.ghost_neighbourhood(grid.D):
+        nb, ok = grid.shift(c)
+        z = (ok & zeta[nb]).astype(np.float64)
+        for d in range(grid.D):
+            n[d] += z * c[d]
+    n[:, ~ghost] = 0.0
+    return n
+
+
+def chi_coefficient(beta, kappa, theta_deg, chi_case):
+    """chi_a of chi(phi) = chi_a (phi - phi^2) in Appendix A, Table A1:
+    case 1 -sqrt(2 beta/kappa) cos(theta), case 2 zero, case 3 the opposite of
+    case 1."""
+    c = {1: -1.0, 2: 0.0, 3: 1.0}[int(chi_case)]
+    return c * math.sqrt(2.0 * beta / kappa) * math.cos(math.radians(theta_deg))
 
 
 # ---------------------------------------------------------------- local physics
@@ -227,10 +264,14 @@ def phase_source(L, s):
     return (L.w * L.k)[:, None] * s[None, :]
 
 
-def chemical_potential(beta, kappa, theta_deg, phi, lap_phi, a_v):
+def chemical_potential(beta, kappa, theta_deg, phi, lap_phi, a_v, chi_case=2):
     """Eq. (chemical_potencial2): mu = 4 beta phi (phi-1)(phi-1/2) - kappa lap phi
-    - a_v sqrt(2 kappa beta) cos(theta) (phi - phi^2)."""
+    - a_v sqrt(2 kappa beta) cos(theta) (phi - phi^2).  Cases 1 and 3 of
+    Appendix A use Eq. (chemical_potencial112) with their chi: the wall term is
+    a_v [kappa chi + sqrt(2 kappa beta) cos(theta) (phi - phi^2)], i.e. zero
+    (case 1) or twice the above (case 3)."""
     wet = math.sqrt(2.0 * kappa * beta) * math.cos(math.radians(theta_deg))
+    wet *= {1: 0.0, 2: 1.0, 3: 2.0}[int(chi_case)]
     return (4.0 * beta * phi * (phi - 1.0) * (phi - 0.5) - kappa * lap_phi
             - a_v * wet * (phi - phi * phi))
 
@@ -255,6 +296,14 @@ class Oracle:
         self.zeta, self.eps, self.ghost, self.boundary = classify(
             self.grid, self.L, solid_mask)
         self.a_v = effective_area(self.grid, self.L, self.eps, self.zeta)
+        self.chi_a = chi_coefficient(params.beta, params.kappa, params.theta_deg,
+                                     params.chi_case)
+        if params.chi_case != 2:
+            # Appendix A tests these cases on a flat plate: every ghost must see
+            # the fluid along one lattice axis
+            n = ghost_normals(self.grid, self.zeta, self.ghost)[:, self.ghost]
+            if (np.count_nonzero(n, axis=0) != 1).any():
+                raise ValueError("chi cases 1 and 3 need walls normal to a lattice axis")
         self.tau_g = params.tau_phi if params.tau_phi > 0 else params.tau
         # Eq. (mobility): M = c_s^2 alpha (tau_g - 1/2), c_s^2 of the phase
         # lattice.  READING: tau_g is the given relaxation time and alpha
@@ -285,9 +334,10 @@ class Oracle:
 
     def _mu(self, phi):
         p = self.p
-        phi_full = ghost_fill(self.grid, phi, self.zeta, self.ghost)
+        phi_full = ghost_fill(self.grid, phi, self.zeta, self.ghost, self.chi_a)
         lap = laplacian(self.grid, self.L, phi_full)
-        mu = chemical_potential(p.beta, p.kappa, p.theta_deg, phi_full, lap, self.a_v)
+        mu = chemical_potential(p.beta, p.kappa, p.theta_deg, phi_full, lap, self.a_v,
+                                p.chi_case)
         mu = np.where(self.zeta, mu, 0.0)
         return mu, phi_full, lap
 

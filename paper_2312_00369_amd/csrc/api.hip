@@ -56,6 +56,8 @@ int validate_and_derive(const pflbm_params* p, Derived* d) {
   if (!(p->theta_deg > 0.0 && p->theta_deg < 180.0))
     return set_error(PFLBM_EINVAL, "theta must lie in (0, 180) degrees (got %g)", p->theta_deg);
   if (p->wall_kind < 0 || p->wall_kind > 2) return set_error(PFLBM_EINVAL, "bad wall_kind");
+  if (p->chi_case < 0 || p->chi_case > 3)
+    return set_error(PFLBM_EINVAL, "chi_case must be 0..3 (got %d)", p->chi_case);
 
   d->D = D;
   d->Q = D == 2 ? 9 : 19;
@@ -89,6 +91,13 @@ int validate_and_derive(const pflbm_params* p, Derived* d) {
   ph.kappa = p->kappa;
   // wall coefficient of Eq. (chemical_potencial2): sqrt(2 kappa beta) cos(theta)
   ph.wet = std::sqrt(2.0 * p->kappa * p->beta) * std::cos(p->theta_deg * M_PI / 180.0);
+  // Appendix A: chi = c sqrt(2 beta/kappa) cos(theta) (phi - phi^2) in the ghost
+  // rule, and the wall term of Eq. (chemical_potencial112) becomes (1 + c) wet
+  {
+    const double c = p->chi_case == 1 ? -1.0 : (p->chi_case == 3 ? 1.0 : 0.0);
+    ph.chi_a = c * std::sqrt(2.0 * p->beta / p->kappa) * std::cos(p->theta_deg * M_PI / 180.0);
+    ph.wet *= 1.0 + c;
+  }
   ph.rho_l = p->rho_l;
   ph.rho_g = p->rho_g;
   ph.nu_l = p->nu_l;
@@ -254,6 +263,41 @@ static void classify_t(const Derived& d, const uint8_t* mask, std::vector<uint32
   }
 }
 
+// The ghost rule of Appendix A cases 1 and 3 puts the ghost's mirror node one
+// spacing away along the wall normal, which holds where every ghost node sees
+// the zeta = 1 nodes of its 3^D block along one lattice axis (the sum of their
+// offsets has one nonzero component).
+int check_axis_ghosts(const Derived& d, const std::vector<uint32_t>& words) {
+  const Geo& G = d.geo;
+  const int P3[3] = {G.PX, G.PY, G.PZ};
+  const int dz = d.D == 3 ? 1 : 0;
+  for (int z = 0; z < G.PZ; ++z)
+    for (int y = 0; y < G.PY; ++y)
+      for (int x = 0; x < G.PX; ++x) {
+        if (!(words[G.idx(x, y, z)] & kGhost)) continue;
+        int s[3] = {0, 0, 0};
+        for (int c = -dz; c <= dz; ++c)
+          for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a) {
+              int q[3] = {x + a, y + b, z + c}, ok = 1;
+              for (int k = 0; k < 3; ++k) {
+                if (G.per[k]) q[k] = ((q[k] % P3[k]) + P3[k]) % P3[k];
+                else if (q[k] < 0 || q[k] >= P3[k]) ok = 0;
+              }
+              if (ok && (words[G.idx(q[0], q[1], q[2])] & kZeta)) {
+                s[0] += a;
+                s[1] += b;
+                s[2] += c;
+              }
+            }
+        if ((s[0] != 0) + (s[1] != 0) + (s[2] != 0) != 1)
+          return set_error(PFLBM_EUNSUPPORTED,
+                           "chi cases 1 and 3 need walls normal to a lattice axis; ghost "
+                           "node (%d, %d, %d) is not", x, y, z);
+      }
+  return PFLBM_OK;
+}
+
 void classify_nodes(const Derived& d, const uint8_t* mask, std::vector<uint32_t>& words,
                     uint8_t* classes) {
   if (d.D == 2) classify_t<D2Q9>(d, mask, words, classes);
@@ -370,6 +414,7 @@ int create_common(const pflbm_params* prm, const uint8_t* mask, const double* ph
   std::vector<uint32_t> words;
   h->classes.assign((size_t)prm->nx * prm->ny * prm->nz, 0);
   classify_nodes(dv, mask, words, h->classes.data());
+  if (dv.phys.chi_a != 0.0 && (rc = check_axis_ghosts(dv, words))) return fail(rc);
 #define CK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return fail(set_error(PFLBM_EDEVICE, "%s: %s", #x, hipGetErrorString(e_))); } while (0)
   CK(hipMemsetAsync(h->base, 0, L.total, h->stream));
   CK(hipMemcpyAsync(h->nodes, words.data(), words.size() * 4, hipMemcpyHostToDevice, h->stream));

@@ -44,6 +44,7 @@ struct Geo {
 
 struct Phys {
   double tau, inv_tau_g, alpha, beta, kappa, wet, rho_l, rho_g, nu_l, nu_g;
+  double chi_a;            // chi(phi) = chi_a (phi - phi^2) of the ghost rule; 0 = mean only
   double Fb[3];
   int visc_var;
   float scale_f, scale_g;  // FP16 codec: stored = value * scale (power of two)
@@ -218,10 +219,27 @@ __global__ void k_phi(const uint32_t* __restrict__ nodes, const void* __restrict
 // ------------------------------------------------------------------ LDS stencil pieces
 // A tile of phi and node words in LDS with strides sx (x) and sxy (x*y).
 
-// Ghost mean over the 3^D block (Sec. 2.2.2); only zeta = 1 entries are read,
+// Ghost value from the mean m of the zeta = 1 nodes around it.  chi_a = 0: m
+// itself (Sec. 2.2.2, zero normal gradient).  Otherwise (Appendix A, cases 1
+// and 3) the ghost g meets n_w . grad phi = chi(phi_w) across the wall, m
+// standing for the mirror node one spacing away: m - g = chi((m + g)/2) with
+// chi(phi) = a (phi - phi^2).  With phi_w = (m + g)/2 that is
+// a phi_w^2 - (a + 2) phi_w + 2 m = 0; the root tending to m as a -> 0 is
+// taken (a negative discriminant is clamped to zero), and g = 2 phi_w - m.
+template <class C>
+__device__ inline C ghost_value(C m, C a) {
+  if (a == C(0)) return m;
+  const C b = a + C(2);
+  const C disc = b * b - C(8) * a * m;
+  const C w = (b - sqrt(disc > C(0) ? disc : C(0))) / (C(2) * a);
+  return C(2) * w - m;
+}
+
+// Ghost value over the 3^D block (Sec. 2.2.2); only zeta = 1 entries are read,
 // so filling ghosts in place is order-independent.
 template <class L, class C>
-__device__ inline C ghost_mean(const C* sphi, const uint32_t* sw, int t, int sx, int sxy) {
+__device__ inline C ghost_mean(const C* sphi, const uint32_t* sw, int t, int sx, int sxy,
+                               C chi_a) {
   C num = C(0);
   int den = 0;
   constexpr int z0 = (L::D == 3) ? -1 : 0, z1 = (L::D == 3) ? 1 : 0;
@@ -237,7 +255,7 @@ __device__ inline C ghost_mean(const C* sphi, const uint32_t* sw, int t, int sx,
           ++den;
         }
       }
-  return den > 0 ? num / C(den) : C(0);
+  return den > 0 ? ghost_value(num / C(den), chi_a) : C(0);
 }
 
 // mu of Eq. (chemical_potencial2) at a zeta = 1 entry: isotropic Laplacian
@@ -332,7 +350,7 @@ __global__ void k_mu(const uint32_t* __restrict__ nodes, C* __restrict__ phi,
     const int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
     const bool inner = lx >= 1 && lx < LX - 1 && ly >= 1 && ly < LY - 1 &&
                        (L::D == 2 || (lz >= 1 && lz < LZ - 1));
-    if (inner && (sw[t] & kGhost)) sphi[t] = ghost_mean<L, C>(sphi, sw, t, LX, LX * LY);
+    if (inner && (sw[t] & kGhost)) sphi[t] = ghost_mean<L, C>(sphi, sw, t, LX, LX * LY, C(P.chi_a));
   }
   __syncthreads();
 
@@ -669,7 +687,7 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
     for (int m = tid; m < N1; m += NT) {
       const int lx = 1 + m % H1X, ly = 1 + (m / H1X) % H1Y, lz = (D3 ? 1 : 0) + m / (H1X * H1Y);
       const int t = lx + SX * ly + SXY * lz;
-      if (sw[t] & kGhost) sphi[t] = ghost_mean<L, C>(sphi, sw, t, SX, SXY);
+      if (sw[t] & kGhost) sphi[t] = ghost_mean<L, C>(sphi, sw, t, SX, SXY, C(P.chi_a));
     }
     __syncthreads();
   }
@@ -794,7 +812,7 @@ __device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __rest
     for (int m = tid; m < N1; m += NT) {
       const int lx = 1 + m % H1X, ly = 1 + (m / H1X) % H1Y, lz = (D3 ? 1 : 0) + m / (H1X * H1Y);
       const int t = lx + SX * ly + SXY * lz;
-      if (sw[t] & kGhost) sphi[t] = ghost_mean<L, C>(sphi, sw, t, SX, SXY);
+      if (sw[t] & kGhost) sphi[t] = ghost_mean<L, C>(sphi, sw, t, SX, SXY, C(P.chi_a));
     }
     __syncthreads();
   }
@@ -956,7 +974,7 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
               ++den;
             }
           }
-      if (den > 0) sphi[s0 + t] = num / C(den);
+      if (den > 0) sphi[s0 + t] = ghost_value(num / C(den), C(P.chi_a));
     }
   };
   for (int z = z0 - 2; z <= z0 + 1; ++z) load_plane(z);

@@ -51,6 +51,7 @@ class pflbm_params(ct.Structure):
         ("wall_point", ct.c_double * 3), ("wall_normal", ct.c_double * 3),
         ("wall_radius", ct.c_double), ("diag_width", ct.c_double),
         ("steady_tol", ct.c_double),
+        ("chi_case", ct.c_int32),
     ]
 
 
@@ -143,7 +144,8 @@ def beta_kappa(sigma, width):
 
 def make_params(lattice, shape, periodic, theta_deg, beta, kappa, storage="f32", tau=0.8,
                 tau_phi=0.0, mobility=0.1, rho_l=10.0, rho_g=1.0, nu_l=0.0, nu_g=0.0,
-                body_force=(0.0, 0.0, 0.0), wall=None, diag_width=4.0, steady_tol=1e-5):
+                body_force=(0.0, 0.0, 0.0), wall=None, diag_width=4.0, steady_tol=1e-5,
+                chi_case=2):
     p = pflbm_params()
     p.struct_size = ct.sizeof(pflbm_params)
     p.lattice = LATTICE[lattice]
@@ -174,6 +176,7 @@ def make_params(lattice, shape, periodic, theta_deg, beta, kappa, storage="f32",
         p.wall_radius = wall["radius"]
     p.diag_width = diag_width
     p.steady_tol = steady_tol
+    p.chi_case = int(chi_case)
     return p
 
 
@@ -182,7 +185,8 @@ def params_from_case(c, storage=None, **over):
     beta, kappa = beta_kappa(c["sigma"], c["width"])
     kw = dict(storage=storage or c.get("storage", "f32"), tau=c.get("tau", 0.8),
               mobility=c.get("mobility", 0.1), rho_l=c.get("rho_l", 10.0),
-              rho_g=c.get("rho_g", 1.0), wall=c.get("wall"), diag_width=c["width"])
+              rho_g=c.get("rho_g", 1.0), wall=c.get("wall"), diag_width=c["width"],
+              chi_case=c.get("chi_case", 2))
     kw.update(over)
     return make_params(case_lattice(c), c["shape"], c["periodic"], c["theta_deg"], beta, kappa,
                        **kw)

@@ -361,3 +361,70 @@ def test_fp16_scale_rescale_and_upkeep(P):
         a.set_fp16_scales(3.0, sg2)
     with pytest.raises(P.PflbmError):
         P.Case.from_case(c, "f32").set_fp16_scales(1.0, 1.0)
+
+
+@pytest.mark.parametrize("chi_case", [1, 3])
+def test_parity_chi_cases_fp64(P, chi_case):
+    """Appendix A cases 1 and 3: the ghost rule of Eq. (cubicc) and the wall term
+    of Eq. (chemical_potencial112) scaled by 0 or 2, against the oracle in FP64
+    (ragged 67 x 37 tiles; ghost values compared too)."""
+    c = workloads.flat_droplet_case(67, 37, 11.0, 60.0, 4.0)
+    c["chi_case"] = chi_case
+    g = P.Case.from_case(c, "f64")
+    o = oracle_for(c)
+    zeta = _zeta(g)
+    ghost = (g.classes() & 4).astype(bool)
+    for k in range(4):
+        g.step(50)
+        o.step(50)
+        gf, of = g.fields(), o.fields()
+        _compare(gf, of, zeta, 1e-12, 1e-12)
+        assert maxdiff(gf["phi"], of["phi"], ghost) <= 1e-12
+
+
+def _flat_3d(chi_case, n=(24, 20, 18)):
+    shape = n
+    mask = workloads.flat_walls(shape)
+    phi0 = workloads.droplet(shape, (n[0] / 2, n[1] / 2, -0.5), 6.0, 4.0)
+    wall = dict(kind="plane", point=(0.0, 0.0, -0.5), normal=(0.0, 0.0, 1.0))
+    c = workloads._case("D3Q19", shape, (True, True, False), mask, phi0, 120.0, 1e-3, 4.0, wall)
+    c["chi_case"] = chi_case
+    return c
+
+
+@pytest.mark.parametrize("lattice,chi_case", [("D2Q9", 1), ("D2Q9", 3), ("D3Q19", 1),
+                                              ("D3Q19", 3)])
+def test_chi_cases_every_step_variant_bitwise(P, lattice, chi_case):
+    """Every step kernel applies the same ghost rule: FP32 fields bit-identical
+    to the three-kernel path for cases 1 and 3, in 2D and 3D; the 3D case is
+    also checked against the oracle (FP32 storage, 1e-5)."""
+    if lattice == "D2Q9":
+        c = workloads.flat_droplet_case(70, 21, 6.0, 120.0, 4.0)
+        c["chi_case"] = chi_case
+    else:
+        c = _flat_3d(chi_case)
+    ref = P.Case.from_case(c, "f32")
+    ref.set_step_kernel(-1)
+    ref.step(30)
+    fr = ref.fields()
+    for v in range(len(P.step_variants(lattice))):
+        g = P.Case.from_case(c, "f32")
+        g.set_step_kernel(v)
+        g.step(30)
+        f = g.fields()
+        for k in ("phi", "p", "u", "mu"):
+            assert np.array_equal(f[k], fr[k]), (v, k)
+    if lattice == "D3Q19":
+        o = oracle_for(c)
+        o.step(30)
+        assert maxdiff(fr["phi"], o.fields()["phi"], _zeta(ref)) < 1e-5
+
+
+def test_chi_cases_refuse_curved_walls(P):
+    """Cases 1 and 3 need axis-aligned walls: a cylinder is refused at creation."""
+    c = workloads.cylinder_case(64, 32, 0.3, 100.0)
+    c["chi_case"] = 1
+    with pytest.raises(P.PflbmError):
+        P.Case.from_case(c, "f32")
+    c["chi_case"] = 2
+    P.Case.from_case(c, "f32").close()

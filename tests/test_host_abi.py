@@ -95,7 +95,8 @@ def _params(P, **kw):
     ("tau", 0.5, -1), ("mobility", 0.0, -1), ("theta_deg", 0.0, -1),
     ("theta_deg", 180.0, -1), ("beta", -1.0, -1), ("rho_g", 0.0, -1),
     ("lattice", 7, -6), ("storage", 9, -6), ("nx", 0, -1), ("nz", 3, -1),
-    ("struct_size", 8, -1), ("tau_phi", 0.4, -1), ("wall_kind", 5, -1)])
+    ("struct_size", 8, -1), ("tau_phi", 0.4, -1), ("wall_kind", 5, -1), ("chi_case", 4, -1),
+    ("chi_case", -1, -1)])
 def test_parameter_validation(P, field, value, code):
     prm = _params(P)
     setattr(prm, field, value)

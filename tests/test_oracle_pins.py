@@ -531,3 +531,56 @@ def test_linear_cahn_hilliard_decay_rate(lattice, phase):
     K = 2 * (1 - math.cos(k))
     theory = M * k * k * (beta * (12 * phi0 ** 2 - 12 * phi0 + 2) + kappa * K)
     assert abs(rate / theory - 1) < 0.02, (rate, theory)
+
+
+@pytest.mark.parametrize("chi_case,theta", [(1, 120.0), (3, 60.0)])
+def test_chi_cases_keep_the_cap(chi_case, theta):
+    """Appendix A: the (chi, mu) pairs of Table A1 give the same wetting.  Under
+    case 1 (cubic Robin ghost rule, no wall term in mu) and case 3 (the opposite
+    chi, twice the wall term) the paper's equilibrium cap stays at the
+    prescribed angle, as under the method (case 2, pinned above).  A sign slip
+    in chi or in the wall factor moves it by tens of degrees."""
+    W, sigma = 4.0, 1e-2
+    c = _cap_case(96, 48, 15.0, theta, theta, sigma, W)
+    c["chi_case"] = chi_case
+    o = oracle_for(c, mobility=0.2)
+    o.step(2500)
+    wall = dict(kind="plane", point=(0.0, -0.5), normal=(0.0, 1.0))
+    th = odiag.contact_angle(o.fields()["phi"], o.domain(o.zeta), wall, W)[0]
+    assert abs(th - theta) < 1.5, th
+
+
+def test_chi_case_one_moves_towards_theta():
+    """Case 1 alone (no wall term in mu): a 90 deg semicircle under theta = 60
+    spreads, so the wetting comes from the ghost rule."""
+    W, sigma = 4.0, 1e-2
+    c = _cap_case(96, 48, 15.0, 60.0, 90.0, sigma, W)
+    c["chi_case"] = 1
+    o = oracle_for(c, mobility=0.2)
+    o.step(2500)
+    wall = dict(kind="plane", point=(0.0, -0.5), normal=(0.0, 1.0))
+    th = odiag.contact_angle(o.fields()["phi"], o.domain(o.zeta), wall, W)[0]
+    assert th < 87.0, th
+
+
+def test_chi_ghost_rule_and_its_limits():
+    """The ghost value of cases 1 and 3 satisfies the central difference
+    m - g = chi((m + g)/2) of Eq. (cubicc); chi_a = 0 gives the plain mean, and
+    m = 0 or 1 (pure phases, chi = 0) leaves the mean unchanged."""
+    c = workloads.flat_droplet_case(24, 12, 5.0, 60.0, 4.0)
+    o = oracle_for(c)
+    rng = np.random.default_rng(3)
+    phi = np.where(o.zeta, rng.uniform(0.0, 1.0, o.grid.N), 0.0)
+    mean = om.ghost_fill(o.grid, phi, o.zeta, o.ghost)
+    for a in (-0.5, 0.3, 0.866):
+        g = om.ghost_fill(o.grid, phi, o.zeta, o.ghost, a)
+        m, gg = mean[o.ghost], g[o.ghost]
+        w = 0.5 * (m + gg)
+        assert np.abs((m - gg) - a * (w - w * w)).max() < 1e-14
+    pure = np.where(o.zeta, 1.0, 0.0)
+    assert np.abs(om.ghost_fill(o.grid, pure, o.zeta, o.ghost, 0.7)[o.ghost] - 1.0).max() < 1e-14
+    # curved walls are refused for cases 1 and 3
+    cyl = workloads.cylinder_case(64, 32, 0.3, 100.0)
+    cyl["chi_case"] = 1
+    with pytest.raises(ValueError):
+        oracle_for(cyl)
