@@ -44,7 +44,8 @@ def parse():
                     help="comma list of: main (the 1024x512 line), twin (8192x4096), 3d "
                          "(256^3 D3Q19), batched (64 cases), serve (Poisson serving), cpu "
                          "(oracle baseline); not in the default: table1 (the Sec. 3.1 angle "
-                         "sweep), appendixA (the chi cases of Table A1); the JSON line always "
+                         "sweep), incline2d (Sec. 3.2), cylinder2d (Sec. 3.3), appendixA (the "
+                         "chi cases of Table A1); the JSON line always "
                          "carries the main figures")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
@@ -62,6 +63,8 @@ def parse():
     ap.add_argument("--serve-util70", type=int, default=1)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--table1-max-steps", type=int, default=12000000)
+    ap.add_argument("--sweep-max-steps", type=int, default=4000000,
+                    help="step cap of the incline2d / cylinder2d sections")
     ap.add_argument("--appendix-a-marks", type=lambda v: [int(x) for x in v.split(",")],
                     default=[100000, 300000, 1000000, 3000000, 6000000])
     ap.add_argument("--batch-steps", type=int, default=1000)
@@ -244,6 +247,65 @@ def table1(a, torch, P, workloads):
                                                  if r["prescribed"] <= 160), 2)}
 
 
+def _angle_sweep(torch, P, cases, max_steps, chunk=100000, label="sweep"):
+    """Runs the cases as one group until every theta moved less than 0.02 deg
+    over the last two polls (2 chunks) or max_steps; returns the final angles,
+    a sparse history and the wall time."""
+    g = P.Group()
+    ms = [P.Case.from_case(c, "f32") for c in cases]
+    for m in ms:
+        g.add(m)
+    g.set_graph_chunk(1000)
+    hist, marks, steps, t0 = [], {}, 0, time.perf_counter()
+    while steps < max_steps:
+        g.step(chunk)
+        steps += chunk
+        diags, _ = g.poll()
+        hist.append([d["theta_deg"] for d in diags])
+        if steps in (500000, 1000000, 2000000, 4000000):
+            marks[str(steps)] = [round(t, 2) for t in hist[-1]]
+        if len(hist) >= 3 and all(abs(x - y) < 0.02 for x, y in zip(hist[-1], hist[-3])):
+            break
+        if steps % 500000 == 0:
+            progress(f"{label}: {steps} steps")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    marks[str(steps)] = [round(t, 2) for t in hist[-1]]
+    drift = [round(x - y, 3) for x, y in zip(hist[-1], hist[-3])] if len(hist) >= 3 else None
+    nodes = sum(int((m.classes() & 1).sum()) for m in ms)
+    for m in ms:
+        g.remove(m)
+        m.close()
+    g.close()
+    return dict(steps=steps, wall_s=round(wall, 1), group_MLUPS=round(nodes * steps / wall / 1e6, 1),
+                final=hist[-1], history=marks, drift_last_2_polls=drift)
+
+
+def incline_2d(a, torch, P, workloads):
+    """Sec. 3.2 in 2D: drops on the staircase incline y = slope x (slopes 1, 0.5,
+    0.25; theta 30..150; W = 4), plus W = 6 and 8 at slope 0.25 for theta = 90
+    and 120 (the paper's Fig. on the interface width), as one group."""
+    combos = [(s_, th, 4.0) for s_ in workloads.SEC32_SLOPES for th in workloads.SEC3_ANGLES]
+    combos += [(0.25, th, w) for w in (6.0, 8.0) for th in (90.0, 120.0)]
+    cs = [workloads.sec32_incline_case(th, s_, w) for s_, th, w in combos]
+    r = _angle_sweep(torch, P, cs, a.sweep_max_steps, label="incline2d")
+    rows = [{"slope": s_, "W": w, "prescribed": th, "measured": round(t, 2), "error": round(t - th, 2)}
+            for (s_, th, w), t in zip(combos, r.pop("final"))]
+    return dict(workload="Sec. 3.2 2D incline, 256x256 D2Q9 FP32, closed box, R = 50, "
+                         "sigma 0.005, M 0.01, rho 10/1, nu 0.1", angles=rows, **r)
+
+
+def cylinder_2d(a, torch, P, workloads):
+    """Sec. 3.3 in 2D: drops on a cylinder of R_s = 60 (W = 6), theta 30..150,
+    as one group; theta from the circle fit against the wall circle."""
+    cs = [workloads.sec33_cylinder_case(th) for th in workloads.SEC3_ANGLES]
+    r = _angle_sweep(torch, P, cs, a.sweep_max_steps, label="cylinder2d")
+    rows = [{"prescribed": th, "measured": round(t, 2), "error": round(t - th, 2)}
+            for th, t in zip(workloads.SEC3_ANGLES, r.pop("final"))]
+    return dict(workload="Sec. 3.3 2D cylinder R_s = 60, 256x256 D2Q9 FP32, R_i = 50, W = 6, "
+                         "sigma 0.005, M 0.01, rho 10/1, nu 0.1", angles=rows, **r)
+
+
 def appendix_a(a, torch, P, workloads):
     """Appendix A, Fig. A1: the drop of Sec. 3.1 spreading under the three
     (chi, mu) pairs of Table A1 at theta = 60 and 120 degrees, six cases in one
@@ -405,6 +467,14 @@ def main():
         with torch.cuda.stream(stream):
             line["table1_2d"] = table1(a, torch, P, workloads)
         progress("table1 done")
+    if "incline2d" in a.sec:
+        with torch.cuda.stream(stream):
+            line["incline_2d"] = incline_2d(a, torch, P, workloads)
+        progress("incline2d done")
+    if "cylinder2d" in a.sec:
+        with torch.cuda.stream(stream):
+            line["cylinder_2d"] = cylinder_2d(a, torch, P, workloads)
+        progress("cylinder2d done")
     if "appendixA" in a.sec:
         with torch.cuda.stream(stream):
             line["appendix_a"] = appendix_a(a, torch, P, workloads)

@@ -174,3 +174,31 @@ def test_table1_case_geometry():
     paper = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
                                         "table1_2d_paper.json")))
     assert paper["prescribed_deg"] == [int(t) for t in workloads.TABLE1_ANGLES]
+
+
+def test_sec3_incline_and_cylinder_geometry(P):
+    """The Sec. 3.2 and 3.3 inputs as the paper describes them: solid below
+    y = slope x with the drop centred on that line at x = Nx/2; a cylinder of
+    R_s = 60 centred at (Nx/2, Ny/2 - 50) with the drop centred at (Nx/2, Ny/2);
+    both classify, and the wall the angle is measured against is the line moved
+    one node into the solid / the circle of radius R_s - 1."""
+    import math
+    for slope in workloads.SEC32_SLOPES:
+        c = workloads.sec32_incline_case(60.0, slope)
+        m = c["mask"]
+        assert m.shape == (256, 256)
+        y, x = 100, 150
+        assert m[y, x] == (1 if y < slope * x else 0)
+        assert c["phi0"][int(round(slope * 128)) + 10, 128] > 0.99        # inside the drop
+        n = c["wall"]["normal"]
+        assert abs(math.hypot(*n) - 1) < 1e-12 and abs(n[1] / -n[0] - 1 / slope) < 1e-9
+        d = c["wall"]["point"][1] - slope * c["wall"]["point"][0]      # line offset of the plane
+        assert abs(abs(d) * math.cos(math.atan(slope)) - 1.0) < 1e-9 and d < 0
+        cls = P.classify(P.params_from_case(c, "f32"), m)
+        assert (cls & 1).sum() > 0 and ((cls & 2) > 0).sum() == (m == 0).sum()
+    c = workloads.sec33_cylinder_case(90.0)
+    m = c["mask"]
+    assert m[78, 128] == 1 and m[78 + 59, 128] == 1 and m[78 + 61, 128] == 0
+    assert c["wall"]["radius"] == 59.0 and c["width"] == 6.0 and c["mobility"] == 0.01
+    assert c["phi0"][160, 128] > 0.99 and c["phi0"][185, 128] < 0.01
+    assert P.classify(P.params_from_case(c, "f32"), m).any()

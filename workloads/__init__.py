@@ -148,6 +148,50 @@ def cylinder_case(nx, ny, rc_frac, theta, width=4.0, sigma=1e-3, drop_frac=0.3):
                  storage="f32", name=f"cyl-{nx}x{ny}")
 
 
+SEC32_SLOPES = (1.0, 0.5, 0.25)
+SEC3_ANGLES = (30.0, 60.0, 90.0, 120.0, 150.0)
+
+
+def sec32_incline_case(theta, slope, width=4.0, n=256):
+    """Sec. 3.2 in 2D: an n x n box, closed on all sides, solid below the line
+    y = slope x; a semicircular drop of R = 50 (scaled with n) centred on the
+    line at x = n/2.  The wall the angle is measured against is that line moved
+    one node into the solid along its normal (the bounce-back plane of flat
+    walls).  sigma = 0.005, M = 0.01, rho 10/1, nu 0.1 in both phases."""
+    shape = (n, n)
+    gam = math.atan(slope)
+    mask = inclined_plane(shape, (0.0, 0.0), math.degrees(gam))
+    nrm = (-math.sin(gam), math.cos(gam))
+    x0 = n / 2.0
+    R = 50.0 * n / 256.0
+    # the lower half of the circle lies in the solid, where only the boundary
+    # nodes (zeta = 1) read it
+    phi0 = droplet(shape, (x0, slope * x0), R, width)
+    wall = dict(kind="plane", point=(-nrm[0], -nrm[1]), normal=nrm)
+    c = _case("D2Q9", shape, (False, False), mask, phi0, theta, 0.005, width, wall)
+    c.update(mobility=0.01, storage="f32", radius=R,
+             name=f"sec32-slope{slope}-theta{int(theta)}-W{int(width)}")
+    return c
+
+
+def sec33_cylinder_case(theta, width=6.0, n=256):
+    """Sec. 3.3 in 2D: a solid cylinder of radius R_s = 60 centred at
+    (n/2, n/2 - 50) in an n x n box (scaled with n), periodic in x and closed in
+    y; a drop of R_i = 50 centred at (n/2, n/2), inside the cylinder's top (only
+    zeta = 1 nodes read phi0).  The wall circle of the angle fit has radius
+    R_s - 1.
+    sigma = 0.005, M = 0.01, rho 10/1, nu 0.1 in both phases, W = 6."""
+    shape = (n, n)
+    k = n / 256.0
+    rs, centre = 60.0 * k, (n / 2.0, n / 2.0 - 50.0 * k)
+    mask = ball(shape, centre, rs)
+    phi0 = droplet(shape, (n / 2.0, n / 2.0), 50.0 * k, width)
+    wall = dict(kind="circle", center=centre, radius=rs - 1.0)
+    c = _case("D2Q9", shape, (True, False), mask, phi0, theta, 0.005, width, wall)
+    c.update(mobility=0.01, storage="f32", name=f"sec33-cylinder-theta{int(theta)}")
+    return c
+
+
 def config3(seed=3, n_cases=64):
     """64 D2Q9 cylinder cases, sizes U{128..768 step 16} x half, R_c ~ U[0.2, 0.4] Ny,
     droplet 0.3 R_c, theta ~ U[30, 150] deg, W = 4, FP32."""
