@@ -261,6 +261,7 @@ def _angle_sweep(torch, P, cases, max_steps, chunk=100000, label="sweep"):
         g.step(chunk)
         steps += chunk
         diags, _ = g.poll()
+        last = diags
         hist.append([d["theta_deg"] for d in diags])
         if steps in (500000, 1000000, 2000000, 4000000):
             marks[str(steps)] = [round(t, 2) for t in hist[-1]]
@@ -278,7 +279,8 @@ def _angle_sweep(torch, P, cases, max_steps, chunk=100000, label="sweep"):
         m.close()
     g.close()
     return dict(steps=steps, wall_s=round(wall, 1), group_MLUPS=round(nodes * steps / wall / 1e6, 1),
-                final=hist[-1], history=marks, drift_last_2_polls=drift)
+                final=hist[-1], history=marks, drift_last_2_polls=drift,
+                fits=[(d["centre"], d["radius"]) for d in last])
 
 
 def incline_2d(a, torch, P, workloads):
@@ -291,6 +293,7 @@ def incline_2d(a, torch, P, workloads):
     r = _angle_sweep(torch, P, cs, a.sweep_max_steps, label="incline2d")
     rows = [{"slope": s_, "W": w, "prescribed": th, "measured": round(t, 2), "error": round(t - th, 2)}
             for (s_, th, w), t in zip(combos, r.pop("final"))]
+    r.pop("fits")
     return dict(workload="Sec. 3.2 2D incline, 256x256 D2Q9 FP32, closed box, R = 50, "
                          "sigma 0.005, M 0.01, rho 10/1, nu 0.1", angles=rows, **r)
 
@@ -298,10 +301,18 @@ def incline_2d(a, torch, P, workloads):
 def cylinder_2d(a, torch, P, workloads):
     """Sec. 3.3 in 2D: drops on a cylinder of R_s = 60 (W = 6), theta 30..150,
     as one group; theta from the circle fit against the wall circle."""
+    import math
     cs = [workloads.sec33_cylinder_case(th) for th in workloads.SEC3_ANGLES]
     r = _angle_sweep(torch, P, cs, a.sweep_max_steps, label="cylinder2d")
-    rows = [{"prescribed": th, "measured": round(t, 2), "error": round(t - th, 2)}
-            for th, t in zip(workloads.SEC3_ANGLES, r.pop("final"))]
+    rows = []
+    for c, th, t, (cen, R) in zip(cs, workloads.SEC3_ANGLES, r.pop("final"), r.pop("fits")):
+        # the same fitted circle against other readings of the wall radius
+        d = math.hypot(cen[0] - c["wall"]["center"][0], cen[1] - c["wall"]["center"][1])
+        alt = {}
+        for rw in (59.5, 60.0):
+            cs_ = (R * R + rw * rw - d * d) / (2.0 * R * rw)
+            alt[f"theta_vs_R{rw}"] = round(math.degrees(math.acos(max(-1.0, min(1.0, cs_)))), 2)
+        rows.append(dict(prescribed=th, measured=round(t, 2), error=round(t - th, 2), **alt))
     return dict(workload="Sec. 3.3 2D cylinder R_s = 60, 256x256 D2Q9 FP32, R_i = 50, W = 6, "
                          "sigma 0.005, M 0.01, rho 10/1, nu 0.1", angles=rows, **r)
 
