@@ -44,7 +44,8 @@ def parse():
                     help="comma list of: main (the 1024x512 line), twin (8192x4096), 3d "
                          "(256^3 D3Q19), batched (64 cases), serve (Poisson serving), cpu "
                          "(oracle baseline); not in the default: table1 (the Sec. 3.1 angle "
-                         "sweep), incline2d (Sec. 3.2), cylinder2d (Sec. 3.3), appendixA (the "
+                         "sweep), table1_3d (its 3D column at reduced size), incline2d (Sec. 3.2), "
+                         "cylinder2d (Sec. 3.3), appendixA (the "
                          "chi cases of Table A1); the JSON line always "
                          "carries the main figures")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -63,6 +64,10 @@ def parse():
     ap.add_argument("--serve-util70", type=int, default=1)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--table1-max-steps", type=int, default=12000000)
+    ap.add_argument("--table1-3d-shape", default="128x128x64")
+    ap.add_argument("--table1-3d-angles", type=lambda v: [float(x) for x in v.split(",")],
+                    default=[60.0, 90.0, 120.0, 140.0])
+    ap.add_argument("--table1-3d-max-steps", type=int, default=1200000)
     ap.add_argument("--sweep-max-steps", type=int, default=4000000,
                     help="step cap of the incline2d / cylinder2d sections")
     ap.add_argument("--appendix-a-marks", type=lambda v: [int(x) for x in v.split(",")],
@@ -257,6 +262,7 @@ def _angle_sweep(torch, P, cases, max_steps, chunk=100000, label="sweep"):
         g.add(m)
     g.set_graph_chunk(1000)
     hist, marks, steps, t0 = [], {}, 0, time.perf_counter()
+    t_said = t0
     while steps < max_steps:
         g.step(chunk)
         steps += chunk
@@ -267,8 +273,9 @@ def _angle_sweep(torch, P, cases, max_steps, chunk=100000, label="sweep"):
             marks[str(steps)] = [round(t, 2) for t in hist[-1]]
         if len(hist) >= 3 and all(abs(x - y) < 0.02 for x, y in zip(hist[-1], hist[-3])):
             break
-        if steps % 500000 == 0:
+        if time.perf_counter() - t_said > 30.0:
             progress(f"{label}: {steps} steps")
+            t_said = time.perf_counter()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     marks[str(steps)] = [round(t, 2) for t in hist[-1]]
@@ -315,6 +322,23 @@ def cylinder_2d(a, torch, P, workloads):
         rows.append(dict(prescribed=th, measured=round(t, 2), error=round(t - th, 2), **alt))
     return dict(workload="Sec. 3.3 2D cylinder R_s = 60, 256x256 D2Q9 FP32, R_i = 50, W = 6, "
                          "sigma 0.005, M 0.01, rho 10/1, nu 0.1", angles=rows, **r)
+
+
+def table1_3d(a, torch, P, workloads):
+    """Table 1, 3D column, at reduced size (default 128 x 128 x 64, R = 25):
+    the prescribed angles of a.table1_3d_angles as one group."""
+    import json as _json
+    n = tuple(int(v) for v in a.table1_3d_shape.split("x"))
+    paper = _json.load(open(os.path.join(ROOT, "tests", "golden", "table1_2d_paper.json")))
+    p3 = dict(zip(paper["prescribed_deg"], paper.get("paper_3d_deg", [None] * 11)))
+    cs = [workloads.table1_case_3d(th, n) for th in a.table1_3d_angles]
+    r = _angle_sweep(torch, P, cs, a.table1_3d_max_steps, label="table1_3d")
+    r.pop("fits")
+    rows = [{"prescribed": th, "measured": round(t, 2), "error": round(t - th, 2),
+             "paper_3d_at_256x256x128": p3.get(int(th))}
+            for th, t in zip(a.table1_3d_angles, r.pop("final"))]
+    return dict(workload=f"Sec. 3.1 plate in 3D at {n[0]}x{n[1]}x{n[2]}, D3Q19 FP32, "
+                         f"R = {cs[0]['radius']}, sigma 0.005, M 0.01, W 4", angles=rows, **r)
 
 
 def appendix_a(a, torch, P, workloads):
@@ -486,6 +510,10 @@ def main():
         with torch.cuda.stream(stream):
             line["cylinder_2d"] = cylinder_2d(a, torch, P, workloads)
         progress("cylinder2d done")
+    if "table1_3d" in a.sec:
+        with torch.cuda.stream(stream):
+            line["table1_3d"] = table1_3d(a, torch, P, workloads)
+        progress("table1_3d done")
     if "appendixA" in a.sec:
         with torch.cuda.stream(stream):
             line["appendix_a"] = appendix_a(a, torch, P, workloads)

@@ -202,3 +202,20 @@ def test_sec3_incline_and_cylinder_geometry(P):
     assert c["wall"]["radius"] == 59.0 and c["width"] == 6.0 and c["mobility"] == 0.01
     assert c["phi0"][160, 128] > 0.99 and c["phi0"][185, 128] < 0.01
     assert P.classify(P.params_from_case(c, "f32"), m).any()
+
+
+def test_table1_case_3d_geometry(P):
+    """The 3D plate of Sec. 3.1 (scaled): plate 0.25 Nz thick from 0.05 Nz, drop
+    centred at (Nx/2, Ny/2, 0.25 Nz) as printed, dry below the plate's top row;
+    classifies; the golden file carries the paper's 3D column."""
+    import json
+    c = workloads.table1_case_3d(90.0, (32, 32, 64))
+    m = c["mask"]
+    layers = np.where(m.any(axis=(1, 2)))[0]
+    assert layers.min() == 3 and layers.max() == 18 and m[3:19].all()
+    assert c["wall"]["point"][2] == 17.5 and c["radius"] == 25.0
+    assert c["phi0"][:18].max() == 0.0 and c["phi0"][18 + 5, 16, 16] > 0.99
+    assert P.classify(P.params_from_case(c, "f32"), m).any()
+    paper = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                        "table1_2d_paper.json")))
+    assert len(paper["paper_3d_deg"]) == len(paper["prescribed_deg"]) == 11

@@ -148,6 +148,26 @@ def cylinder_case(nx, ny, rc_frac, theta, width=4.0, sigma=1e-3, drop_frac=0.3):
                  storage="f32", name=f"cyl-{nx}x{ny}")
 
 
+def table1_case_3d(theta, n=(256, 256, 128)):
+    """The 3D flat-plate test of Sec. 3.1: Nx x Ny x Nz, periodic on every side,
+    D3Q19 FP32; the plate as in 2D (0.25 Nz thick, 0.05 Nz above the bottom) and
+    a drop of R = 50 (scaled with Nz / 128) centred at (Nx/2, Ny/2, 0.25 Nz), the
+    centre the paper prints; rows below the plate's top row start dry.  The wall
+    plane of the angle fit is half a node below the plate's top row."""
+    nx, ny, nz = n
+    z_lo, thick = round(0.05 * nz), round(0.25 * nz)
+    mask = np.zeros((nz, ny, nx), dtype=np.uint8)
+    mask[z_lo:z_lo + thick] = 1
+    z_wall = z_lo + thick - 1.5
+    R = {10.0: 30.0, 20.0: 40.0}.get(float(theta), 50.0) * nz / 128.0
+    phi0 = droplet(n, (nx / 2.0, ny / 2.0, 0.25 * nz), R, 4.0)
+    phi0[:z_lo + thick - 1] = 0.0
+    wall = dict(kind="plane", point=(0.0, 0.0, z_wall), normal=(0.0, 0.0, 1.0))
+    c = _case("D3Q19", n, (True, True, True), mask, phi0, theta, 0.005, 4.0, wall)
+    c.update(mobility=0.01, storage="f32", radius=R, name=f"table1-3d-{int(theta)}")
+    return c
+
+
 SEC32_SLOPES = (1.0, 0.5, 0.25)
 SEC3_ANGLES = (30.0, 60.0, 90.0, 120.0, 150.0)
 
