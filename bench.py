@@ -118,13 +118,13 @@ def measured_traffic(name, nodes):
 
 
 def inclined_3d(a, torch, P, workloads, stream):
-    """configs[2]: 256^3 D3Q19, 30-degree staircase wall, sphere R = 40, theta = 45;
+    """256^3 D3Q19, 30-degree staircase wall, sphere R = 40, theta = 45;
     FP32 against FP16-deviation storage (MLUPS, roofline at 313 / 165 B per node,
     and the FP16 field error against FP32 after the same steps)."""
     out = {}
     fields = {}
     for st, alg in (("f32", 313), ("f16dev", 165)):
-        c = workloads.config2(storage=st, n=256)
+        c = workloads.inclined_3d_256(storage=st, n=256)
         h = P.Case.from_case(c, st, stream=stream)
         h.set_graph_chunk(a.chunk_3d)
         nodes = int((h.classes() & 1).sum())
@@ -148,7 +148,7 @@ def inclined_3d(a, torch, P, workloads, stream):
     d7 = {}
     v7 = dict(zip(("f32", "f16dev"), (int(v) for v in str(a.variant_d3q7).split(","))))
     for st in ("f32", "f16dev"):
-        c = workloads.config2(storage=st, n=256)
+        c = workloads.inclined_3d_256(storage=st, n=256)
         c["phase_lattice"] = "D3Q7"
         h = P.Case.from_case(c, st, stream=stream)
         h.set_graph_chunk(a.chunk_3d)
@@ -167,7 +167,7 @@ def inclined_3d(a, torch, P, workloads, stream):
 def batched(a, torch, P, workloads, stream):
     """64 uneven D2Q9 cylinder cases: one after another (each with its own graph
     chunks) against one group (persistent batched kernel)."""
-    cases = workloads.config3()
+    cases = workloads.cylinder_batch()
     hs = [P.Case.from_case(c, "f32", stream=stream) for c in cases]
     nodes = sum(int((h.classes() & 1).sum()) for h in hs)
     K = a.batch_steps
@@ -399,7 +399,7 @@ def served(a, torch, P, workloads):
     from paper_2312_00369_amd.serve import GpuExecutor, Server
 
     def requests(n, rate, seed):
-        reqs = workloads.config4(seed=seed, n_requests=n, rate=rate, nx_range=(128, 256),
+        reqs = workloads.serving_requests(seed=seed, n_requests=n, rate=rate, nx_range=(128, 256),
                                  n3_range=(48, 48))
         for r in reqs:
             r["steady_tol"] = a.serve_tol
@@ -519,13 +519,13 @@ def main():
             line["appendix_a"] = appendix_a(a, torch, P, workloads)
         progress("appendix A done")
     if "cpu" in a.sec:
-        line["cpu_baseline"] = cpu_baseline(workloads.config1(theta=a.theta))
+        line["cpu_baseline"] = cpu_baseline(workloads.flat_1024x512_fp32(theta=a.theta))
         progress("cpu baseline done")
     print(json.dumps(line), flush=True)
 
 
 def run(a, torch, P, workloads, stream):
-    c = workloads.config1(theta=a.theta, nx=a.nx, ny=a.ny)
+    c = workloads.flat_1024x512_fp32(theta=a.theta, nx=a.nx, ny=a.ny)
     case = P.Case.from_case(c, "f32", stream=stream)
     case.set_graph_chunk(a.chunk)
     case.set_step_kernel(a.variant)
@@ -574,7 +574,7 @@ def run(a, torch, P, workloads, stream):
     progress("main done")
     if "twin" in a.sec:
         # DRAM-bound twin: 8192 x 4096 (33.5 M nodes), same physics
-        big = workloads.config1(theta=a.theta, nx=8192, ny=4096)
+        big = workloads.flat_1024x512_fp32(theta=a.theta, nx=8192, ny=4096)
         cb = P.Case.from_case(big, "f32", stream=stream)
         cb.set_graph_chunk(a.chunk)
         cb.set_step_kernel(a.variant)

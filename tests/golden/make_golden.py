@@ -18,8 +18,8 @@ from oracle import diagnostics as odiag  # noqa: E402
 from oracle.model import Oracle, Params, beta_kappa  # noqa: E402
 
 
-def config0_fp64(steps=5000, every=100):
-    c = workloads.config0()
+def flat_128x64_fp64(steps=5000, every=100):
+    c = workloads.flat_128x64_fp64()
     beta, kappa = beta_kappa(c["sigma"], c["width"])
     o = Oracle(Params(lattice="D2Q9", shape=c["shape"], periodic=c["periodic"], tau=0.8,
                       mobility=0.1, beta=beta, kappa=kappa, rho_l=10.0, rho_g=1.0,
@@ -31,11 +31,11 @@ def config0_fp64(steps=5000, every=100):
     f = o.fields()
     theta, centre, radius, npts = odiag.contact_angle(f["phi"], o.domain(o.zeta), c["wall"],
                                                       c["width"])
-    np.savez_compressed(os.path.join(HERE, "config0_fp64.npz"), phi=f["phi"], p=f["p"],
+    np.savez_compressed(os.path.join(HERE, "flat_128x64_fp64.npz"), phi=f["phi"], p=f["p"],
                         u=f["u"], mu=f["mu"], mass=np.array(mass), mass_every=every,
                         steps=steps, theta=theta, radius=radius, centre=centre)
-    print(f"config0: theta {theta:.4f} deg, R {radius:.4f}, points {npts}, mass {mass[-1]:.12f}")
+    print(f"flat 128x64 FP64: theta {theta:.4f} deg, R {radius:.4f}, points {npts}, mass {mass[-1]:.12f}")
 
 
 if __name__ == "__main__":
-    config0_fp64()
+    flat_128x64_fp64()

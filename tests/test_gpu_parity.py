@@ -30,7 +30,7 @@ def _compare(gf, of, zeta, tol_phi, tol_other):
 
 
 def test_init_fields_fp64(P):
-    c = workloads.config0()
+    c = workloads.flat_128x64_fp64()
     g = P.Case.from_case(c, "f64")
     o = oracle_for(c)
     zeta = _zeta(g)
@@ -58,11 +58,11 @@ def test_parity_fp64_short(P, shape, periodic):
         assert abs(g.diagnostics()["mass"] - o.mass()) <= 1e-11 * o.mass()
 
 
-def test_parity_fp64_config0_golden(P):
-    """configs[0]: 128x64 FP64, 5000 steps; fields and mass trajectory against the
+def test_parity_fp64_flat_128x64_golden(P):
+    """128x64 FP64 flat-wall droplet, 5000 steps; fields and mass trajectory against the
     stored oracle run (tests/golden/make_golden.py)."""
-    gold = np.load(os.path.join(GOLDEN, "config0_fp64.npz"), allow_pickle=False)
-    c = workloads.config0()
+    gold = np.load(os.path.join(GOLDEN, "flat_128x64_fp64.npz"), allow_pickle=False)
+    c = workloads.flat_128x64_fp64()
     g = P.Case.from_case(c, "f64")
     zeta = _zeta(g)
     every = int(gold["mass_every"])
@@ -81,9 +81,9 @@ def test_parity_fp64_config0_golden(P):
     assert abs(d["theta_deg"] - float(gold["theta"])) <= 0.5
 
 
-def test_parity_fp32_config0_golden(P):
-    gold = np.load(os.path.join(GOLDEN, "config0_fp64.npz"), allow_pickle=False)
-    c = workloads.config0()
+def test_parity_fp32_flat_128x64_golden(P):
+    gold = np.load(os.path.join(GOLDEN, "flat_128x64_fp64.npz"), allow_pickle=False)
+    c = workloads.flat_128x64_fp64()
     g = P.Case.from_case(c, "f32")
     zeta = _zeta(g)
     g.step(int(gold["steps"]))
@@ -154,7 +154,7 @@ def test_parity_d3q19_periodic_fp32(P):
 
 def test_mass_budget_identity(P):
     """M(t+1) - M(t) = -(1.5 S(t) - 0.5 S(t-1)) with S the sum of s over zeta = 1."""
-    c = workloads.config0()
+    c = workloads.flat_128x64_fp64()
     g = P.Case.from_case(c, "f64")
     g.step(100)
     d0 = g.diagnostics()
@@ -312,11 +312,11 @@ def test_parity_d3q19_fp32_and_fp16dev_vs_oracle(P, phase):
     assert errs["f16dev"] <= 2e-4
 
 
-def test_fp16dev_config0_error_statement(P):
-    """configs[0] geometry in FP16-deviation storage, 5000 steps, against the
+def test_fp16dev_flat_128x64_error_statement(P):
+    """The 128x64 flat-wall geometry in FP16-deviation storage, 5000 steps, against the
     stored FP64 oracle run: error stated and bounded."""
-    gold = np.load(os.path.join(GOLDEN, "config0_fp64.npz"), allow_pickle=False)
-    c = workloads.config0()
+    gold = np.load(os.path.join(GOLDEN, "flat_128x64_fp64.npz"), allow_pickle=False)
+    c = workloads.flat_128x64_fp64()
     g = P.Case.from_case(c, "f16dev")
     zeta = _zeta(g)
     g.step(int(gold["steps"]))

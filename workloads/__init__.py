@@ -98,14 +98,14 @@ def flat_droplet_case(nx=128, ny=64, radius=20.0, theta=60.0, width=4.0,
     return _case(lattice, shape, (True, False), mask, phi0, theta, sigma, width, wall)
 
 
-def config0():
+def flat_128x64_fp64():
     """128 x 64 D2Q9, FP64, R = 20, theta = 60 deg, W = 4, sigma = 1e-3, 5000 steps."""
     c = flat_droplet_case(128, 64, 20.0, 60.0, 4.0)
     c.update(storage="f64", steps=5000, name="flat-128x64-fp64")
     return c
 
 
-def config1(theta=60.0, nx=1024, ny=512):
+def flat_1024x512_fp32(theta=60.0, nx=1024, ny=512):
     """1024 x 512 D2Q9, FP32, R = 80 on a flat wall, W = 5; 50k steps."""
     c = flat_droplet_case(nx, ny, 80.0 * nx / 1024, theta, 5.0)
     c.update(storage="f32", steps=50000, name=f"flat-{nx}x{ny}-fp32-theta{int(theta)}")
@@ -130,7 +130,7 @@ def inclined_droplet_case_3d(n=256, radius=40.0, theta=45.0, angle=30.0, width=5
                  name=f"inclined-{n}^3-{storage}")
 
 
-def config2(storage="f32", n=256):
+def inclined_3d_256(storage="f32", n=256):
     return inclined_droplet_case_3d(n=n, radius=40.0 * n / 256, storage=storage)
 
 
@@ -212,7 +212,7 @@ def sec33_cylinder_case(theta, width=6.0, n=256):
     return c
 
 
-def config3(seed=3, n_cases=64):
+def cylinder_batch(seed=3, n_cases=64):
     """64 D2Q9 cylinder cases, sizes U{128..768 step 16} x half, R_c ~ U[0.2, 0.4] Ny,
     droplet 0.3 R_c, theta ~ U[30, 150] deg, W = 4, FP32."""
     rng = np.random.default_rng(seed)
@@ -300,7 +300,7 @@ def serving_request(rng, idx, nx_range=(256, 1024), n3_range=(64, 192)):
     return c
 
 
-def config4(seed=4, n_requests=200, rate=20.0, nx_range=(256, 1024), n3_range=(64, 192)):
+def serving_requests(seed=4, n_requests=200, rate=20.0, nx_range=(256, 1024), n3_range=(64, 192)):
     """Poisson arrivals (mean `rate` per second) of mixed serving requests."""
     rng = np.random.default_rng(seed)
     t = 0.0
