@@ -193,3 +193,25 @@ def test_group_poll_matches_single_diagnostics(P, variant):
         assert (np.isnan(dk["theta_deg"]) and np.isnan(ref["theta_deg"])) or \
             abs(dk["theta_deg"] - ref["theta_deg"]) < 1e-8
         assert dk["step"] == ref["step"] == 80
+
+
+@pytest.mark.parametrize("variant", [1, 6])
+def test_group_chi_cases_bitwise(P, variant):
+    """Members with different Appendix A chi cases (each member's ghost rule and
+    wall factor travel in its own parameters) beside a curved-wall case: every
+    member matches its run alone bit for bit."""
+    cs = []
+    for k, th in ((1, 60.0), (3, 120.0), (2, 80.0)):
+        c = workloads.flat_droplet_case(70, 33, 8.0, th, 4.0)
+        c["chi_case"] = k
+        cs.append(c)
+    cs.append(workloads.cylinder_case(96, 48, 0.3, 110.0))
+    g = P.Group()
+    g.set_tile(variant)
+    members = [P.Case.from_case(c, "f32") for c in cs]
+    for m in members:
+        g.add(m)
+    g.step(25)
+    for c, m in zip(cs, members):
+        ref = _alone(P, c, "f32", 25, variant)
+        assert np.array_equal(m.fields()["phi"], ref["phi"])
