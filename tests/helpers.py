@@ -26,3 +26,27 @@ def maxdiff(a, b, mask=None):
     if mask is not None:
         d = d[mask]
     return float(d.max()) if d.size else 0.0
+
+
+def window(c, centre, half):
+    """Sub-box of case `c` of half-width `half` around the node `centre`
+    ((x, y) or (x, y, z)) as a case of its own, closed on every axis.  Periodic
+    axes wrap; closed axes are cut at the domain edge, which then stays the real
+    edge.  Returns (window case, per-axis global indices, per-axis position of
+    the centre inside the window)."""
+    shape, D = tuple(c["shape"]), len(c["shape"])
+    idx, pos = [], []
+    for d in range(D):
+        n, lo, hi = shape[d], centre[d] - half, centre[d] + half + 1
+        if c["periodic"][d]:
+            ids = np.arange(lo, hi) % n
+            pos.append(half)
+        else:
+            ids = np.arange(max(lo, 0), min(hi, n))
+            pos.append(centre[d] - max(lo, 0))
+        idx.append(ids)
+    sel = np.ix_(*idx[::-1])                 # arrays are (z,) y, x
+    w = dict(c, shape=tuple(len(i) for i in idx), periodic=(False,) * D,
+             mask=np.ascontiguousarray(c["mask"][sel]),
+             phi0=np.ascontiguousarray(c["phi0"][sel]))
+    return w, idx, pos
