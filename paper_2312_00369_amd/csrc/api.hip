@@ -455,7 +455,10 @@ int fp16_upkeep(pflbm_case_s* h, int* changed) {
     // diagnostics record) leaves the scale alone
     if (!(m[k] > 0.0f) || !std::isfinite(m[k])) continue;
     if (m[k] >= 2048.0f && m[k] <= 16384.0f) continue;
-    const int e = (int)std::floor(std::log2(8192.0 / (double)m[k]));
+    int e = (int)std::floor(std::log2(8192.0 / (double)m[k]));
+    // the scale stays within [2^-60, 2^60], the range pflbm_set_fp16_scales accepts
+    const int e_now = std::ilogb(*scale[k]);
+    e = std::max(-60 - e_now, std::min(60 - e_now, e));
     if (e == 0) continue;
     const float factor = std::ldexp(1.0f, e);
     if ((rc = run_rescale(h, k, factor))) return rc;
