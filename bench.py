@@ -469,13 +469,17 @@ def cpu_baseline(c, budget_s=15.0):
                       mobility=0.1, beta=beta, kappa=kappa, theta_deg=c["theta_deg"]),
                c["mask"], c["phi0"])
     nodes = int(o.zeta.sum())
-    o.step(1)
-    steps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
+    # the oracle's NumPy calls are single-threaded (element-wise ufuncs and
+    # einsum without BLAS); BLAS pools are pinned to one thread all the same
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
         o.step(1)
-        steps += 1
-    dt = time.perf_counter() - t0
+        steps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            o.step(1)
+            steps += 1
+        dt = time.perf_counter() - t0
     return dict(value=round(nodes * steps / dt / 1e6, 4), unit="MLUPS", cores=1, kind="oracle",
                 sample=f"{c['shape'][0]}x{c['shape'][1]} D2Q9 FP64 NumPy oracle, {steps} steps "
                        f"after one untimed step ({dt:.1f} s, single-threaded NumPy)")
