@@ -68,6 +68,7 @@ def parse():
     ap.add_argument("--table1-3d-angles", type=lambda v: [float(x) for x in v.split(",")],
                     default=[60.0, 90.0, 120.0, 140.0])
     ap.add_argument("--table1-3d-max-steps", type=int, default=1200000)
+    ap.add_argument("--table1-3d-phase", default="", help="'' (D3Q19 for g) or D3Q7")
     ap.add_argument("--sweep-max-steps", type=int, default=4000000,
                     help="step cap of the incline2d / cylinder2d sections")
     ap.add_argument("--appendix-a-marks", type=lambda v: [int(x) for x in v.split(",")],
@@ -332,12 +333,16 @@ def table1_3d(a, torch, P, workloads):
     paper = _json.load(open(os.path.join(ROOT, "tests", "golden", "table1_2d_paper.json")))
     p3 = dict(zip(paper["prescribed_deg"], paper.get("paper_3d_deg", [None] * 11)))
     cs = [workloads.table1_case_3d(th, n) for th in a.table1_3d_angles]
+    if a.table1_3d_phase:
+        for c in cs:
+            c["phase_lattice"] = a.table1_3d_phase
     r = _angle_sweep(torch, P, cs, a.table1_3d_max_steps, label="table1_3d")
     r.pop("fits")
     rows = [{"prescribed": th, "measured": round(t, 2), "error": round(t - th, 2),
              "paper_3d_at_256x256x128": p3.get(int(th))}
             for th, t in zip(a.table1_3d_angles, r.pop("final"))]
-    return dict(workload=f"Sec. 3.1 plate in 3D at {n[0]}x{n[1]}x{n[2]}, D3Q19 FP32, "
+    lat = "D3Q19/" + a.table1_3d_phase if a.table1_3d_phase else "D3Q19"
+    return dict(workload=f"Sec. 3.1 plate in 3D at {n[0]}x{n[1]}x{n[2]}, {lat} FP32, "
                          f"R = {cs[0]['radius']}, sigma 0.005, M 0.01, W 4", angles=rows, **r)
 
 
