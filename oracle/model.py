@@ -8,12 +8,14 @@ by a ghost node stays inside the array.  Flat index = x + Px*(y + Py*z).
 One time step (the paper gives no algorithm box; this is the explicit order the
 equations imply, every quantity at time t built from phi(t) and f(t)):
   1. phi = sum_i g_i                                  Eq. (order-parameter)
-  2. ghost phi = zeta-weighted mean of its 3^D block  Sec. 2.2.2
+  2. ghost phi = zeta-weighted mean of its 3^D block  Sec. 2.2.2 (Appendix A
+     cases 1 and 3: the ghost solves n_w . grad phi = chi across the wall)
   3. rho(phi), grad phi, lap phi, grad rho            Eq. (gradient), (Laplace)
   4. mu with the wall term a_v sqrt(2 kappa beta) cos(theta) (phi - phi^2)
                                                       Eq. (chemical_potencial2)
   5. F = mu grad phi + F_b                            Sec. 2.1.1
-  6. u from rho u = sum c_i f_i + F/2; then p         Sec. 2.1.2, after Eq. (GGi)
+  6. u from rho u = sum c_i f_i + F/2 (u = 0 on boundary nodes, which lie in
+     the solid); then p                               Sec. 2.1.2, after Eq. (GGi)
   7. s = u . grad phi; g collides with G_i and the time derivative of G_i
                                                       Eq. (BGK), (H_i), (F_i)
   8. f collides with F_i                              Eq. (BGK-NS), (feq_i), (GGi)
@@ -21,6 +23,9 @@ equations imply, every quantity at time t built from phi(t) and f(t)):
      the post-collision population of the opposite direction at the same node
      (bounce-back, Sec. 2.2.2).
 Readings of points the paper leaves open are marked READING in the comments.
+Parity unpinned: alpha's split of M (only M = c_s^2 alpha (tau_g - 1/2) is
+printed) and the backward difference for the time derivative of G_i have no
+printed result to pin them beyond the physics checks.
 """
 from dataclasses import dataclass, field
 import math
