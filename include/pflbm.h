@@ -247,9 +247,11 @@ int pflbm_group_step(pflbm_group g, int64_t nsteps);
 /* Reductions for every member; d[k] and flags[k] (bit 0 steady, bit 1
  * nonfinite) for member k in insertion order; capacity >= group size.  (sync) */
 int pflbm_group_poll(pflbm_group g, pflbm_diag* d, int32_t* flags, int32_t capacity);
-/* Launch shape of the batched kernel: fused-step tile variant (-1 = library
- * default) and workgroups per CU of the persistent grid (0 = as many as fit).
- * Results do not depend on either. */
+/* Launch shape of the batched kernel: step tile variant (-1 = library default)
+ * and blocks_per_cu: 0 = one workgroup per table entry (the default; the grid
+ * follows the table, so a membership change recaptures the step graph);
+ * > 0 = a persistent grid of that many workgroups per CU (capped by occupancy)
+ * striding over the table.  Results do not depend on either. */
 int pflbm_group_set_tile(pflbm_group g, int32_t variant, int32_t blocks_per_cu);
 /* Steps per captured HIP graph (0 = direct launches; odd values round up). */
 int pflbm_group_set_graph_chunk(pflbm_group g, int32_t steps);

@@ -102,6 +102,7 @@ int step_variant_tile(int D, int v, int tile[5]);
 // One launch of the batched step kernel.
 struct GroupLaunch {
   int lattice, storage, variant, grid;
+  int persist;           // 1: fixed grid striding over the table; 0: one workgroup per entry
   hipStream_t stream;
   const TileEntry* table;
   const int* ntiles;

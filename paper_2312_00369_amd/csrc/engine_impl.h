@@ -178,11 +178,18 @@ struct Engine {
 
 template <class L, int S>
 struct GroupEngine {
+  // gl.persist: a fixed grid strides over the table (the PERSIST kernels);
+  // otherwise one workgroup per table entry.  The occupancy queries are for
+  // the persistent kernels, whose grid they size.
   template <int BY, int BZ, int KY, int KZ>
   static int launch(const GroupLaunch& gl, int parity) {
     constexpr int bz = (L::D == 3) ? BZ : 1, kz = (L::D == 3) ? KZ : 1;
-    hipLaunchKernelGGL((k_step_group<L, S, BY, bz, KY, kz>), dim3(gl.grid), dim3(64, BY, bz), 0,
-                       gl.stream, gl.table, gl.ntiles, gl.cases, parity);
+    if (gl.persist)
+      hipLaunchKernelGGL((k_step_group<L, S, BY, bz, KY, kz, true>), dim3(gl.grid),
+                         dim3(64, BY, bz), 0, gl.stream, gl.table, gl.ntiles, gl.cases, parity);
+    else
+      hipLaunchKernelGGL((k_step_group<L, S, BY, bz, KY, kz, false>), dim3(gl.grid),
+                         dim3(64, BY, bz), 0, gl.stream, gl.table, gl.ntiles, gl.cases, parity);
     PFLBM_HIP(hipGetLastError());
     return PFLBM_OK;
   }
@@ -190,17 +197,26 @@ struct GroupEngine {
   static int occupancy(int* blocks) {
     constexpr int bz = (L::D == 3) ? BZ : 1, kz = (L::D == 3) ? KZ : 1;
     PFLBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        blocks, reinterpret_cast<const void*>(&k_step_group<L, S, BY, bz, KY, kz>), 64 * BY * bz, 0));
+        blocks, reinterpret_cast<const void*>(&k_step_group<L, S, BY, bz, KY, kz, true>),
+        64 * BY * bz, 0));
     return PFLBM_OK;
   }
   template <int BY, int BZ>
   static int launch_split(const GroupLaunch& gl, int parity) {
     constexpr int bz = (L::D == 3) ? BZ : 1;
-    hipLaunchKernelGGL((k_phi_group<L, S, BY, bz>), dim3(gl.grid), dim3(64, BY, bz), 0, gl.stream,
-                       gl.table, gl.ntiles, gl.cases, parity);
-    PFLBM_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_stepB_group<L, S, BY, bz>), dim3(gl.grid), dim3(64, BY, bz), 0,
-                       gl.stream, gl.table, gl.ntiles, gl.cases, parity);
+    if (gl.persist) {
+      hipLaunchKernelGGL((k_phi_group<L, S, BY, bz, true>), dim3(gl.grid), dim3(64, BY, bz), 0,
+                         gl.stream, gl.table, gl.ntiles, gl.cases, parity);
+      PFLBM_HIP(hipGetLastError());
+      hipLaunchKernelGGL((k_stepB_group<L, S, BY, bz, true>), dim3(gl.grid), dim3(64, BY, bz), 0,
+                         gl.stream, gl.table, gl.ntiles, gl.cases, parity);
+    } else {
+      hipLaunchKernelGGL((k_phi_group<L, S, BY, bz, false>), dim3(gl.grid), dim3(64, BY, bz), 0,
+                         gl.stream, gl.table, gl.ntiles, gl.cases, parity);
+      PFLBM_HIP(hipGetLastError());
+      hipLaunchKernelGGL((k_stepB_group<L, S, BY, bz, false>), dim3(gl.grid), dim3(64, BY, bz),
+                         0, gl.stream, gl.table, gl.ntiles, gl.cases, parity);
+    }
     PFLBM_HIP(hipGetLastError());
     return PFLBM_OK;
   }
@@ -210,8 +226,12 @@ struct GroupEngine {
       hipLaunchKernelGGL((k_phi_group_all<L, S>), dim3(gl.grid), dim3(256), 0, gl.stream,
                          gl.table, gl.ntiles, gl.cases, parity, 64, TY, TZ);
       PFLBM_HIP(hipGetLastError());
-      hipLaunchKernelGGL((k_stepC_group<L, S, TY, TZ>), dim3(gl.grid), dim3(64, TY), 0, gl.stream,
-                         gl.table, gl.ntiles, gl.cases, parity);
+      if (gl.persist)
+        hipLaunchKernelGGL((k_stepC_group<L, S, TY, TZ, true>), dim3(gl.grid), dim3(64, TY), 0,
+                           gl.stream, gl.table, gl.ntiles, gl.cases, parity);
+      else
+        hipLaunchKernelGGL((k_stepC_group<L, S, TY, TZ, false>), dim3(gl.grid), dim3(64, TY), 0,
+                           gl.stream, gl.table, gl.ntiles, gl.cases, parity);
       PFLBM_HIP(hipGetLastError());
       return PFLBM_OK;
     }
@@ -221,7 +241,7 @@ struct GroupEngine {
   static int occupancy_column(int* blocks) {
     if constexpr (L::D == 3) {
       PFLBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          blocks, reinterpret_cast<const void*>(&k_stepC_group<L, S, TY, TZ>), 64 * TY, 0));
+          blocks, reinterpret_cast<const void*>(&k_stepC_group<L, S, TY, TZ, true>), 64 * TY, 0));
       return PFLBM_OK;
     }
     return set_error(PFLBM_EINVAL, "z-marching variants are for D3Q19");
@@ -230,7 +250,8 @@ struct GroupEngine {
   static int occupancy_split(int* blocks) {
     constexpr int bz = (L::D == 3) ? BZ : 1;
     PFLBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        blocks, reinterpret_cast<const void*>(&k_stepB_group<L, S, BY, bz>), 64 * BY * bz, 0));
+        blocks, reinterpret_cast<const void*>(&k_stepB_group<L, S, BY, bz, true>), 64 * BY * bz,
+        0));
     return PFLBM_OK;
   }
   static int go(const GroupLaunch& gl, int parity, int* occ) {

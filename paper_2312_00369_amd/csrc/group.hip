@@ -26,7 +26,7 @@ struct pflbm_group_s {
   std::vector<int> cur0;
   int lattice = -1, storage = -1, D = 0;
   int variant = -1;        // -1: library default for the lattice
-  int blocks_per_cu = 0;   // 0: as many as fit
+  int blocks_per_cu = 0;   // 0: one workgroup per table entry; > 0: persistent grid
   int cus = 0;
   // device table (capacity-managed; addresses change only on growth)
   TileEntry* d_table = nullptr;
@@ -73,6 +73,7 @@ GroupLaunch launch_of(const pflbm_group_s* g) {
   gl.storage = g->storage;
   gl.variant = g->variant;
   gl.grid = g->grid;
+  gl.persist = g->blocks_per_cu > 0 ? 1 : 0;
   gl.stream = g->stream;
   gl.table = g->d_table;
   gl.ntiles = g->d_ntiles;
@@ -183,13 +184,18 @@ int rebuild(pflbm_group_s* g) {
   PFLBM_HIP(hipMemcpyAsync(g->d_ntiles, &g->ntiles, sizeof(int), hipMemcpyHostToDevice, g->stream));
   // the host vectors go out of scope: wait for the copies
   PFLBM_HIP(hipStreamSynchronize(g->stream));
-  // persistent grid: as many workgroups as fit on the device (capped by the table)
-  if (!g->cus) PFLBM_HIP(hipDeviceGetAttribute(&g->cus, hipDeviceAttributeMultiprocessorCount, 0));
-  int occ = 0;
-  if (int rc = run_step_group(launch_of(g), 0, &occ)) return rc;
-  occ = std::max(1, occ);
-  if (g->blocks_per_cu > 0) occ = std::min(occ, g->blocks_per_cu);
-  const int grid = std::max(1, g->cus * occ);
+  // blocks_per_cu > 0: a persistent grid of that many workgroups per CU (capped
+  // by occupancy) strides over the table; 0: one workgroup per table entry
+  // (fewer registers, more waves per SIMD; measured faster)
+  int grid = std::max(1, g->ntiles);
+  if (g->blocks_per_cu > 0) {
+    if (!g->cus)
+      PFLBM_HIP(hipDeviceGetAttribute(&g->cus, hipDeviceAttributeMultiprocessorCount, 0));
+    int occ = 0;
+    if (int rc = run_step_group(launch_of(g), 0, &occ)) return rc;
+    occ = std::max(1, std::min(occ, g->blocks_per_cu));
+    grid = std::max(1, g->cus * occ);
+  }
   if (grid != g->grid) drop_graph(g);
   g->grid = grid;
   g->dirty = false;

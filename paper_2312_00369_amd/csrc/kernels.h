@@ -1087,15 +1087,25 @@ struct TileEntry {
   int tile;          // tile index within the case, x-fastest
 };
 
-template <class L, int S, int BY, int BZ, int KY, int KZ>
+// Table entries of one workgroup: its own entry (the grid covers the table),
+// or, with PERSIST, a grid-stride walk over the table by a fixed grid.
+template <bool PERSIST, class Body>
+__device__ inline void for_entries(int n, Body&& body) {
+  if constexpr (PERSIST) {
+    for (int e = blockIdx.x; e < n; e += gridDim.x) body(e);
+  } else {
+    if ((int)blockIdx.x < n) body((int)blockIdx.x);
+  }
+}
+
+template <class L, int S, int BY, int BZ, int KY, int KZ, bool PERSIST = false>
 __global__ __launch_bounds__(64 * BY * BZ) void k_step_group(
     const TileEntry* __restrict__ table, const int* __restrict__ ntiles,
     const CaseDesc* __restrict__ cases, int parity) {
   using T = StepTile<L, S, BY, BZ, KY, KZ>;
   __shared__ typename T::C sphi[T::NL];
   __shared__ uint32_t sw[T::NL];
-  const int n = *ntiles;
-  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+  for_entries<PERSIST>(*ntiles, [&](int e) {
     const TileEntry te = table[e];
     const CaseDesc& cd = cases[te.case_id];
     const Geo G = cd.G;
@@ -1107,18 +1117,17 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_step_group(
                                     cd.f[1 - c], cd.g[1 - c], static_cast<ComputeT<S>*>(cd.s), G,
                                     cd.P, sphi, sw);
     __syncthreads();   // the next tile reuses the LDS arrays
-  }
+  });
 }
 
 
 // Batched split step: the phi pass and the collide pass, each over the table.
-template <class L, int S, int BY, int BZ>
+template <class L, int S, int BY, int BZ, bool PERSIST = false>
 __global__ __launch_bounds__(64 * BY * BZ) void k_phi_group(
     const TileEntry* __restrict__ table, const int* __restrict__ ntiles,
     const CaseDesc* __restrict__ cases, int parity) {
-  const int n = *ntiles;
   const int TZ = (L::D == 3) ? BZ : 1;
-  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+  for_entries<PERSIST>(*ntiles, [&](int e) {
     const TileEntry te = table[e];
     const CaseDesc& cd = cases[te.case_id];
     const Geo G = cd.G;
@@ -1127,10 +1136,10 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_phi_group(
     const int b = te.tile;
     phi_tile<L, S, BY, BZ, true>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ,
                            cd.nodes, cd.g[c], static_cast<ComputeT<S>*>(cd.phi), G, cd.P);
-  }
+  });
 }
 
-template <class L, int S, int BY, int BZ>
+template <class L, int S, int BY, int BZ, bool PERSIST = false>
 __global__ __launch_bounds__(64 * BY * BZ) void k_stepB_group(
     const TileEntry* __restrict__ table, const int* __restrict__ ntiles,
     const CaseDesc* __restrict__ cases, int parity) {
@@ -1138,9 +1147,8 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_stepB_group(
   constexpr int NL = 68 * (BY + 4) * (D3 ? BZ + 4 : 1);
   __shared__ ComputeT<S> sphi[NL];
   __shared__ uint32_t sw[NL];
-  const int n = *ntiles;
   const int TZ = D3 ? BZ : 1;
-  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+  for_entries<PERSIST>(*ntiles, [&](int e) {
     const TileEntry te = table[e];
     const CaseDesc& cd = cases[te.case_id];
     const Geo G = cd.G;
@@ -1152,18 +1160,17 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_stepB_group(
                              static_cast<ComputeT<S>*>(cd.s),
                              static_cast<const ComputeT<S>*>(cd.phi), G, cd.P, sphi, sw);
     __syncthreads();
-  }
+  });
 }
 
-template <class L, int S, int TY, int TZ>
+template <class L, int S, int TY, int TZ, bool PERSIST = false>
 __global__ __launch_bounds__(64 * TY) void k_stepC_group(
     const TileEntry* __restrict__ table, const int* __restrict__ ntiles,
     const CaseDesc* __restrict__ cases, int parity) {
   using T = ColumnTile<L, S, TY, TZ>;
   __shared__ ComputeT<S> sphi[T::NL];
   __shared__ uint32_t sw[T::NL];
-  const int n = *ntiles;
-  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+  for_entries<PERSIST>(*ntiles, [&](int e) {
     const TileEntry te = table[e];
     const CaseDesc& cd = cases[te.case_id];
     const Geo G = cd.G;
@@ -1175,7 +1182,7 @@ __global__ __launch_bounds__(64 * TY) void k_stepC_group(
                              static_cast<ComputeT<S>*>(cd.s),
                              static_cast<const ComputeT<S>*>(cd.phi), G, cd.P, sphi, sw);
     __syncthreads();
-  }
+  });
 }
 
 // ------------------------------------------------------------------ init

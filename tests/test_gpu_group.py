@@ -215,3 +215,37 @@ def test_group_chi_cases_bitwise(P, variant):
     for c, m in zip(cs, members):
         ref = _alone(P, c, "f32", 25, variant)
         assert np.array_equal(m.fields()["phi"], ref["phi"])
+
+
+@pytest.mark.parametrize("lattice,variant", [("D2Q9", 1), ("D2Q9", 6), ("D3Q19", 3), ("D3Q19", 7),
+                                             ("D3Q19", 8)])
+def test_group_persistent_grid_equals_per_entry_grid(P, lattice, variant):
+    """The persistent grid (a fixed grid striding over the table, blocks_per_cu
+    > 0) and one workgroup per table entry (blocks_per_cu = 0) give the same
+    bits, with graph replay, across a membership change."""
+    if lattice == "D2Q9":
+        cs = _cases2d()[:5]
+    else:
+        cs = [workloads.inclined_droplet_case_3d(n=n, radius=0.25 * n, theta=th, width=4.0)
+              for n, th in ((18, 60.0), (26, 120.0), (22, 90.0))]
+    out = {}
+    for bpc in (0, 1):
+        g = P.Group()
+        g.set_tile(variant, bpc)
+        g.set_graph_chunk(4)
+        ms = [P.Case.from_case(c, "f32") for c in cs]
+        for m in ms[:-1]:
+            g.add(m)
+        g.step(8)
+        g.add(ms[-1])
+        g.step(8)
+        g.remove(ms[0])
+        g.step(8)
+        out[bpc] = [m.fields()["phi"] for m in ms]
+        for m in ms[1:]:
+            g.remove(m)
+        for m in ms:
+            m.close()
+        g.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
