@@ -167,7 +167,7 @@ def inclined_3d(a, torch, P, workloads, stream):
 
 def batched(a, torch, P, workloads, stream):
     """64 uneven D2Q9 cylinder cases: one after another (each with its own graph
-    chunks) against one group (persistent batched kernel)."""
+    chunks) against one group (batched kernel, one workgroup per table entry)."""
     cases = workloads.cylinder_batch()
     hs = [P.Case.from_case(c, "f32", stream=stream) for c in cases]
     nodes = sum(int((h.classes() & 1).sum()) for h in hs)

@@ -224,7 +224,7 @@ void pflbm_destroy(pflbm_handle h);
 /* ---------------------------------------------------------------- groups (batched) */
 
 /* A group advances many cases of one lattice and storage together: each step
- * is one launch of a persistent grid that walks a device (case, tile) table,
+ * is one launch over a device (case, tile) table (see pflbm_group_set_tile),
  * so small and uneven cases fill the GPU together; full chunks of steps replay
  * a captured HIP graph.  The per-node arithmetic is that of the single-case
  * fused step with the same tile variant, so every member's result is

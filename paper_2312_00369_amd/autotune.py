@@ -2,7 +2,8 @@
 
 Candidates are the fused-step tile variants the library exports
 (`pflbm_step_variants`), with and without the XCD-contiguous tile order, and for
-groups the number of workgroups per CU of the persistent grid.  Each candidate
+groups one workgroup per table entry or a persistent grid of 1, 2 or 4
+workgroups per CU.  Each candidate
 is timed on the real case with graph replay; the case's state is saved before
 and restored after, so tuning leaves it exactly as it was (resume is
 bit-identical, and no launch shape changes the results).  The best choice is

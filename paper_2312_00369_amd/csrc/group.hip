@@ -1,5 +1,6 @@
-// Groups: many cases of one lattice and storage advanced by one persistent
-// launch per step that walks a device (case, tile) table.
+// Groups: many cases of one lattice and storage advanced by one launch per
+// step over a device (case, tile) table (one workgroup per entry, or a
+// persistent grid striding over it).
 //
 // Buffer parity.  Each member's descriptor records which of its two buffers
 // held the current state when the table was last built (cur0); launch k after

@@ -1056,11 +1056,13 @@ __global__ __launch_bounds__(64 * TY) void k_stepC(
 }
 
 // ------------------------------------------------------------------ batched step
-// Many cases of one lattice and storage advance together.  A persistent grid
-// walks a device table of (case, tile) entries; each case has a descriptor
-// with its geometry, physics and buffers.  The table and descriptors live in
-// device memory and may change between launches (cases joining or leaving)
-// without touching the launch arguments, so captured graphs stay valid.
+// Many cases of one lattice and storage advance together over a device table
+// of (case, tile) entries; each case has a descriptor with its geometry,
+// physics and buffers.  One workgroup takes one entry, or (PERSIST) a fixed
+// grid strides over the table.  The table and descriptors live in device
+// memory and may change between launches (cases joining or leaving) without
+// touching the launch arguments; with the fixed grid captured graphs stay
+// valid, with one workgroup per entry the grid follows the table size.
 struct Wall {
   int kind;          // 0 none, 1 plane, 2 ball
   double p[3], nrm[3], radius, width;
