@@ -219,3 +219,47 @@ def test_table1_case_3d_geometry(P):
     paper = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
                                         "table1_2d_paper.json")))
     assert len(paper["paper_3d_deg"]) == len(paper["prescribed_deg"]) == 11
+
+
+def test_header_is_plain_c_and_links(P, tmp_path):
+    """include/pflbm.h compiles as C99 with warnings as errors, and a C program
+    using it links against libpflbm.so and runs the host-only calls (footprint,
+    lattice table, error strings) without touching a GPU."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <string.h>
+#include "pflbm.h"
+int main(void) {
+  pflbm_params p;
+  memset(&p, 0, sizeof p);
+  p.struct_size = sizeof p;
+  p.lattice = PFLBM_D2Q9; p.storage = PFLBM_FP32;
+  p.nx = 64; p.ny = 32; p.nz = 1; p.periodic[0] = 1;
+  p.tau = 0.8; p.mobility = 0.1; p.beta = 3e-3; p.kappa = 6e-3;
+  p.rho_l = 10.0; p.rho_g = 1.0; p.theta_deg = 60.0; p.steady_tol = 1e-5;
+  size_t bytes = 0;
+  if (pflbm_footprint(&p, &bytes) != PFLBM_OK || bytes == 0) return 1;
+  int32_t c[27 * 3]; double w[27], k[27]; int32_t opp[27];
+  if (pflbm_lattice_table(PFLBM_D2Q9, c, w, opp, k) != 9 || w[0] != 4.0 / 9.0) return 2;
+  p.theta_deg = 200.0;
+  if (pflbm_footprint(&p, &bytes) != PFLBM_EINVAL) return 3;
+  printf("%zu %s %s\n", bytes, pflbm_strerror(PFLBM_EINVAL), pflbm_last_error());
+  return 0;
+}
+''')
+    exe = tmp_path / "use"
+    inc = os.path.join(ROOT, "include")
+    libdir = os.path.dirname(P.LIB_PATH)
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-I", inc, str(src),
+                        "-L", libdir, "-lpflbm", f"-Wl,-rpath,{libdir}", "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    assert "invalid argument" in r.stdout
