@@ -79,6 +79,13 @@ enum { PFLBM_WALL_NONE = 0, PFLBM_WALL_PLANE = 1, PFLBM_WALL_BALL = 2 };
  *                 c = +1.  Cases 1 and 3 need every ghost node to face the fluid
  *                 along one lattice axis (flat axis-aligned walls); pflbm_create
  *                 returns PFLBM_EUNSUPPORTED otherwise.
+ *  theta_map      heterogeneous wetting: a contact angle per solid node, in
+ *                 (0, 180) degrees, else PFLBM_EINVAL.  The wall term of mu at a
+ *                 node uses the mean cos(theta) over the solid and virtual nodes
+ *                 of its 3^D block (virtual nodes take theta_deg).  At most 1023
+ *                 distinct values besides theta_deg's arise, else
+ *                 PFLBM_EUNSUPPORTED; with chi_case 1 or 3, PFLBM_EUNSUPPORTED.
+ *                 The array is not kept.
  */
 typedef struct pflbm_params {
   uint32_t struct_size;          /* = sizeof(pflbm_params) */
@@ -93,6 +100,8 @@ typedef struct pflbm_params {
   double steady_tol;
   int32_t chi_case;              /* Appendix A, Table A1: 0 or 2 = the method (chi = 0),
                                     1 = cubic Robin ghost rule, 3 = its opposite */
+  const double* theta_map;       /* NULL, or nx*ny*nz contact angles in degrees (x fastest),
+                                    read on solid nodes at pflbm_create only */
 } pflbm_params;
 
 /* Diagnostics record (all reductions in FP64 over zeta = 1 nodes). */

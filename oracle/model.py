@@ -64,6 +64,7 @@ class Params:
     nu_g: float = 0.0
     theta_deg: float = 60.0
     chi_case: int = 2                 # Appendix A, Table A1: 1, 2 (the method) or 3
+    theta_map: object = None          # per-node contact angle (degrees) on solid nodes
     body_force: tuple = (0.0, 0.0, 0.0)
     extra: dict = field(default_factory=dict)
 
@@ -269,14 +270,35 @@ def phase_source(L, s):
     return (L.w * L.k)[:, None] * s[None, :]
 
 
-def chemical_potential(beta, kappa, theta_deg, phi, lap_phi, a_v, chi_case=2):
+def local_cos_theta(grid, eps, theta_deg, theta_map, solid):
+    """Heterogeneous wetting.  READING: the paper has one theta per case; with a
+    contact angle per solid node, the wall term at a node uses the mean of
+    cos(theta) over the epsilon = 0 nodes (solid or virtual) of its 3^D block.
+    Solid nodes take theta_map, virtual nodes the case's theta.  A uniform map
+    gives back the single-theta chemical potential."""
+    cos_node = np.full(grid.N, math.cos(math.radians(theta_deg)))
+    if theta_map is not None:
+        tm = grid.from_domain(np.asarray(theta_map, dtype=np.float64), fill=theta_deg)
+        cos_node = np.where(solid, np.cos(np.radians(tm)), cos_node)
+    num = np.zeros(grid.N)
+    den = np.zeros(grid.N)
+    for c in lat.ghost_neighbourhood(grid.D):
+        nb, ok = grid.shift(c)
+        wall = (ok & (eps[nb] == 0.0)).astype(np.float64)
+        num += wall * cos_node[nb]
+        den += wall
+    return np.where(den > 0, num / np.maximum(den, 1.0), math.cos(math.radians(theta_deg)))
+
+
+def chemical_potential(beta, kappa, theta_deg, phi, lap_phi, a_v, chi_case=2, cos_local=None):
     """Eq. (chemical_potencial2): mu = 4 beta phi (phi-1)(phi-1/2) - kappa lap phi
     - a_v sqrt(2 kappa beta) cos(theta) (phi - phi^2).  Cases 1 and 3 of
     Appendix A use Eq. (chemical_potencial112) with their chi: the wall term is
     a_v [kappa chi + sqrt(2 kappa beta) cos(theta) (phi - phi^2)], i.e. zero
     (case 1) or twice the above (case 3)."""
-    wet = math.sqrt(2.0 * kappa * beta) * math.cos(math.radians(theta_deg))
-    wet *= {1: 0.0, 2: 1.0, 3: 2.0}[int(chi_case)]
+    cos_t = math.cos(math.radians(theta_deg)) if cos_local is None else cos_local
+    wet = math.sqrt(2.0 * kappa * beta) * cos_t
+    wet = wet * {1: 0.0, 2: 1.0, 3: 2.0}[int(chi_case)]
     return (4.0 * beta * phi * (phi - 1.0) * (phi - 0.5) - kappa * lap_phi
             - a_v * wet * (phi - phi * phi))
 
@@ -301,8 +323,14 @@ class Oracle:
         self.zeta, self.eps, self.ghost, self.boundary = classify(
             self.grid, self.L, solid_mask)
         self.a_v = effective_area(self.grid, self.L, self.eps, self.zeta)
+        solid = self.grid.from_domain(np.asarray(solid_mask, dtype=bool), fill=False)
+        self.cos_local = (None if params.theta_map is None else
+                          local_cos_theta(self.grid, self.eps, params.theta_deg,
+                                          params.theta_map, solid))
         self.chi_a = chi_coefficient(params.beta, params.kappa, params.theta_deg,
                                      params.chi_case)
+        if params.theta_map is not None and params.chi_case != 2:
+            raise ValueError("a per-node contact angle goes with the chi = 0 method only")
         if params.chi_case != 2:
             # Appendix A tests these cases on a flat plate: every ghost must see
             # the fluid along one lattice axis
@@ -342,7 +370,7 @@ class Oracle:
         phi_full = ghost_fill(self.grid, phi, self.zeta, self.ghost, self.chi_a)
         lap = laplacian(self.grid, self.L, phi_full)
         mu = chemical_potential(p.beta, p.kappa, p.theta_deg, phi_full, lap, self.a_v,
-                                p.chi_case)
+                                p.chi_case, self.cos_local)
         mu = np.where(self.zeta, mu, 0.0)
         return mu, phi_full, lap
 

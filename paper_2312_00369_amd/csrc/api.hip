@@ -98,6 +98,9 @@ int validate_and_derive(const pflbm_params* p, Derived* d) {
     ph.chi_a = c * std::sqrt(2.0 * p->beta / p->kappa) * std::cos(p->theta_deg * M_PI / 180.0);
     ph.wet *= 1.0 + c;
   }
+  ph.wet_tab = nullptr;     // set at create (device table of per-node wall coefficients)
+  if (p->theta_map && (p->chi_case == 1 || p->chi_case == 3))
+    return set_error(PFLBM_EUNSUPPORTED, "a per-node contact angle goes with chi case 2 only");
   ph.rho_l = p->rho_l;
   ph.rho_g = p->rho_g;
   ph.nu_l = p->nu_l;
@@ -182,6 +185,7 @@ Layout make_layout(const Derived& d, int storage, dim3 tile) {
   L.partial = take(max_parts * kRecN * sizeof(double));
   L.rec = take(kRecN * sizeof(double) * 2);
   L.popmax = take(2 * kPopmaxBlocks * sizeof(float));
+  L.wet = take(kWetEntries * sizeof(double));
   L.total = off;
   return L;
 }
@@ -294,6 +298,73 @@ int check_axis_ghosts(const Derived& d, const std::vector<uint32_t>& words) {
           return set_error(PFLBM_EUNSUPPORTED,
                            "chi cases 1 and 3 need walls normal to a lattice axis; ghost "
                            "node (%d, %d, %d) is not", x, y, z);
+      }
+  return PFLBM_OK;
+}
+
+// Per-node contact angles (theta_map, degrees, read on mask nodes).  READING:
+// the wall term of mu at a zeta = 1 node uses the mean cos(theta) over the
+// epsilon = 0 nodes of its 3^D block, mask nodes with their own theta and
+// virtual nodes with the case's.  The distinct coefficients sqrt(2 kappa beta)
+// times that mean go into a table of kWetEntries (entry 0: the case's value);
+// each node word carries its entry (wet_bits).
+int wet_table(const Derived& d, const pflbm_params* p, const uint8_t* mask,
+              std::vector<uint32_t>& words, std::vector<double>& tab) {
+  tab.assign(kWetEntries, 0.0);
+  tab[0] = d.phys.wet;
+  if (!p->theta_map) return PFLBM_OK;
+  const Geo& G = d.geo;
+  const int nx = G.PX - 2 * G.pad[0], ny = G.PY - 2 * G.pad[1], nz = G.PZ - 2 * G.pad[2];
+  const double cos0 = std::cos(p->theta_deg * M_PI / 180.0);
+  std::vector<double> cosn((size_t)d.N, cos0);
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const size_t dom = (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z);
+        if (!mask[dom]) continue;
+        const double th = p->theta_map[dom];
+        if (!(th > 0.0 && th < 180.0))
+          return set_error(PFLBM_EINVAL, "theta_map must lie in (0, 180) degrees on solid nodes "
+                           "(got %g at node %zu)", th, dom);
+        cosn[G.idx(x + G.pad[0], y + G.pad[1], z + G.pad[2])] = std::cos(th * M_PI / 180.0);
+      }
+  const double base = std::sqrt(2.0 * p->kappa * p->beta);
+  const int P3[3] = {G.PX, G.PY, G.PZ};
+  const int dz = d.D == 3 ? 1 : 0;
+  int used = 1;
+  for (int z = 0; z < G.PZ; ++z)
+    for (int y = 0; y < G.PY; ++y)
+      for (int x = 0; x < G.PX; ++x) {
+        const long long n = G.idx(x, y, z);
+        if (!(words[n] & kZeta)) continue;
+        double sum = 0.0;
+        int cnt = 0;
+        for (int c = -dz; c <= dz; ++c)
+          for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a) {
+              int q[3] = {x + a, y + b, z + c}, ok = 1;
+              for (int k = 0; k < 3; ++k) {
+                if (G.per[k]) q[k] = ((q[k] % P3[k]) + P3[k]) % P3[k];
+                else if (q[k] < 0 || q[k] >= P3[k]) ok = 0;
+              }
+              if (!ok) continue;
+              const long long m = G.idx(q[0], q[1], q[2]);
+              if (words[m] & kFluid) continue;
+              sum += cosn[m];
+              ++cnt;
+            }
+        if (!cnt) continue;
+        const double w = base * (sum / cnt);
+        if (w == tab[0]) continue;
+        int k = 1;
+        while (k < used && tab[k] != w) ++k;
+        if (k == used) {
+          if (used == kWetEntries)
+            return set_error(PFLBM_EUNSUPPORTED, "theta_map gives more than %d distinct wall "
+                             "coefficients", kWetEntries - 1);
+          tab[used++] = w;
+        }
+        words[n] |= wet_bits((unsigned)k);
       }
   return PFLBM_OK;
 }
@@ -415,9 +486,15 @@ int create_common(const pflbm_params* prm, const uint8_t* mask, const double* ph
   h->classes.assign((size_t)prm->nx * prm->ny * prm->nz, 0);
   classify_nodes(dv, mask, words, h->classes.data());
   if (dv.phys.chi_a != 0.0 && (rc = check_axis_ghosts(dv, words))) return fail(rc);
+  std::vector<double> wet;
+  if ((rc = wet_table(dv, prm, mask, words, wet))) return fail(rc);
+  h->dv.phys.wet_tab = reinterpret_cast<const double*>(h->base + L.wet);
+  h->prm.theta_map = nullptr;   // the caller's array is read here only
 #define CK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return fail(set_error(PFLBM_EDEVICE, "%s: %s", #x, hipGetErrorString(e_))); } while (0)
   CK(hipMemsetAsync(h->base, 0, L.total, h->stream));
   CK(hipMemcpyAsync(h->nodes, words.data(), words.size() * 4, hipMemcpyHostToDevice, h->stream));
+  CK(hipMemcpyAsync(h->base + L.wet, wet.data(), wet.size() * sizeof(double),
+                    hipMemcpyHostToDevice, h->stream));
   if ((rc = upload_phi0(h, phi0, words))) return fail(rc);
   // mu(phi0) with ghosts, g = g_eq(phi0, mu0) placed for the first pull, f = 0.
   if ((rc = run_mu(h))) return fail(rc);

@@ -27,7 +27,7 @@ void clear_error();
   } while (0)
 
 struct Layout {
-  size_t nodes, f[2], g[2], s, phi, mu, snap, partial, rec, popmax, total;
+  size_t nodes, f[2], g[2], s, phi, mu, snap, partial, rec, popmax, wet, total;
   size_t f_bytes, g_bytes;   // one f buffer, one g buffer
   size_t c_bytes;     // one compute-type field
   long long nparts;   // reduction partial records

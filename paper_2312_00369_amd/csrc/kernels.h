@@ -45,6 +45,7 @@ struct Geo {
 struct Phys {
   double tau, inv_tau_g, alpha, beta, kappa, wet, rho_l, rho_g, nu_l, nu_g;
   double chi_a;            // chi(phi) = chi_a (phi - phi^2) of the ghost rule; 0 = mean only
+  const double* wet_tab;   // device table of wall coefficients for per-node contact angles
   double Fb[3];
   int visc_var;
   float scale_f, scale_g;  // FP16 codec: stored = value * scale (power of two)
@@ -260,6 +261,19 @@ __device__ inline C ghost_mean(const C* sphi, const uint32_t* sw, int t, int sx,
 
 // mu of Eq. (chemical_potencial2) at a zeta = 1 entry: isotropic Laplacian
 // (Eq. Laplace) of phi and a_v = |grad eps| (Eq. avvv) from the neighbours.
+// Wall coefficient sqrt(2 kappa beta) cos(theta) of Eq. (chemical_potencial2) at
+// a node: the case's value, or with a per-node contact angle the table entry
+// its word carries (the mean cos(theta) of the walls around it).
+// Entry 0 of the table holds the case's value.  The two forms give the same
+// value; each is the one that costs the step kernels of its dimension no
+// extra registers (2D: skip the load for entry 0; 3D: always load).
+template <int D, class C>
+__device__ inline C wet_of(uint32_t word, const Phys& P) {
+  const uint32_t k = wet_entry(word);
+  if constexpr (D == 2) return k ? C(P.wet_tab[k]) : C(P.wet);
+  else return C(P.wet_tab[k]);
+}
+
 template <class L, class C>
 __device__ inline C mu_at(const C* sphi, const uint32_t* sw, int t, int sx, int sxy,
                           const Phys& P) {
@@ -282,7 +296,7 @@ __device__ inline C mu_at(const C* sphi, const uint32_t* sw, int t, int sx, int 
   ez *= inv_cs2;
   const C av = sqrt(ex * ex + ey * ey + ez * ez);
   return C(4) * C(P.beta) * ph * (ph - C(1)) * (ph - C(0.5)) - C(P.kappa) * lap -
-         av * C(P.wet) * (ph - ph * ph);
+         av * wet_of<L::D, C>(sw[t], P) * (ph - ph * ph);
 }
 
 // grad phi of Eq. (gradient) from neighbour values v(i) = phi(x + c_i).
@@ -1030,7 +1044,7 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
         ez *= inv_cs2;
         const C av = sqrt(ex * ex + ey * ey + ez * ez);
         const C m = C(4) * C(P.beta) * ph * (ph - C(1)) * (ph - C(0.5)) - C(P.kappa) * lap -
-                    av * C(P.wet) * (ph - ph * ph);
+                    av * wet_of<L::D, C>(w, P) * (ph - ph * ph);
         C gx, gy, gz;
         grad_of<L, C>([&](int i) { return sphi[at(i)]; }, gx, gy, gz);
         node_update<L, S, 0, O>(f, g0, g, ph, m, gx, gy, gz, w, n, fdst, gdst, sprev, nullptr,

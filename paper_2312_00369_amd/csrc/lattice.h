@@ -97,5 +97,14 @@ constexpr unsigned kZeta = 1u;        // fluid or boundary node: carries f and g
 constexpr unsigned kFluid = 2u;       // epsilon = 1
 constexpr unsigned kGhost = 4u;       // zeta = 0 node one link from a zeta = 1 node
 constexpr int kLinkShift = 8;         // bit kLinkShift + i: node - c_i is zeta = 0
+// Wall-wetting table entry of a node (0: the case's value): 10 bits, the low 5
+// in bits 27..31 and the high 5 in bits 3..7 (both unused otherwise).
+constexpr int kWetEntries = 1024;
+__host__ __device__ constexpr unsigned wet_entry(unsigned word) {
+  return (word >> 27) | ((word << 2) & 0x3e0u);
+}
+__host__ __device__ constexpr unsigned wet_bits(unsigned k) {
+  return ((k & 31u) << 27) | ((k >> 5) << 3);
+}
 
 }  // namespace pflbm

@@ -52,6 +52,7 @@ class pflbm_params(ct.Structure):
         ("wall_radius", ct.c_double), ("diag_width", ct.c_double),
         ("steady_tol", ct.c_double),
         ("chi_case", ct.c_int32),
+        ("theta_map", ct.c_void_p),
     ]
 
 
@@ -145,7 +146,7 @@ def beta_kappa(sigma, width):
 def make_params(lattice, shape, periodic, theta_deg, beta, kappa, storage="f32", tau=0.8,
                 tau_phi=0.0, mobility=0.1, rho_l=10.0, rho_g=1.0, nu_l=0.0, nu_g=0.0,
                 body_force=(0.0, 0.0, 0.0), wall=None, diag_width=4.0, steady_tol=1e-5,
-                chi_case=2):
+                chi_case=2, theta_map=None):
     p = pflbm_params()
     p.struct_size = ct.sizeof(pflbm_params)
     p.lattice = LATTICE[lattice]
@@ -177,6 +178,13 @@ def make_params(lattice, shape, periodic, theta_deg, beta, kappa, storage="f32",
     p.diag_width = diag_width
     p.steady_tol = steady_tol
     p.chi_case = int(chi_case)
+    if theta_map is not None:
+        # contact angle per node (numpy order (z,) y, x, i.e. x fastest); the
+        # array lives as long as the parameter record
+        p._theta_map = np.ascontiguousarray(theta_map, dtype=np.float64).ravel()
+        if p._theta_map.size != p.nx * p.ny * p.nz:
+            raise ValueError("theta_map must have one value per domain node")
+        p.theta_map = p._theta_map.ctypes.data
     return p
 
 
@@ -186,7 +194,7 @@ def params_from_case(c, storage=None, **over):
     kw = dict(storage=storage or c.get("storage", "f32"), tau=c.get("tau", 0.8),
               mobility=c.get("mobility", 0.1), rho_l=c.get("rho_l", 10.0),
               rho_g=c.get("rho_g", 1.0), wall=c.get("wall"), diag_width=c["width"],
-              chi_case=c.get("chi_case", 2))
+              chi_case=c.get("chi_case", 2), theta_map=c.get("theta_map"))
     kw.update(over)
     return make_params(case_lattice(c), c["shape"], c["periodic"], c["theta_deg"], beta, kappa,
                        **kw)

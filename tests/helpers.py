@@ -11,7 +11,8 @@ def oracle_for(c, **over):
     kw = dict(lattice=c["lattice"], shape=tuple(c["shape"]), periodic=tuple(c["periodic"]),
               tau=c.get("tau", 0.8), mobility=c.get("mobility", 0.1), beta=beta, kappa=kappa,
               rho_l=c.get("rho_l", 10.0), rho_g=c.get("rho_g", 1.0), theta_deg=c["theta_deg"],
-              phase_lattice=c.get("phase_lattice", ""), chi_case=c.get("chi_case", 2))
+              phase_lattice=c.get("phase_lattice", ""), chi_case=c.get("chi_case", 2),
+              theta_map=c.get("theta_map"))
     kw.update(over)
     return Oracle(Params(**kw), c["mask"], c["phi0"])
 

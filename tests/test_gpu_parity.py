@@ -428,3 +428,94 @@ def test_chi_cases_refuse_curved_walls(P):
         P.Case.from_case(c, "f32")
     c["chi_case"] = 2
     P.Case.from_case(c, "f32").close()
+
+
+def test_parity_body_force_and_variable_viscosity_fp64(P):
+    """Gravity (F_b) and nu_l != nu_g (tau_f per node from nu(phi)) against the
+    oracle in FP64, on the flat-wall drop, 200 steps."""
+    c = workloads.flat_droplet_case(67, 37, 11.0, 60.0, 4.0)
+    over = dict(body_force=(0.0, -2e-6, 0.0), nu_l=0.12, nu_g=0.04)
+    g = P.Case.from_case(c, "f64", **over)
+    o = oracle_for(c, **over)
+    zeta = _zeta(g)
+    for k in range(4):
+        g.step(50)
+        o.step(50)
+        _compare(g.fields(), o.fields(), zeta, 1e-12, 1e-12)
+
+
+def _patchy_2d():
+    c = workloads.flat_droplet_case(67, 37, 11.0, 120.0, 4.0)
+    tm = np.full((37, 67), 120.0)
+    tm[0, :30] = 60.0            # bottom row: 60 deg on the left, 120 on the right
+    tm[-1, :] = 95.0             # top row
+    c["theta_map"] = tm
+    return c
+
+
+def _patchy_3d():
+    c = workloads.inclined_droplet_case_3d(n=22, radius=6.0, theta=100.0, width=4.0)
+    tm = np.full(c["mask"].shape, 100.0)
+    tm[:, :, :11] = 50.0          # x < 11: 50 deg
+    c["theta_map"] = tm
+    return c
+
+
+@pytest.mark.parametrize("make", [_patchy_2d, _patchy_3d], ids=["2d", "3d"])
+def test_parity_theta_map_fp64(P, make):
+    """Heterogeneous wetting (a contact angle per solid node) against the
+    oracle in FP64, 200 steps; the per-node wall coefficients travel as table
+    entries in the node words."""
+    c = make()
+    g = P.Case.from_case(c, "f64")
+    o = oracle_for(c)
+    zeta = _zeta(g)
+    for k in range(4):
+        g.step(50)
+        o.step(50)
+        _compare(g.fields(), o.fields(), zeta, 1e-12, 1e-12)
+
+
+@pytest.mark.parametrize("make,lattice", [(_patchy_2d, "D2Q9"), (_patchy_3d, "D3Q19")],
+                         ids=["2d", "3d"])
+def test_theta_map_every_variant_and_group_bitwise(P, make, lattice):
+    """Every step kernel reads the per-node coefficients: FP32 fields
+    bit-identical to the three-kernel path; inside a group beside a uniform case
+    the patchy case matches its run alone."""
+    c = make()
+    ref = P.Case.from_case(c, "f32")
+    ref.set_step_kernel(-1)
+    ref.step(20)
+    fr = ref.fields()
+    for v in range(len(P.step_variants(lattice))):
+        g = P.Case.from_case(c, "f32")
+        g.set_step_kernel(v)
+        g.step(20)
+        assert np.array_equal(g.fields()["phi"], fr["phi"]), v
+        assert np.array_equal(g.fields()["mu"], fr["mu"]), v
+    other = dict(c)
+    other.pop("theta_map")
+    grp = P.Group()
+    ms = [P.Case.from_case(x, "f32") for x in (c, other)]
+    for m in ms:
+        grp.add(m)
+    grp.step(20)
+    for x, m in zip((c, other), ms):
+        a = P.Case.from_case(x, "f32")
+        a.step(20)
+        assert np.array_equal(m.fields()["phi"], a.fields()["phi"])
+
+
+def test_theta_map_refusals(P):
+    """Angles outside (0, 180) on solid nodes, and more than 1023 distinct wall
+    coefficients (a random angle per solid node of a 30^3 staircase), are
+    refused at creation."""
+    c = _patchy_2d()
+    c["theta_map"] = c["theta_map"].copy()
+    c["theta_map"][0, 5] = 180.0
+    with pytest.raises(P.PflbmError):
+        P.Case.from_case(c, "f32")
+    c = workloads.inclined_droplet_case_3d(n=30, radius=6.0, theta=100.0, width=4.0)
+    c["theta_map"] = np.random.default_rng(1).uniform(20.0, 160.0, c["mask"].shape)
+    with pytest.raises(P.PflbmError):
+        P.Case.from_case(c, "f32")

@@ -263,3 +263,18 @@ int main(void) {
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
     assert "invalid argument" in r.stdout
+
+
+def test_theta_map_with_chi_case_refused(P):
+    """A per-node contact angle goes with the chi = 0 method only: parameter
+    validation refuses it with chi cases 1 and 3 (no device work)."""
+    c = workloads.flat_droplet_case(32, 16, 5.0, 60.0)
+    c["theta_map"] = np.full((16, 32), 70.0)
+    prm = P.params_from_case(c, "f32")
+    n = ct.c_size_t(0)
+    assert P.lib.pflbm_footprint(ct.byref(prm), ct.byref(n)) == 0
+    c["chi_case"] = 1
+    prm = P.params_from_case(c, "f32")
+    assert P.lib.pflbm_footprint(ct.byref(prm), ct.byref(n)) == -6
+    with pytest.raises(ValueError):
+        oracle_for(c)

@@ -584,3 +584,68 @@ def test_chi_ghost_rule_and_its_limits():
     cyl["chi_case"] = 1
     with pytest.raises(ValueError):
         oracle_for(cyl)
+
+
+def test_body_force_momentum_grows_exactly():
+    """Sec. 2.1.1 body force through Eq. (GGi) and rho u = sum c f + F/2: in a
+    periodic single-phase box (mu = 0, grad phi = 0, so F = F_b) collision adds
+    exactly F to sum c f per step, so after n steps rho u = (n + 1/2) F_b at
+    every node.  A dropped F/2 or a wrong (1 - 1/2tau) factor breaks this."""
+    c = dict(lattice="D2Q9", shape=(12, 10), periodic=(True, True),
+             mask=np.zeros((10, 12), np.uint8), phi0=np.zeros((10, 12)), theta_deg=90.0,
+             sigma=1e-3, width=4.0, tau=0.8, mobility=0.1, rho_l=10.0, rho_g=1.0, wall=None)
+    F = (3e-6, -2e-6, 0.0)
+    o = oracle_for(c, body_force=F)
+    o.step(50)
+    u = o.fields()["u"]
+    for d in range(2):
+        assert np.abs(u[d] / (50.5 * F[d] / 1.0) - 1.0).max() < 1e-12
+
+
+def test_variable_viscosity_poiseuille_ratio():
+    """Sec. 2.1.1, nu linear in phi with nu = c_s^2 (tau_f - 1/2): the same
+    force-driven channel filled with liquid and then with gas reaches centre-line
+    velocities in the ratio rho_g nu_g / (rho_l nu_l) (u_max = F H^2 / (8 rho nu)).
+    Within 10 %: the bounce-back slip moves the effective walls by a tau-dependent
+    fraction of a node.  Viscosity ignored would give rho_g / rho_l (3x off),
+    swapped phases 9x off."""
+    H = 24
+    um = {}
+    for ph, steps in ((0.0, 15000), (1.0, 7500)):
+        c = dict(lattice="D2Q9", shape=(4, H), periodic=(True, False),
+                 mask=workloads.flat_walls((4, H)), phi0=np.full((H, 4), ph), theta_deg=90.0,
+                 sigma=1e-3, width=4.0, tau=0.8, mobility=0.1, rho_l=10.0, rho_g=1.0, wall=None)
+        o = oracle_for(c, body_force=(1e-6, 0.0, 0.0), nu_l=0.12, nu_g=0.04)
+        o.step(steps)
+        um[ph] = o.fields()["u"][0].max()
+    want = (1.0 * 0.04) / (10.0 * 0.12)
+    assert abs(um[1.0] / um[0.0] / want - 1.0) < 0.10, um[1.0] / um[0.0]
+
+
+def test_per_node_theta_patch_and_uniform_map():
+    """Heterogeneous wetting (a contact angle per solid node): a uniform map
+    reproduces the single-theta run; the paper's 60 deg cap on a 60 deg patch
+    wider than its base, in a 120 deg wall, stays at 60 deg, while the same cap
+    on the uniform 120 deg wall climbs away from it.  A map read in the wrong
+    orientation or not applied locally fails one of the two."""
+    W, sigma = 4.0, 1e-2
+    wall = dict(kind="plane", point=(0.0, -0.5), normal=(0.0, 1.0))
+    a = oracle_for(_cap_case(96, 48, 15.0, 60.0, 60.0, sigma, W), mobility=0.2)
+    cb = _cap_case(96, 48, 15.0, 60.0, 60.0, sigma, W)
+    cb["theta_map"] = np.full((48, 96), 60.0)
+    b = oracle_for(cb, mobility=0.2)
+    a.step(100)
+    b.step(100)
+    assert np.abs(a.fields()["phi"] - b.fields()["phi"]).max() < 1e-15
+    c = _cap_case(96, 48, 15.0, 120.0, 60.0, sigma, W)
+    tm = np.full((48, 96), 120.0)
+    tm[0, 18:79] = 60.0                      # |x - 48| <= 30 on the solid bottom row
+    c["theta_map"] = tm
+    o = oracle_for(c, mobility=0.2)
+    o.step(2500)
+    th = odiag.contact_angle(o.fields()["phi"], o.domain(o.zeta), wall, W)[0]
+    assert abs(th - 60.0) < 1.5, th
+    u = oracle_for(_cap_case(96, 48, 15.0, 120.0, 60.0, sigma, W), mobility=0.2)
+    u.step(2500)
+    th_u = odiag.contact_angle(u.fields()["phi"], u.domain(u.zeta), wall, W)[0]
+    assert th_u > 64.0, th_u
