@@ -12,6 +12,7 @@ equations imply, every quantity at time t built from phi(t) and f(t)):
      cases 1 and 3: the ghost solves n_w . grad phi = chi across the wall)
   3. rho(phi), grad phi, lap phi, grad rho            Eq. (gradient), (Laplace)
   4. mu with the wall term a_v sqrt(2 kappa beta) cos(theta) (phi - phi^2)
+     (with a per-node theta: the mean cos(theta) of the walls around the node)
                                                       Eq. (chemical_potencial2)
   5. F = mu grad phi + F_b                            Sec. 2.1.1
   6. u from rho u = sum c_i f_i + F/2 (u = 0 on boundary nodes, which lie in
