@@ -249,3 +249,31 @@ def test_group_persistent_grid_equals_per_entry_grid(P, lattice, variant):
         g.close()
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
+
+
+def test_group_poll_fp16_upkeep_matches_alone(P):
+    """FP16-deviation scale upkeep inside a group: a member whose scales were
+    pushed out of band is rescaled at the poll and continues exactly like the
+    same case run alone with a diagnostics call at the same step."""
+    c = workloads.flat_droplet_case(96, 40, 9.0, 70.0, 4.0)
+    alone = P.Case.from_case(c, "f16dev")
+    member = P.Case.from_case(c, "f16dev")
+    other = P.Case.from_case(workloads.flat_droplet_case(64, 32, 7.0, 110.0, 4.0), "f16dev")
+    sf, sg = alone.fp16_scales()
+    for h in (alone, member):
+        h.set_fp16_scales(sf / 64, sg / 64)
+    g = P.Group()
+    g.add(member)
+    g.add(other)
+    g.step(12)
+    g.poll()
+    g.step(14)
+    alone.step(12)
+    alone.diagnostics()
+    alone.step(14)
+    g.remove(member)
+    g.remove(other)
+    sf2, sg2 = member.fp16_scales()
+    assert sf2 > sf / 64 and sg2 > sg / 64
+    assert (sf2, sg2) == alone.fp16_scales()
+    assert np.array_equal(member.fields()["phi"], alone.fields()["phi"])
