@@ -519,3 +519,32 @@ def test_theta_map_refusals(P):
     c["theta_map"] = np.random.default_rng(1).uniform(20.0, 160.0, c["mask"].shape)
     with pytest.raises(P.PflbmError):
         P.Case.from_case(c, "f32")
+
+
+@pytest.mark.parametrize("variant", [1, 6, -1])
+def test_degenerate_one_wide_and_all_solid(P, variant):
+    """Degenerate inputs: a periodic domain one node wide (every x neighbour is
+    the node itself) against the oracle in FP64, for the fused, split and
+    three-kernel paths; and an all-solid domain (no zeta = 1 node), which steps
+    and reports zero mass without a non-finite flag."""
+    ny = 24
+    y = np.arange(ny)[:, None]
+    phi0 = (0.5 + 0.5 * np.tanh(2.0 * (8.0 - y) / 4.0)) * np.ones((ny, 1))
+    c = dict(lattice="D2Q9", shape=(1, ny), periodic=(True, False),
+             mask=workloads.flat_walls((1, ny)), phi0=phi0, theta_deg=60.0, sigma=1e-3,
+             width=4.0, tau=0.8, mobility=0.1, rho_l=10.0, rho_g=1.0, wall=None)
+    g = P.Case.from_case(c, "f64")
+    g.set_step_kernel(variant)
+    o = oracle_for(c)
+    g.step(50)
+    o.step(50)
+    _compare(g.fields(), o.fields(), _zeta(g), 1e-12, 1e-12)
+    g.close()
+    s = dict(c, shape=(40, 12), periodic=(True, True), mask=np.ones((12, 40), np.uint8),
+             phi0=np.zeros((12, 40)))
+    h = P.Case.from_case(s, "f32")
+    h.set_step_kernel(variant)
+    h.step(10)
+    d = h.diagnostics()
+    assert d["mass"] == 0.0 and not d["nonfinite"] and d["n_points"] == 0
+    h.close()
