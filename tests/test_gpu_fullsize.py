@@ -104,3 +104,32 @@ def test_fullsize_256cubed_windows(P, storage):
         o.step(k)
         errs = _centre_compare(gf, o.fields(), zeta, idx, pos, 2, tol_phi, tol_other)
         print(f"256^3 {storage} window at {pt}: {errs}")
+
+
+def test_over_4gib_buffers_use_64bit_offsets(P):
+    """Maximum sizes: 384^3 D3Q19 FP32 has a g buffer above 4 GiB, so its
+    kernels form 64-bit load offsets (the 32-bit form serves every smaller
+    case).  Three windows on the interface against the oracle after 6
+    graph-replayed steps; a group, whose kernels use 32-bit offsets only,
+    refuses it."""
+    k = 6
+    c = workloads.inclined_droplet_case_3d(n=384, radius=60.0, theta=45.0, width=5.0)
+    prm = P.params_from_case(c, "f32")
+    assert P.footprint(prm) > 2 * 4 * 2 ** 30
+    g = P.Case.from_case(c, "f32")
+    g.set_graph_chunk(3)
+    g.step(k)
+    gf = g.fields()
+    zeta = (g.classes() & 1).astype(bool)
+    for pt in [(192, 252, 95), (244, 192, 125), (162, 192, 147)]:
+        w, idx, pos = window(c, pt, 3 * k + 4)
+        o = oracle_for(w)
+        o.step(k)
+        errs = _centre_compare(gf, o.fields(), zeta, idx, pos, 2, 1e-5, 1e-6)
+        print(f"384^3 window at {pt}: {errs}")
+    del gf
+    grp = P.Group()
+    with pytest.raises(P.PflbmError):
+        grp.add(g)
+    grp.close()
+    g.close()
