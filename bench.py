@@ -493,7 +493,7 @@ def cpu_baseline(c, budget_s=15.0):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import numpy as np
     import torch
