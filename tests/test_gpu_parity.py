@@ -548,3 +548,38 @@ def test_degenerate_one_wide_and_all_solid(P, variant):
     d = h.diagnostics()
     assert d["mass"] == 0.0 and not d["nonfinite"] and d["n_points"] == 0
     h.close()
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_laplace_law_on_the_gpu(P, D):
+    """Laplace's law at the paper's surface tension (sigma = 0.005, W = 4) for
+    free droplets stepped by the default kernels in FP32: p_in - p_out =
+    sigma / R in 2D and 2 sigma / R in 3D, within 3 % (2D) and 5 % (3D).  The
+    pressure difference is averaged over the tail of the run (acoustic ringing)
+    and R is the fitted phi = 1/2 radius."""
+    from oracle import diagnostics as odiag
+    sigma, W = 0.005, 4.0
+    n = 96 if D == 2 else 48
+    radii_in = (16.0, 24.0, 32.0) if D == 2 else (10.0, 13.0, 16.0)
+    shape = (n,) * D
+    X = np.indices(shape[::-1]).astype(float)
+    r = np.sqrt(sum((X[d] - n / 2) ** 2 for d in range(D)))
+    for R in radii_in:
+        phi0 = workloads.droplet(shape, (n / 2,) * D, R, W)
+        c = dict(lattice="D2Q9" if D == 2 else "D3Q19", shape=shape, periodic=(True,) * D,
+                 mask=np.zeros(shape[::-1], np.uint8), phi0=phi0, sigma=sigma, width=W,
+                 theta_deg=90.0, tau=0.8, mobility=0.1, rho_l=10.0, rho_g=1.0, wall=None)
+        g = P.Case.from_case(c, "f32")
+        g.set_graph_chunk(50)
+        g.step(6000)
+        dps, rs = [], []
+        for k in range(40):
+            g.step(50)
+            f = g.fields()
+            dps.append(f["p"][r < R - 2 * W].mean() - f["p"][r > R + 2 * W].mean())
+            pts = odiag.interface_points(f["phi"], np.ones(shape[::-1], bool))
+            rs.append(odiag.kasa_fit(pts)[1])
+        g.close()
+        ratio = np.mean(dps) * np.mean(rs) / ((D - 1) * sigma)
+        print(f"D={D} R0={R}: (p_in - p_out) R / ((D-1) sigma) = {ratio:.4f}")
+        assert abs(ratio - 1.0) < (0.03 if D == 2 else 0.05), (R, ratio)
