@@ -45,7 +45,7 @@ def parse():
                          "(256^3 D3Q19), batched (64 cases), serve (Poisson serving), cpu "
                          "(oracle baseline); not in the default: table1 (the Sec. 3.1 angle "
                          "sweep), table1_3d (its 3D column at reduced size), incline2d (Sec. 3.2), "
-                         "cylinder2d (Sec. 3.3), appendixA (the "
+                         "cylinder2d (Sec. 3.3), sphere3d (its 3D case at reduced size), appendixA (the "
                          "chi cases of Table A1); the JSON line always "
                          "carries the main figures")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -69,6 +69,10 @@ def parse():
                     default=[60.0, 90.0, 120.0, 140.0])
     ap.add_argument("--table1-3d-max-steps", type=int, default=1200000)
     ap.add_argument("--table1-3d-phase", default="", help="'' (D3Q19 for g) or D3Q7")
+    ap.add_argument("--sphere-n", type=int, default=128)
+    ap.add_argument("--sphere-angles", type=lambda v: [float(x) for x in v.split(",")],
+                    default=[60.0, 90.0, 120.0])
+    ap.add_argument("--sphere-max-steps", type=int, default=1200000)
     ap.add_argument("--sweep-max-steps", type=int, default=4000000,
                     help="step cap of the incline2d / cylinder2d sections")
     ap.add_argument("--appendix-a-marks", type=lambda v: [int(x) for x in v.split(",")],
@@ -346,6 +350,19 @@ def table1_3d(a, torch, P, workloads):
                          f"R = {cs[0]['radius']}, sigma 0.005, M 0.01, W 4", angles=rows, **r)
 
 
+def sphere_3d(a, torch, P, workloads):
+    """Sec. 3.3 in 3D at reduced size (default 128^3: R_s = 30, R_i = 25,
+    W = 6): drops on a sphere, the angles of a.sphere_angles as one group."""
+    cs = [workloads.sec33_sphere_case(th, n=a.sphere_n) for th in a.sphere_angles]
+    r = _angle_sweep(torch, P, cs, a.sphere_max_steps, label="sphere3d")
+    r.pop("fits")
+    rows = [{"prescribed": th, "measured": round(t, 2), "error": round(t - th, 2)}
+            for th, t in zip(a.sphere_angles, r.pop("final"))]
+    return dict(workload=f"Sec. 3.3 3D sphere at {a.sphere_n}^3 (R_s = {60 * a.sphere_n / 256}, "
+                         f"R_i = {50 * a.sphere_n / 256}), D3Q19 FP32, W 6, sigma 0.005, M 0.01",
+                angles=rows, **r)
+
+
 def appendix_a(a, torch, P, workloads):
     """Appendix A, Fig. A1: the drop of Sec. 3.1 spreading under the three
     (chi, mu) pairs of Table A1 at theta = 60 and 120 degrees, six cases in one
@@ -523,6 +540,10 @@ def main():
         with torch.cuda.stream(stream):
             line["table1_3d"] = table1_3d(a, torch, P, workloads)
         progress("table1_3d done")
+    if "sphere3d" in a.sec:
+        with torch.cuda.stream(stream):
+            line["sphere_3d"] = sphere_3d(a, torch, P, workloads)
+        progress("sphere3d done")
     if "appendixA" in a.sec:
         with torch.cuda.stream(stream):
             line["appendix_a"] = appendix_a(a, torch, P, workloads)

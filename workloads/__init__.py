@@ -212,6 +212,23 @@ def sec33_cylinder_case(theta, width=6.0, n=256):
     return c
 
 
+def sec33_sphere_case(theta, n=256, width=6.0):
+    """Sec. 3.3 in 3D: a solid sphere of radius R_s = 60 centred at
+    (n/2, n/2, n/2 - 50) in an n^3 box (scaled with n / 256), periodic in x and
+    y and closed in z; a drop of R_i = 50 centred at (n/2, n/2, n/2).  The wall
+    sphere of the angle fit has radius R_s - 1.  sigma = 0.005, M = 0.01,
+    rho 10/1, nu 0.1 in both phases, W = 6, D3Q19 FP32."""
+    shape = (n, n, n)
+    k = n / 256.0
+    rs, centre = 60.0 * k, (n / 2.0, n / 2.0, n / 2.0 - 50.0 * k)
+    mask = ball(shape, centre, rs)
+    phi0 = droplet(shape, (n / 2.0, n / 2.0, n / 2.0), 50.0 * k, width)
+    wall = dict(kind="ball", center=centre, radius=rs - 1.0)
+    c = _case("D3Q19", shape, (True, True, False), mask, phi0, theta, 0.005, width, wall)
+    c.update(mobility=0.01, storage="f32", name=f"sec33-sphere-theta{int(theta)}")
+    return c
+
+
 def cylinder_batch(seed=3, n_cases=64):
     """64 D2Q9 cylinder cases, sizes U{128..768 step 16} x half, R_c ~ U[0.2, 0.4] Ny,
     droplet 0.3 R_c, theta ~ U[30, 150] deg, W = 4, FP32."""
