@@ -278,3 +278,17 @@ def test_theta_map_with_chi_case_refused(P):
     assert P.lib.pflbm_footprint(ct.byref(prm), ct.byref(n)) == -6
     with pytest.raises(ValueError):
         oracle_for(c)
+
+
+def test_sec33_sphere_geometry(P):
+    """The Sec. 3.3 3D input (scaled): a sphere of R_s = 60 k centred at
+    (n/2, n/2, n/2 - 50 k), k = n / 256, the drop of R_i = 50 k at the box
+    centre, wall sphere of radius R_s - 1 for the angle fit; it classifies."""
+    c = workloads.sec33_sphere_case(90.0, n=64)
+    m = c["mask"]
+    k = 64 / 256.0
+    cz = 32 - 50 * k
+    assert m[int(cz), 32, 32] == 1 and m[int(cz + 60 * k) + 1, 32, 32] == 0
+    assert c["wall"]["kind"] == "ball" and c["wall"]["radius"] == 60 * k - 1
+    assert c["phi0"][32, 32, 32] > 0.99 and c["periodic"] == (True, True, False)
+    assert P.classify(P.params_from_case(c, "f32"), m).any()
