@@ -45,7 +45,8 @@ def parse():
                          "(256^3 D3Q19), batched (64 cases), serve (Poisson serving), cpu "
                          "(oracle baseline); not in the default: table1 (the Sec. 3.1 angle "
                          "sweep), table1_3d (its 3D column at reduced size), incline2d (Sec. 3.2), "
-                         "cylinder2d (Sec. 3.3), sphere3d (its 3D case at reduced size), appendixA (the "
+                         "cylinder2d (Sec. 3.3), incline3d and sphere3d (their 3D cases at reduced size), "
+                         "appendixA (the "
                          "chi cases of Table A1); the JSON line always "
                          "carries the main figures")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -69,6 +70,11 @@ def parse():
                     default=[60.0, 90.0, 120.0, 140.0])
     ap.add_argument("--table1-3d-max-steps", type=int, default=1200000)
     ap.add_argument("--table1-3d-phase", default="", help="'' (D3Q19 for g) or D3Q7")
+    ap.add_argument("--incline3d-n", type=int, default=128)
+    ap.add_argument("--incline3d-angles", type=lambda v: [float(x) for x in v.split(",")],
+                    default=[60.0, 120.0])
+    ap.add_argument("--incline3d-max-steps", type=int, default=1200000)
+    ap.add_argument("--incline3d-phase", default="", help="'' (D3Q19 for g) or D3Q7")
     ap.add_argument("--sphere-n", type=int, default=128)
     ap.add_argument("--sphere-angles", type=lambda v: [float(x) for x in v.split(",")],
                     default=[60.0, 90.0, 120.0])
@@ -350,6 +356,25 @@ def table1_3d(a, torch, P, workloads):
                          f"R = {cs[0]['radius']}, sigma 0.005, M 0.01, W 4", angles=rows, **r)
 
 
+def incline_3d(a, torch, P, workloads):
+    """Sec. 3.2 in 3D at reduced size (default 128^3, R = 25, W = 6): drops on
+    the staircase plane z = slope x for slopes 1, 0.5, 0.25 and the angles of
+    a.incline3d_angles, as one group (phase lattice a.incline3d_phase)."""
+    combos = [(s_, th) for s_ in workloads.SEC32_SLOPES for th in a.incline3d_angles]
+    cs = [workloads.sec32_incline_case_3d(th, s_, n=a.incline3d_n) for s_, th in combos]
+    if a.incline3d_phase:
+        for c in cs:
+            c["phase_lattice"] = a.incline3d_phase
+    r = _angle_sweep(torch, P, cs, a.incline3d_max_steps, label="incline3d")
+    r.pop("fits")
+    rows = [{"slope": s_, "prescribed": th, "measured": round(t, 2), "error": round(t - th, 2)}
+            for (s_, th), t in zip(combos, r.pop("final"))]
+    lat = "D3Q19/" + a.incline3d_phase if a.incline3d_phase else "D3Q19"
+    return dict(workload=f"Sec. 3.2 3D incline at {a.incline3d_n}^3, {lat} FP32, R = "
+                         f"{50 * a.incline3d_n / 256}, W 6, sigma 0.005, M 0.01",
+                angles=rows, **r)
+
+
 def sphere_3d(a, torch, P, workloads):
     """Sec. 3.3 in 3D at reduced size (default 128^3: R_s = 30, R_i = 25,
     W = 6): drops on a sphere, the angles of a.sphere_angles as one group."""
@@ -540,6 +565,10 @@ def main():
         with torch.cuda.stream(stream):
             line["table1_3d"] = table1_3d(a, torch, P, workloads)
         progress("table1_3d done")
+    if "incline3d" in a.sec:
+        with torch.cuda.stream(stream):
+            line["incline_3d"] = incline_3d(a, torch, P, workloads)
+        progress("incline3d done")
     if "sphere3d" in a.sec:
         with torch.cuda.stream(stream):
             line["sphere_3d"] = sphere_3d(a, torch, P, workloads)

@@ -194,6 +194,26 @@ def sec32_incline_case(theta, slope, width=4.0, n=256):
     return c
 
 
+def sec32_incline_case_3d(theta, slope, n=256, width=6.0):
+    """Sec. 3.2 in 3D: an n^3 box, closed on all sides, solid below the plane
+    z = slope x; a drop of R = 50 (scaled with n / 256) centred on the plane at
+    (n/2, n/2, slope n/2).  The wall the angle is measured against is that plane
+    moved one node into the solid along its normal.  sigma = 0.005, M = 0.01,
+    rho 10/1, nu 0.1 in both phases, W = 6, D3Q19 FP32."""
+    shape = (n, n, n)
+    gam = math.atan(slope)
+    mask = inclined_plane(shape, (0.0, 0.0), math.degrees(gam))
+    nrm = (-math.sin(gam), 0.0, math.cos(gam))
+    x0 = n / 2.0
+    R = 50.0 * n / 256.0
+    phi0 = droplet(shape, (x0, n / 2.0, slope * x0), R, width)
+    wall = dict(kind="plane", point=(-nrm[0], 0.0, -nrm[2]), normal=nrm)
+    c = _case("D3Q19", shape, (False, False, False), mask, phi0, theta, 0.005, width, wall)
+    c.update(mobility=0.01, storage="f32", radius=R,
+             name=f"sec32-3d-slope{slope}-theta{int(theta)}")
+    return c
+
+
 def sec33_cylinder_case(theta, width=6.0, n=256):
     """Sec. 3.3 in 2D: a solid cylinder of radius R_s = 60 centred at
     (n/2, n/2 - 50) in an n x n box (scaled with n), periodic in x and closed in
