@@ -292,3 +292,19 @@ def test_sec33_sphere_geometry(P):
     assert c["wall"]["kind"] == "ball" and c["wall"]["radius"] == 60 * k - 1
     assert c["phi0"][32, 32, 32] > 0.99 and c["periodic"] == (True, True, False)
     assert P.classify(P.params_from_case(c, "f32"), m).any()
+
+
+def test_sec32_incline_3d_geometry(P):
+    """The Sec. 3.2 3D input (scaled): solid below z = slope x, drop centred
+    on the plane at (n/2, n/2, slope n/2), wall plane one node into the solid."""
+    import math
+    for slope in workloads.SEC32_SLOPES:
+        c = workloads.sec32_incline_case_3d(60.0, slope, n=48)
+        m = c["mask"]
+        x, y = 40, 10
+        zc = slope * x
+        assert m[int(zc) - 1, y, x] == 1 and m[int(zc) + 2, y, x] == 0
+        assert c["phi0"][int(round(slope * 24)) + 3, 24, 24] > 0.99
+        n_ = c["wall"]["normal"]
+        assert abs(math.hypot(*n_) - 1) < 1e-12 and abs(-n_[0] / n_[2] - slope) < 1e-12
+        assert P.classify(P.params_from_case(c, "f32"), m).any()
