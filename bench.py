@@ -285,7 +285,7 @@ def _angle_sweep(torch, P, cases, max_steps, chunk=100000, label="sweep"):
         if len(hist) >= 3 and all(abs(x - y) < 0.02 for x, y in zip(hist[-1], hist[-3])):
             break
         if time.perf_counter() - t_said > 30.0:
-            progress(f"{label}: {steps} steps")
+            progress(f"{label}: {steps} steps, theta {[round(t, 2) for t in hist[-1]]}")
             t_said = time.perf_counter()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
