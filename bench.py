@@ -40,9 +40,10 @@ def parse():
     ap.add_argument("--chunk", type=int, default=100, help="steps per captured HIP graph")
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--variant", type=int, default=1, help="fused step tile variant")
-    ap.add_argument("--sections", default="main,twin,3d,batched,serve,cpu",
+    ap.add_argument("--sections", default="main,twin,3d,precision,batched,serve,cpu",
                     help="comma list of: main (the 1024x512 line), twin (8192x4096), 3d "
-                         "(256^3 D3Q19), batched (64 cases), serve (Poisson serving), cpu "
+                         "(256^3 D3Q19), precision (each storage type against the stored FP64 "
+                         "oracle run), batched (64 cases), serve (Poisson serving), cpu "
                          "(oracle baseline); not in the default: table1 (the Sec. 3.1 angle "
                          "sweep), table1_3d (its 3D column at reduced size), incline2d (Sec. 3.2), "
                          "cylinder2d (Sec. 3.3), incline3d and sphere3d (their 3D cases at reduced size), "
@@ -55,12 +56,16 @@ def parse():
     ap.add_argument("--steps-3d", type=int, default=400)
     ap.add_argument("--err-steps-3d", type=int, default=2000)
     ap.add_argument("--chunk-3d", type=int, default=20)
+    ap.add_argument("--variant-3d", default="7,8",
+                    help="step variants (FP32,FP16-dev) for the 256^3 D3Q19 workload")
     ap.add_argument("--variant-d3q7", default="7,8",
                     help="step variants (FP32,FP16-dev) for the 3D workload with D3Q7 for g")
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-tol", type=float, default=1e-3)
     ap.add_argument("--serve-chunk", type=int, default=1000)
+    ap.add_argument("--serve-cap-2d", type=int, default=100000)
+    ap.add_argument("--serve-cap-3d", type=int, default=30000)
     ap.add_argument("--serve-alone-sample", type=int, default=3000)
     ap.add_argument("--serve-util70", type=int, default=1)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
@@ -89,8 +94,24 @@ def parse():
     return a
 
 
-def time_steps(torch, case, steps, warmup):
-    case.step(warmup)
+def graph_chunk_for(steps, chunk):
+    """Steps per captured HIP graph for a timed run of `steps`: the requested
+    chunk, or the whole run when it is shorter, made even (a replay must leave
+    the ping-pong parity where it found it).  The timed region then replays
+    graphs whatever --steps is; an odd remainder step runs eagerly."""
+    k = max(2, min(int(chunk), int(steps)))
+    return k - (k & 1)
+
+
+def time_steps(torch, case, steps, warmup, chunk):
+    """Average over `steps` timed steps (HIP events on torch's current stream,
+    which is the stream the library launches on).  The warm-up is a whole
+    number of graph replays (at least `warmup` steps), so the graph is captured
+    before the timed region starts.  Returns (total ms, steps per graph)."""
+    K = graph_chunk_for(steps, chunk)
+    case.set_graph_chunk(K)
+    w = -(-max(int(warmup), K) // K) * K
+    case.step(w)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -98,7 +119,19 @@ def time_steps(torch, case, steps, warmup):
     case.step(steps)
     t1.record()
     torch.cuda.synchronize()
-    return t0.elapsed_time(t1)
+    return t0.elapsed_time(t1), K
+
+
+def roofline(alg_bytes, units, ms, kernel, note=None, traffic=None):
+    """Roofline entry of one launch sequence: algorithmic bytes per launch over
+    its measured duration against the 8 TB/s HBM peak."""
+    achieved = alg_bytes * units / (ms / 1e3) / 1e9
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+         "alg_bytes_per_node": alg_bytes, "nodes_per_launch": units, "avg_ms": round(ms, 5)}
+    if note:
+        r["note"] = note
+    return r
 
 
 def kernel_source_hash():
@@ -110,9 +143,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name, nodes):
-    """HBM bytes per launch of the fused step from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+def measured_traffic(name, nodes, prefix=""):
+    """HBM bytes per launch sequence (one step) from a committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None.  The
+    summary's `<prefix>fetch_kib_per_step` / `<prefix>write_kib_per_step` (or,
+    for one-kernel steps, `fetch_kib_per_dispatch` / `write_kib_per_dispatch`)
+    are scaled by the copy-calibrated factors it records."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None, "no counter summary"
@@ -123,32 +159,47 @@ def measured_traffic(name, nodes):
             kv[k.strip().lstrip("- ")] = v.strip()
     if kv.get("kernel_source_sha1") != kernel_source_hash():
         return None, "kernel changed since the counters were taken"
-    fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"]) * 1024
-    write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"]) * 1024
+    fk = prefix + "fetch_kib_per_step" if prefix + "fetch_kib_per_step" in kv else "fetch_kib_per_dispatch"
+    wk = prefix + "write_kib_per_step" if prefix + "write_kib_per_step" in kv else "write_kib_per_dispatch"
+    if fk not in kv or wk not in kv:
+        return None, "no counters for this variant"
+    fetch = float(kv[fk]) * float(kv["fetch_scale"]) * 1024
+    write = float(kv[wk]) * float(kv["write_scale"]) * 1024
     return fetch + write, f"{(fetch + write) / nodes:.1f} B/node ({fetch / nodes:.1f} read, {write / nodes:.1f} write)"
 
 
 def inclined_3d(a, torch, P, workloads, stream):
     """256^3 D3Q19, 30-degree staircase wall, sphere R = 40, theta = 45;
     FP32 against FP16-deviation storage (MLUPS, roofline at 313 / 165 B per node,
-    and the FP16 field error against FP32 after the same steps)."""
+    and the FP16 field error against FP32 after the same steps).  One step is
+    the launch sequence of the chosen step variant (split: the phi pass and the
+    collide pass); the roofline entry takes the whole step as its unit."""
     out = {}
     fields = {}
+    var = dict(zip(("f32", "f16dev"), (int(v) for v in str(a.variant_3d).split(","))))
     for st, alg in (("f32", 313), ("f16dev", 165)):
         c = workloads.inclined_3d_256(storage=st, n=256)
         h = P.Case.from_case(c, st, stream=stream)
-        h.set_graph_chunk(a.chunk_3d)
+        h.set_step_kernel(var[st])
         nodes = int((h.classes() & 1).sum())
-        ms = time_steps(torch, h, a.steps_3d, 20)
-        h.step(a.err_steps_3d - a.steps_3d - 20)
+        ms, K = time_steps(torch, h, a.steps_3d, 20, a.chunk_3d)
+        kern = h.profile(20)
+        h.step(max(0, a.err_steps_3d - a.steps_3d - 2 * K))
         f = h.fields()
         d = h.diagnostics()
         fields[st] = f["phi"]
         mlups = nodes * 1e3 / ms * a.steps_3d / 1e6
+        traffic, note = measured_traffic(f"step_d3q19_{st}_256cubed_counters.md", nodes,
+                                         prefix=f"v{var[st]}_")
+        r = roofline(alg, nodes, ms / a.steps_3d, f"step variant {var[st]} (whole step)",
+                     traffic=traffic)
+        r["traffic_note"] = note
+        r["target_frac"] = 0.45 if st == "f32" else 0.35
         out[st] = {"MLUPS": round(mlups, 1), "ms_per_step": round(ms / a.steps_3d, 4),
                    "hbm_roofline_pct": round(100 * mlups * 1e6 * alg / (HBM_PEAK_GBS * 1e9), 2),
-                   "alg_bytes_per_node": alg, "theta_deg": round(d["theta_deg"], 3),
-                   "mass": d["mass"]}
+                   "alg_bytes_per_node": alg, "variant": var[st], "graph_chunk": K,
+                   "eager_launch_avg_ms": round(float(kern[3]), 4),
+                   "theta_deg": round(d["theta_deg"], 3), "mass": d["mass"], "roofline": r}
         zeta = (h.classes() & 1).astype(bool)
         h.close()
     out["f16dev_vs_f32_max_abs_dphi"] = float(np.abs(fields["f16dev"] - fields["f32"])[zeta].max())
@@ -162,9 +213,8 @@ def inclined_3d(a, torch, P, workloads, stream):
         c = workloads.inclined_3d_256(storage=st, n=256)
         c["phase_lattice"] = "D3Q7"
         h = P.Case.from_case(c, st, stream=stream)
-        h.set_graph_chunk(a.chunk_3d)
         h.set_step_kernel(v7[st])
-        ms = time_steps(torch, h, a.steps_3d, 20)
+        ms, K = time_steps(torch, h, a.steps_3d, 20, a.chunk_3d)
         alg = ALG_BYTES[("D3Q19/D3Q7", st)]
         mlups = nodes * 1e3 / ms * a.steps_3d / 1e6
         d7[st] = {"MLUPS": round(mlups, 1), "ms_per_step": round(ms / a.steps_3d, 4),
@@ -435,22 +485,26 @@ def progress(msg):
 
 
 def served(a, torch, P, workloads):
-    """Continuous batching over Poisson arrivals of mixed 2D / 3D wetting cases
-    (the serving workload at reduced grid sizes): an overloaded run at the
-    given arrival rate, then a run at about 70 % of the capacity the first run
-    measured.  A case is steady when max |phi(t) - phi(t - 1000)| <= serve_tol
-    at a poll every 1000 steps; caps are 2e5 steps (2D) and 1e5 (3D).  The
-    one-case-at-a-time reference is the plain solver (graph replay, the same
-    poll cadence) timed on a sample of each served case and scaled to the
-    case's step count."""
+    """Continuous batching over Poisson arrivals (mean a.serve_rate per second)
+    of mixed wetting cases at the serving workload's sizes: 2D 256x128 ..
+    1024x512 and 3D 64^3 .. 192^3, flat / inclined / curved walls, theta ~
+    U[30, 150], FP32.  Each request starts from the drop of radius 0.2 N placed
+    so that it meets the wall at its theta (start="cap") and asks for the steady
+    state: max |phi(t) - phi(t - chunk)| <= serve_tol at a poll every
+    serve_chunk steps, or the step cap (2D / 3D).  The first pass is overloaded
+    (all requests arrive within about a second); the second offers about 70 %
+    of the capacity the first measured.  The one-case-at-a-time reference is
+    the plain solver (graph replay, the same poll cadence) timed on a sample of
+    each served case and scaled to the case's step count."""
     from paper_2312_00369_amd.serve import GpuExecutor, Server
 
+    caps = {"D2Q9": a.serve_cap_2d, "D3Q19": a.serve_cap_3d}
+
     def requests(n, rate, seed):
-        reqs = workloads.serving_requests(seed=seed, n_requests=n, rate=rate, nx_range=(128, 256),
-                                 n3_range=(48, 48))
+        reqs = workloads.serving_requests(seed=seed, n_requests=n, rate=rate, start="cap")
         for r in reqs:
             r["steady_tol"] = a.serve_tol
-            r["max_steps"] = 200000 if r["lattice"] == "D2Q9" else 100000
+            r["max_steps"] = caps[r["lattice"]]
         return reqs
 
     def run_once(reqs):
@@ -463,11 +517,15 @@ def served(a, torch, P, workloads):
         keep = ("requests", "served", "steady", "wall_s", "gpu_busy_s", "utilisation",
                 "cases_per_s", "aggregate_MLUPS", "p50_time_to_steady_s", "p99_time_to_steady_s",
                 "p50_time_to_result_s", "p99_time_to_result_s", "offered_rate_per_s", "by_lattice")
-        return rec, {k: (round(summ[k], 4) if isinstance(summ[k], float) else summ[k]) for k in keep}
+        out = {k: (round(summ[k], 4) if isinstance(summ[k], float) else summ[k]) for k in keep}
+        out["achieved_rate_per_s"] = out["cases_per_s"]
+        out["steps_to_steady"] = sorted(int(r["steps"]) for r in rec if r.get("steady"))
+        return rec, out
 
     reqs = requests(a.serve_requests, a.serve_rate, 4)
     rec, s1 = run_once(reqs)
-    progress(f"served (overloaded): {s1['served']} cases in {s1['wall_s']} s")
+    progress(f"served (overloaded): {s1['served']} cases, {s1['steady']} steady, "
+             f"{s1['wall_s']} s")
     # one case at a time: per-step time of each served case alone, scaled to its steps
     t_alone = 0.0
     for r in rec:
@@ -490,13 +548,17 @@ def served(a, torch, P, workloads):
         torch.cuda.synchronize()
         t_alone += (time.perf_counter() - t0) / k * int(r["steps"])
         h.close()
-    out = {"workload": f"Poisson arrivals of mixed D2Q9 128x64..256x128 and D3Q19 48^3 "
-                       f"flat/inclined/curved wetting cases, theta U[30,150], FP32; steady = "
-                       f"max|dphi| <= {a.serve_tol} over {a.serve_chunk} steps, caps 2e5 (2D) / "
-                       f"1e5 (3D) steps",
+    sizes = sorted({tuple(q["shape"]) for q in reqs})
+    out = {"workload": f"Poisson arrivals at {a.serve_rate}/s of {len(reqs)} mixed D2Q9 256x128.."
+                       f"1024x512 and D3Q19 64^3..192^3 flat/inclined/curved wetting cases, theta "
+                       f"U[30,150], FP32, started as the drop meeting the wall at theta; steady = "
+                       f"max|dphi| <= {a.serve_tol} over {a.serve_chunk} steps, caps "
+                       f"{a.serve_cap_2d} (2D) / {a.serve_cap_3d} (3D) steps",
+           "grid_sizes": [list(v) for v in sizes],
            "overloaded": s1,
            "one_at_a_time_s_est": round(t_alone, 2),
            "throughput_vs_one_at_a_time": round(t_alone / s1["wall_s"], 2)}
+    progress("served: one-at-a-time reference done")
     if a.serve_util70 and s1["gpu_busy_s"]:
         cap = s1["served"] / s1["gpu_busy_s"]            # cases per second of busy GPU
         rate = 0.7 * cap
@@ -528,8 +590,10 @@ def cpu_baseline(c, budget_s=15.0):
             steps += 1
         dt = time.perf_counter() - t0
     return dict(value=round(nodes * steps / dt / 1e6, 4), unit="MLUPS", cores=1, kind="oracle",
+                host_cores=os.cpu_count(),
                 sample=f"{c['shape'][0]}x{c['shape'][1]} D2Q9 FP64 NumPy oracle, {steps} steps "
-                       f"after one untimed step ({dt:.1f} s, single-threaded NumPy)")
+                       f"after one untimed step ({dt:.1f} s, single-threaded NumPy on one of the "
+                       f"host's {os.cpu_count()} cores)")
 
 
 def main():
@@ -586,30 +650,28 @@ def main():
 def run(a, torch, P, workloads, stream):
     c = workloads.flat_1024x512_fp32(theta=a.theta, nx=a.nx, ny=a.ny)
     case = P.Case.from_case(c, "f32", stream=stream)
-    case.set_graph_chunk(a.chunk)
     case.set_step_kernel(a.variant)
     nodes = int((case.classes() & 1).sum())
-    ms = time_steps(torch, case, a.steps, a.warmup)
+    ms, K = time_steps(torch, case, a.steps, a.warmup, a.chunk)
     ms_step = ms / a.steps
     mlups = nodes * a.steps / (ms / 1e3) / 1e6
     d = case.diagnostics()
-    # The fused step is one launch of k_step per step, so the timed region gives
-    # its average duration directly (HIP events on the stream it launches on).
-    # Per-launch events around eager launches are reported beside it; they add
-    # the launch gaps that graph replay removes.
+    # The fused step is one launch of k_step per step and the timed region
+    # replays captured graphs of K steps, so the events over it give the
+    # kernel's average duration (plus the sub-microsecond gaps between graph
+    # nodes).  Per-launch events around eager launches are reported beside it.
     kern_ms = case.profile(a.profile_steps)
-    step_kern_ms = ms_step
     alg = ALG_BYTES[("D2Q9", "f32")]
-    achieved = alg * nodes / (step_kern_ms / 1e3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_step (fused time step, one launch per step)", "alg_bytes_per_node": alg,
-            "nodes_per_launch": nodes, "avg_ms": round(step_kern_ms, 5),
-            "eager_launch_avg_ms": round(float(kern_ms[3]), 5)}
+    roof = roofline(alg, nodes, ms_step, "k_step (fused time step, one launch per step)")
+    roof["eager_launch_avg_ms"] = round(float(kern_ms[3]), 5)
     if (a.nx, a.ny) == (1024, 512):
         traffic, note = measured_traffic("k_step_d2q9_fp32_1024x512_counters.md", nodes)
         roof["traffic"] = traffic
         roof["traffic_note"] = note
+        roof["cache_resident"] = ("the ~82 MB state fits the 256 MB Infinity Cache (MALL): the "
+                                  "counters count bytes beyond L2, which here are mostly MALL "
+                                  "hits, and frac is not an HBM-bound figure; the HBM-bound twin "
+                                  "(8192x4096) is graded against 70 %")
     # the three-kernel path on the same case, for reference
     case.set_step_kernel(-1)
     k3 = case.profile(a.profile_steps)
@@ -623,7 +685,8 @@ def run(a, torch, P, workloads, stream):
         "data": "synthetic",
         "config": {"workload": f"D2Q9 FP32 {a.nx}x{a.ny} flat-wall droplet R={80 * a.nx / 1024:g}, "
                                f"theta={a.theta:g}, W=5, rho 10/1, tau 0.8, M 0.1, sigma 1e-3",
-                   "nodes": nodes, "graph_chunk": a.chunk},
+                   "nodes": nodes, "graph_chunk": K, "timed_graph_replays": a.steps // K,
+                   "timed_eager_steps": a.steps % K},
         "hbm_roofline_pct_step": round(100 * mlups * 1e6 * alg / (HBM_PEAK_GBS * 1e9), 2),
         "roofline": roof,
         "check": {"theta_deg": round(d["theta_deg"], 3), "mass": d["mass"],
@@ -632,25 +695,32 @@ def run(a, torch, P, workloads, stream):
     case.close()
     progress("main done")
     if "twin" in a.sec:
-        # DRAM-bound twin: 8192 x 4096 (33.5 M nodes), same physics
+        # HBM-bound twin: 8192 x 4096 (33.5 M nodes), same physics
         big = workloads.flat_1024x512_fp32(theta=a.theta, nx=8192, ny=4096)
         cb = P.Case.from_case(big, "f32", stream=stream)
-        cb.set_graph_chunk(a.chunk)
         cb.set_step_kernel(a.variant)
         nb = int((cb.classes() & 1).sum())
         k = 400
-        msb = time_steps(torch, cb, k, 20)
+        msb, Kb = time_steps(torch, cb, k, 20, a.chunk)
         kb = cb.profile(20)
         mlb = nb * k / (msb / 1e3) / 1e6
+        traffic, note = measured_traffic("k_step_d2q9_fp32_8192x4096_counters.md", nb)
+        rb = roofline(alg, nb, msb / k, "k_step (fused time step, one launch per step)",
+                      traffic=traffic)
+        rb["traffic_note"] = note
+        rb["target_frac"] = 0.70
         line["dram_twin"] = {"workload": "D2Q9 FP32 8192x4096", "MLUPS": round(mlb, 1),
                              "hbm_roofline_pct": round(100 * mlb * 1e6 * alg / (HBM_PEAK_GBS * 1e9), 2),
-                             "k_step_ms": round(float(kb[3]), 4),
-                             "k_step_GBps_alg": round(alg * nb / (float(kb[3]) / 1e3) / 1e9, 1)}
+                             "ms_per_step": round(msb / k, 4), "graph_chunk": Kb,
+                             "eager_launch_avg_ms": round(float(kb[3]), 4), "roofline": rb}
         cb.close()
         progress("twin done")
     if "3d" in a.sec:
         line["inclined_3d"] = inclined_3d(a, torch, P, workloads, stream)
         progress("3d done")
+    if "precision" in a.sec:
+        line["precision_vs_oracle"] = precision(torch, P, workloads, stream)
+        progress("precision done")
     if "batched" in a.sec:
         line["batched"] = batched(a, torch, P, workloads, stream)
         progress("batched done")
@@ -661,6 +731,39 @@ def run(a, torch, P, workloads, stream):
         torch.cuda.synchronize()
         line["copy_calibration_bytes"] = 2 * x.numel() * 4
     return line
+
+
+def precision(torch, P, workloads, stream):
+    """Error of each storage type against the FP64 oracle on the 128x64 flat-wall
+    case (the stored oracle run of tests/golden, 5000 steps): |dphi|_inf over
+    fluid and boundary nodes, the contact angle and the relative mass difference
+    at the end, and the largest relative mass difference along the trajectory
+    (every 100 steps)."""
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "flat_128x64_fp64.npz"),
+                   allow_pickle=False)
+    c = workloads.flat_128x64_fp64()
+    every = int(gold["mass_every"])
+    out = {"workload": "128x64 D2Q9 flat wall, R=20, theta=60, W=4, 5000 steps, against the "
+                       "stored FP64 oracle run"}
+    for st in ("f64", "f32", "f16dev"):
+        h = P.Case.from_case(c, st, stream=stream)
+        zeta = (h.classes() & 1).astype(bool)
+        h.set_graph_chunk(every)
+        masses = []
+        for k in range(len(gold["mass"])):
+            masses.append(h.diagnostics()["mass"])
+            if k + 1 < len(gold["mass"]):
+                h.step(every)
+        f = h.fields()
+        d = h.diagnostics()
+        rel = np.abs(np.array(masses) - gold["mass"]) / gold["mass"]
+        out[st] = {"max_abs_dphi": float(np.abs(f["phi"] - gold["phi"])[zeta].max()),
+                   "theta_deg": round(d["theta_deg"], 6),
+                   "theta_err_deg": float(abs(d["theta_deg"] - float(gold["theta"]))),
+                   "rel_mass_err_end": float(rel[-1]), "rel_mass_err_max": float(rel.max())}
+        h.close()
+    out["oracle_theta_deg"] = round(float(gold["theta"]), 6)
+    return out
 
 
 if __name__ == "__main__":

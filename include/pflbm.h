@@ -200,8 +200,12 @@ int pflbm_fp16_scales(pflbm_handle h, double* scale_f, double* scale_g);
 int pflbm_set_fp16_scales(pflbm_handle h, double scale_f, double scale_g);
 
 /* Current fields as FP64 host arrays of nx*ny*nz (u: D arrays, component-major).
- * Any pointer may be NULL.  phi holds the ghost value on ghost nodes and 0 on
- * other solid nodes; p, u and mu are 0 on zeta = 0 nodes.  (sync) */
+ * Any pointer may be NULL.  phi = sum_i g_i (Sec. 2.1.3, Eq. order-parameter);
+ * p and u from sum_i f_i and rho u = sum_i c_i f_i + F/2 with F = mu grad phi
+ * + F_b (Sec. 2.1.2, the pressure below Eq. GGi), u = 0 on boundary nodes;
+ * mu of Eq. (chemical_potencial2).  phi holds the ghost value (Sec. 2.2.2) on
+ * ghost nodes and 0 on other solid nodes; p, u and mu are 0 on zeta = 0
+ * nodes.  (sync) */
 int pflbm_fields(pflbm_handle h, double* phi, double* p, double* u, double* mu);
 
 /* Node classes as nx*ny*nz bytes: bit 0 zeta (fluid or boundary), bit 1 fluid
@@ -209,12 +213,21 @@ int pflbm_fields(pflbm_handle h, double* phi, double* p, double* u, double* mu);
 int pflbm_node_classes(pflbm_handle h, uint8_t* classes);
 
 /* Run the reductions now and fill *d.  Also refreshes the steady-state
- * reference field.  (sync) */
+ * reference field.  mass: FP64 sum of phi = sum_i g_i (Eq. order-parameter)
+ * over fluid and boundary nodes, taken from the stored populations in FP64;
+ * s_sum: sum of s = u . grad phi (the source of Eq. F_i sums to -s); theta:
+ * contact angle from a least-squares circle / sphere through the phi = 1/2
+ * crossings at least diag_width from the wall, against the wall plane (cos theta
+ * = -h / R, Sec. 3.1) or the wall circle / sphere (Eq. initialphi_cirref solved
+ * for theta, Sec. 3.3); steady_residual: max |phi - phi at the previous call|.
+ * (sync) */
 int pflbm_diagnostics(pflbm_handle h, pflbm_diag* d);
 
-/* Checkpoint: raw device state (populations, s, step count, scales).
+/* Checkpoint: raw device state (populations, s, step count, and for
+ * FP16-deviation storage the scales the populations are stored with).
  * pflbm_state_size gives the byte count; set_state accepts only a blob from a
- * case with identical parameters.  Resuming is bit-identical.  (sync) */
+ * case with identical parameters and takes over the blob's scales (dropping any
+ * captured graph when they differ).  Resuming is bit-identical.  (sync) */
 int pflbm_state_size(pflbm_handle h, size_t* bytes);
 int pflbm_get_state(pflbm_handle h, void* host, size_t bytes);
 int pflbm_set_state(pflbm_handle h, const void* host, size_t bytes);

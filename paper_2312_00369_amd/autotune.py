@@ -1,7 +1,7 @@
 """Launch-shape autotuner for the fused and batched step kernels.
 
-Candidates are the fused-step tile variants the library exports
-(`pflbm_step_variants`), with and without the XCD-contiguous tile order, and for
+Candidates are the step variants the library exports (`pflbm_step_variants`),
+each with the three XCD dispatch orders (round-robin, contiguous, chunked), and for
 groups one workgroup per table entry or a persistent grid of 1, 2 or 4
 workgroups per CU.  Each candidate
 is timed on the real case with graph replay; the case's state is saved before
@@ -18,6 +18,9 @@ import time
 from . import pflbm as _p
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pflbm_autotune.json")
+# XCD dispatch orders of the step kernels (pflbm_set_step_options): round-robin,
+# one contiguous run per XCD, chunks of whole tile rows dealt round-robin
+XCD_ORDERS = (0, 1, 2)
 
 
 def gpu_arch():
@@ -91,7 +94,7 @@ def tune_case(case, steps=200, cache=None, arch=None, timer=None, sync=None):
     lattice = "D2Q9" if prm.lattice == _p.D2Q9 else "D3Q19"
     results = []
     for v in range(len(_p.step_variants(lattice))):
-        for xo in (False, True):
+        for xo in XCD_ORDERS:
             case.set_step_kernel(v)
             case.set_step_options(xo, False)
             sec = timer(case.step, steps, sync)
@@ -107,17 +110,44 @@ def tune_case(case, steps=200, cache=None, arch=None, timer=None, sync=None):
     return out
 
 
-def tune_group(group, steps=100, blocks_per_cu=(0, 1, 2, 4), timer=None, sync=None):
+def group_shape_class(group):
+    """Shape class of a group: member count and log2 of its total node count,
+    e.g. "2d-x64-n2^23"."""
+    ms = group.members
+    n = sum(math.prod(int(v) for v in m.shape) for m in ms)
+    return f"{len(ms[0].shape)}d-x{len(ms)}-n2^{int(round(math.log2(max(n, 1))))}"
+
+
+def group_cache_key(arch, group):
+    prm = group.members[0].params
+    key = cache_key(arch, prm.lattice, prm.storage, (1,))
+    return key.rsplit("/", 1)[0] + "/group-" + group_shape_class(group)
+
+
+def tune_group(group, steps=100, blocks_per_cu=(0, 1, 2, 4), cache=None, arch=None,
+               variants=None, timer=None, sync=None):
     """Pick the fastest (variant, blocks per CU) for a group; every member's
-    state is restored afterwards.  Applies and returns the choice."""
+    state is restored afterwards.  Applies and returns the choice.  With a
+    cache, a stored choice for the same (architecture, lattice, storage, group
+    shape class) is applied without timing, and a new choice is stored."""
     timer = timer or _wall_timer
     sync = sync or _torch_sync
     if not group.members:
         return None
+    key = None
+    if cache is not None:
+        arch = arch or gpu_arch()
+        key = group_cache_key(arch, group)
+        hit = cache.get(key)
+        if hit:
+            group.set_tile(hit["variant"], hit["blocks_per_cu"])
+            return dict(hit, cached=True, key=key)
     blobs = [m.get_state() for m in group.members]
     lattice = "D2Q9" if group.members[0].params.lattice == _p.D2Q9 else "D3Q19"
+    if variants is None:
+        variants = range(len(_p.step_variants(lattice)))
     results = []
-    for v in range(len(_p.step_variants(lattice))):
+    for v in variants:
         for bpc in blocks_per_cu:
             group.set_tile(v, bpc)
             sec = timer(group.step, steps, sync)
@@ -126,4 +156,6 @@ def tune_group(group, steps=100, blocks_per_cu=(0, 1, 2, 4), timer=None, sync=No
         m.set_state(b)
     best = min(results, key=lambda r: r["ms"])
     group.set_tile(best["variant"], best["blocks_per_cu"])
-    return dict(best, candidates=results)
+    if cache is not None:
+        cache.put(key, {k: best[k] for k in ("variant", "blocks_per_cu", "ms")})
+    return dict(best, candidates=results, key=key)

@@ -876,22 +876,28 @@ int pflbm_set_fp16_scales(pflbm_handle h, double scale_f, double scale_g) {
   return PFLBM_OK;
 }
 
-int pflbm_state_size(pflbm_handle h, size_t* bytes) {
-  clear_error();
-  if (int rc = check_handle(h)) return rc;
-  if (!bytes) return set_error(PFLBM_EINVAL, "bytes is NULL");
-  *bytes = 64 + h->lay.f_bytes + h->lay.g_bytes + h->lay.c_bytes;
-  return PFLBM_OK;
-}
-
 namespace {
+// Checkpoint blob: a kStateHeader-byte header, then the current f buffer, the
+// current g buffer and s.  FP16-deviation buffers hold value * scale, so the
+// header carries the scales they were written with.
+constexpr size_t kStateHeader = 128;
 struct StateHeader {
   char magic[8];
   uint64_t f_bytes, g_bytes, c_bytes;
   int64_t step;
   int32_t lattice, storage, nx, ny, nz, pad_;
+  double scale_f, scale_g;     // FP16-deviation scales of the stored buffers (1 otherwise)
 };
+static_assert(sizeof(StateHeader) <= kStateHeader, "state header");
 }  // namespace
+
+int pflbm_state_size(pflbm_handle h, size_t* bytes) {
+  clear_error();
+  if (int rc = check_handle(h)) return rc;
+  if (!bytes) return set_error(PFLBM_EINVAL, "bytes is NULL");
+  *bytes = kStateHeader + h->lay.f_bytes + h->lay.g_bytes + h->lay.c_bytes;
+  return PFLBM_OK;
+}
 
 int pflbm_get_state(pflbm_handle h, void* host, size_t bytes) {
   clear_error();
@@ -900,7 +906,7 @@ int pflbm_get_state(pflbm_handle h, void* host, size_t bytes) {
   pflbm_state_size(h, &need);
   if (!host || bytes < need) return set_error(PFLBM_EINVAL, "state buffer too small (%zu < %zu)", bytes, need);
   StateHeader hd{};
-  std::memcpy(hd.magic, "PFLBMST1", 8);
+  std::memcpy(hd.magic, "PFLBMST2", 8);
   hd.f_bytes = h->lay.f_bytes;
   hd.g_bytes = h->lay.g_bytes;
   hd.c_bytes = h->lay.c_bytes;
@@ -908,10 +914,13 @@ int pflbm_get_state(pflbm_handle h, void* host, size_t bytes) {
   hd.lattice = h->prm.lattice;
   hd.storage = h->prm.storage;
   hd.nx = h->prm.nx; hd.ny = h->prm.ny; hd.nz = h->prm.nz;
+  const bool half = h->prm.storage == PFLBM_FP16_DEV;
+  hd.scale_f = half ? (double)h->dv.phys.scale_f : 1.0;
+  hd.scale_g = half ? (double)h->dv.phys.scale_g : 1.0;
   unsigned char* p = static_cast<unsigned char*>(host);
-  std::memset(p, 0, 64);
+  std::memset(p, 0, kStateHeader);
   std::memcpy(p, &hd, sizeof hd);
-  p += 64;
+  p += kStateHeader;
   PFLBM_HIP(hipMemcpyAsync(p, h->f[h->cur], h->lay.f_bytes, hipMemcpyDeviceToHost, h->stream));
   PFLBM_HIP(hipMemcpyAsync(p + h->lay.f_bytes, h->g[h->cur], h->lay.g_bytes,
                            hipMemcpyDeviceToHost, h->stream));
@@ -929,12 +938,20 @@ int pflbm_set_state(pflbm_handle h, const void* host, size_t bytes) {
   if (!host || bytes < need) return set_error(PFLBM_EINVAL, "state buffer too small (%zu < %zu)", bytes, need);
   StateHeader hd;
   std::memcpy(&hd, host, sizeof hd);
-  if (std::memcmp(hd.magic, "PFLBMST1", 8) != 0 || hd.f_bytes != h->lay.f_bytes ||
+  if (std::memcmp(hd.magic, "PFLBMST2", 8) != 0 || hd.f_bytes != h->lay.f_bytes ||
       hd.g_bytes != h->lay.g_bytes ||
       hd.c_bytes != h->lay.c_bytes || hd.lattice != h->prm.lattice ||
       hd.storage != h->prm.storage || hd.nx != h->prm.nx || hd.ny != h->prm.ny || hd.nz != h->prm.nz)
     return set_error(PFLBM_EINVAL, "state blob does not match this case");
-  const unsigned char* p = static_cast<const unsigned char*>(host) + 64;
+  const bool half = h->prm.storage == PFLBM_FP16_DEV;
+  if (half) {
+    for (double v : {hd.scale_f, hd.scale_g}) {
+      int e;
+      if (!(v > 0.0) || !std::isfinite(v) || std::frexp(v, &e) != 0.5 || e < -60 || e > 60)
+        return set_error(PFLBM_EINVAL, "state blob holds an invalid FP16 scale (%g)", v);
+    }
+  }
+  const unsigned char* p = static_cast<const unsigned char*>(host) + kStateHeader;
   PFLBM_HIP(hipMemcpyAsync(h->f[h->cur], p, h->lay.f_bytes, hipMemcpyHostToDevice, h->stream));
   PFLBM_HIP(hipMemcpyAsync(h->g[h->cur], p + h->lay.f_bytes, h->lay.g_bytes,
                            hipMemcpyHostToDevice, h->stream));
@@ -943,6 +960,13 @@ int pflbm_set_state(pflbm_handle h, const void* host, size_t bytes) {
   PFLBM_HIP(hipStreamSynchronize(h->stream));
   h->step = hd.step;
   h->snap_valid = false;
+  if (half && ((float)hd.scale_f != h->dv.phys.scale_f || (float)hd.scale_g != h->dv.phys.scale_g)) {
+    // the buffers now hold values at the blob's scales; captured graphs (and a
+    // group's member descriptors) carry the old ones
+    h->dv.phys.scale_f = (float)hd.scale_f;
+    h->dv.phys.scale_g = (float)hd.scale_g;
+    drop_graph(h);
+  }
   group_member_changed(h);
   return PFLBM_OK;
 }
@@ -1022,7 +1046,9 @@ int pflbm_set_step_options(pflbm_handle h, int32_t xcd_order, int32_t nontempora
   clear_error();
   if (int rc = check_handle(h)) return rc;
   drop_graph(h);
-  h->dv.phys.xcd_order = xcd_order ? 1 : 0;
+  if (xcd_order < 0 || xcd_order > 2)
+    return set_error(PFLBM_EINVAL, "xcd_order must be 0, 1 or 2 (got %d)", xcd_order);
+  h->dv.phys.xcd_order = xcd_order;
   h->dv.phys.nt_store = nontemporal ? 1 : 0;
   return PFLBM_OK;
 }

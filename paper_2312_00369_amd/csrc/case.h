@@ -95,7 +95,7 @@ int run_init_g(pflbm_case_s* h);
 int run_reduce(pflbm_case_s* h, int update_snap, double* host_rec);
 int run_step_eager(pflbm_case_s* h);
 int run_step_fused(pflbm_case_s* h);
-constexpr int kStepVariants = 11;   // largest count over the lattices
+constexpr int kStepVariants = 13;   // largest count over the lattices
 int step_variant_count(int D);
 int step_variant_tile(int D, int v, int tile[5]);
 

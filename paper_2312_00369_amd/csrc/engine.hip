@@ -63,19 +63,21 @@ int run_rescale(pflbm_case_s* h, int set_g, float factor) {
 
 #undef PFLBM_ENTRY
 
-int step_variant_count(int D) { return D == 2 ? 8 : 11; }
+int step_variant_count(int D) { return D == 2 ? 8 : 13; }
 
 // Tile of each step variant: threads (64, by, bz), nodes (64, ty, tz).
 int step_variant_tile(int D, int v, int tile[5]) {
   // variants 0-4: fused one-kernel step; 5-7: split step (phi pass + collide
-  // pass); 8-10 (D3Q19 only): split step marching along z
+  // pass); 8-10 (3D only): split step marching along z; 11-12 (3D only): fused
+  // one-kernel step marching along z
   static const int t2[8][5] = {
       {4, 1, 64, 4, 1}, {4, 1, 64, 8, 1}, {4, 1, 64, 16, 1}, {8, 1, 64, 16, 1}, {2, 1, 64, 8, 1},
       {4, 1, 64, 4, 1}, {8, 1, 64, 8, 1}, {16, 1, 64, 16, 1}};
-  static const int t3[11][5] = {
+  static const int t3[13][5] = {
       {2, 2, 64, 2, 2}, {2, 2, 64, 4, 2}, {2, 2, 64, 4, 4}, {4, 4, 64, 4, 4}, {4, 2, 64, 4, 4},
       {4, 4, 64, 4, 4}, {2, 2, 64, 2, 2}, {4, 2, 64, 4, 2},
-      {4, 1, 64, 4, 16}, {8, 1, 64, 8, 16}, {8, 1, 64, 8, 32}};
+      {4, 1, 64, 4, 16}, {8, 1, 64, 8, 16}, {8, 1, 64, 8, 32},
+      {4, 1, 64, 4, 32}, {8, 1, 64, 8, 32}};
   if (v < 0 || v >= step_variant_count(D)) return -1;
   for (int k = 0; k < 5; ++k) tile[k] = D == 2 ? t2[v][k] : t3[v][k];
   return 0;

@@ -64,8 +64,8 @@ struct Engine {
   static int step_v(pflbm_case_s* h) {
     const Geo& G = h->dv.geo;
     constexpr int TY = BY * KY, TZ = (L::D == 3) ? BZ * KZ : 1;
-    const unsigned nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY, nbz = (G.PZ + TZ - 1) / TZ;
-    const dim3 grid(nbx * nby * nbz, 1, 1);
+    const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY, nbz = (G.PZ + TZ - 1) / TZ;
+    const dim3 grid(TileOrder{nbx, nby, nbz, h->dv.phys.xcd_order}.grid(), 1, 1);
     const dim3 block(64, BY, (L::D == 3) ? BZ : 1);
     const int c = h->cur;
     constexpr int bz = (L::D == 3) ? BZ : 1, kz = (L::D == 3) ? KZ : 1;
@@ -85,10 +85,11 @@ struct Engine {
     int rc = phi(h);
     if (rc) return rc;
     constexpr int bz = (L::D == 3) ? BZ : 1;
-    const unsigned nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY, nbz = (G.PZ + bz - 1) / bz;
+    const int nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY, nbz = (G.PZ + bz - 1) / bz;
+    const unsigned ngrid = TileOrder{nbx, nby, nbz, h->dv.phys.xcd_order}.grid();
     const int c = h->cur;
     auto go = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3(nbx * nby * nbz), dim3(64, BY, bz), 0, h->stream, h->nodes,
+      hipLaunchKernelGGL(kern, dim3(ngrid), dim3(64, BY, bz), 0, h->stream, h->nodes,
                          h->f[c], h->g[c], h->f[1 - c], h->g[1 - c], static_cast<C*>(h->s),
                          static_cast<const C*>(h->phi), G, h->dv.phys);
     };
@@ -104,10 +105,11 @@ struct Engine {
       const Geo& G = h->dv.geo;
       int rc = phi(h);
       if (rc) return rc;
-      const unsigned nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY, nbz = (G.PZ + TZ - 1) / TZ;
+      const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY, nbz = (G.PZ + TZ - 1) / TZ;
+      const unsigned ngrid = TileOrder{nbx, nby, nbz, h->dv.phys.xcd_order}.grid();
       const int c = h->cur;
       auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(nbx * nby * nbz), dim3(64, TY), 0, h->stream, h->nodes,
+        hipLaunchKernelGGL(kern, dim3(ngrid), dim3(64, TY), 0, h->stream, h->nodes,
                            h->f[c], h->g[c], h->f[1 - c], h->g[1 - c], static_cast<C*>(h->s),
                            static_cast<const C*>(h->phi), G, h->dv.phys);
       };
@@ -117,6 +119,26 @@ struct Engine {
       return PFLBM_OK;
     }
     return set_error(PFLBM_EINVAL, "z-marching variants are for D3Q19");
+  }
+
+  template <int TY, int TZ>
+  static int march_v(pflbm_case_s* h) {
+    if constexpr (L::D == 3) {
+      const Geo& G = h->dv.geo;
+      const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY, nbz = (G.PZ + TZ - 1) / TZ;
+      const unsigned ngrid = TileOrder{nbx, nby, nbz, h->dv.phys.xcd_order}.grid();
+      const int c = h->cur;
+      auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(ngrid), dim3(64, TY), 0, h->stream, h->nodes,
+                           h->f[c], h->g[c], h->f[1 - c], h->g[1 - c], static_cast<C*>(h->s), G,
+                           h->dv.phys);
+      };
+      if (h->o32) go(k_stepZ<L, S, TY, TZ, true>);
+      else go(k_stepZ<L, S, TY, TZ, false>);
+      PFLBM_HIP(hipGetLastError());
+      return PFLBM_OK;
+    }
+    return set_error(PFLBM_EINVAL, "z-marching variants are for 3D lattices");
   }
 
   static int step_fused(pflbm_case_s* h) {
@@ -145,6 +167,8 @@ struct Engine {
         case 8: return column_v<4, 16>(h);
         case 9: return column_v<8, 16>(h);
         case 10: return column_v<8, 32>(h);
+        case 11: return march_v<4, 32>(h);
+        case 12: return march_v<8, 32>(h);
         default: break;
       }
     }
@@ -164,9 +188,10 @@ struct Engine {
     const Geo& G = h->dv.geo;
     const dim3 t = h->tile;
     const dim3 gr = grid_of(G, t);
-    hipLaunchKernelGGL((k_reduce_partial<L, C>), gr, t, 0, h->stream, h->nodes,
+    hipLaunchKernelGGL((k_reduce_partial<L, S>), gr, t, 0, h->stream, h->nodes, h->g[h->cur],
                        static_cast<const C*>(h->phi), static_cast<const C*>(h->s),
-                       static_cast<C*>(h->snap), h->partial, G, h->dv.wall, update_snap);
+                       static_cast<C*>(h->snap), h->partial, G, h->dv.phys.scale_g, h->dv.wall,
+                       update_snap);
     PFLBM_HIP(hipGetLastError());
     const long long nparts = (long long)gr.x * gr.y * gr.z;
     hipLaunchKernelGGL(k_reduce_final<kRecN>, dim3(1), dim3(256), 0, h->stream, h->partial, nparts,
@@ -238,6 +263,29 @@ struct GroupEngine {
     return set_error(PFLBM_EINVAL, "z-marching variants are for D3Q19");
   }
   template <int TY, int TZ>
+  static int launch_march(const GroupLaunch& gl, int parity) {
+    if constexpr (L::D == 3) {
+      if (gl.persist)
+        hipLaunchKernelGGL((k_stepZ_group<L, S, TY, TZ, true>), dim3(gl.grid), dim3(64, TY), 0,
+                           gl.stream, gl.table, gl.ntiles, gl.cases, parity);
+      else
+        hipLaunchKernelGGL((k_stepZ_group<L, S, TY, TZ, false>), dim3(gl.grid), dim3(64, TY), 0,
+                           gl.stream, gl.table, gl.ntiles, gl.cases, parity);
+      PFLBM_HIP(hipGetLastError());
+      return PFLBM_OK;
+    }
+    return set_error(PFLBM_EINVAL, "z-marching variants are for 3D lattices");
+  }
+  template <int TY, int TZ>
+  static int occupancy_march(int* blocks) {
+    if constexpr (L::D == 3) {
+      PFLBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          blocks, reinterpret_cast<const void*>(&k_stepZ_group<L, S, TY, TZ, true>), 64 * TY, 0));
+      return PFLBM_OK;
+    }
+    return set_error(PFLBM_EINVAL, "z-marching variants are for 3D lattices");
+  }
+  template <int TY, int TZ>
   static int occupancy_column(int* blocks) {
     if constexpr (L::D == 3) {
       PFLBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -259,6 +307,8 @@ struct GroupEngine {
   case V: return occ ? occupancy_split<BY, BZ>(occ) : launch_split<BY, BZ>(gl, parity);
 #define PFLBM_COLUMN(V, TY, TZ) \
   case V: return occ ? occupancy_column<TY, TZ>(occ) : launch_column<TY, TZ>(gl, parity);
+#define PFLBM_MARCH(V, TY, TZ) \
+  case V: return occ ? occupancy_march<TY, TZ>(occ) : launch_march<TY, TZ>(gl, parity);
 #define PFLBM_VARIANT(V, BY, BZ, KY, KZ) \
   case V: return occ ? occupancy<BY, BZ, KY, KZ>(occ) : launch<BY, BZ, KY, KZ>(gl, parity);
     if (L::D == 2) {
@@ -286,12 +336,15 @@ struct GroupEngine {
         PFLBM_COLUMN(8, 4, 16)
         PFLBM_COLUMN(9, 8, 16)
         PFLBM_COLUMN(10, 8, 32)
+        PFLBM_MARCH(11, 4, 32)
+        PFLBM_MARCH(12, 8, 32)
         default: break;
       }
     }
 #undef PFLBM_VARIANT
 #undef PFLBM_SPLIT
 #undef PFLBM_COLUMN
+#undef PFLBM_MARCH
     return set_error(PFLBM_EINVAL, "unknown step variant %d", gl.variant);
   }
 };
@@ -299,12 +352,11 @@ struct GroupEngine {
 template <class L, int S>
 int group_diag_t(const GroupLaunch& gl, int parity, int tx, int ty, int tz, double* partial,
                  double* out, int ncases, int update_snap) {
-  using C = ComputeT<S>;
   hipLaunchKernelGGL((k_phi_group_all<L, S>), dim3(gl.grid), dim3(256), 0, gl.stream, gl.table,
                      gl.ntiles, gl.cases, parity, tx, ty, tz);
   PFLBM_HIP(hipGetLastError());
-  hipLaunchKernelGGL((k_reduce_group<L, C>), dim3(gl.grid), dim3(256), 0, gl.stream, gl.table,
-                     gl.ntiles, gl.cases, partial, tx, ty, tz, update_snap);
+  hipLaunchKernelGGL((k_reduce_group<L, S>), dim3(gl.grid), dim3(256), 0, gl.stream, gl.table,
+                     gl.ntiles, gl.cases, parity, partial, tx, ty, tz, update_snap);
   PFLBM_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_reduce_final_group<kRecN>, dim3(ncases), dim3(256), 0, gl.stream, partial,
                      gl.cases, out);

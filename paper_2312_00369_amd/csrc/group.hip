@@ -213,8 +213,9 @@ int launch_eager(pflbm_group_s* g) {
 }  // namespace
 
 namespace pflbm {
-// A member's step count was set from outside (checkpoint restore): re-base its
-// entry so that the group's bookkeeping reproduces it.
+// A member's state was set from outside (checkpoint restore): re-base its
+// entry so that the group's bookkeeping reproduces its step count, and rebuild
+// the member descriptors before the next launch (they carry its FP16 scales).
 void group_member_changed(pflbm_case_s* h) {
   pflbm_group_s* g = h->group;
   if (!g) return;
@@ -223,6 +224,7 @@ void group_member_changed(pflbm_case_s* h) {
       g->step0[k] = h->step - g->since_build;
       g->cur0[k] = h->cur ^ (int)(g->since_build & 1);
     }
+  g->dirty = true;
 }
 }  // namespace pflbm
 

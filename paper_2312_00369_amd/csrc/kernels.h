@@ -49,7 +49,7 @@ struct Phys {
   double Fb[3];
   int visc_var;
   float scale_f, scale_g;  // FP16 codec: stored = value * scale (power of two)
-  int xcd_order;           // fused step: hand each XCD a contiguous run of tiles
+  int xcd_order;           // step kernels: dispatch order over the XCDs (TileOrder mode)
   int nt_store;            // fused step: non-temporal stores of f*, g*
 };
 
@@ -134,6 +134,12 @@ struct Set {
                                 kRestBytes) +
            (i - 1) * kBlk + n % kBlk;
   }
+  // v as the next step will read it back after a store (FP16: rounded to the
+  // stored half and decoded; otherwise v itself)
+  __device__ static C as_stored(C v, float scale) {
+    if constexpr (kHalf) return decode(__float2half_rn(v * scale), scale);
+    else return C(M(v));
+  }
   __device__ static C decode(M v, float scale) {
     if constexpr (kHalf) return __half2float(v) * (1.0f / scale);
     else return C(v);
@@ -195,6 +201,21 @@ __device__ inline bool node_coords(const Geo& G, int& x, int& y, int& z) {
   z = blockIdx.z * blockDim.z + threadIdx.z;
   return x < G.PX && y < G.PY && z < G.PZ;
 }
+
+// Inside a loop the compiler hoists every value derived from loop-invariant
+// inputs (conversions of the physics constants, products of them with the
+// lattice weights, neighbour coordinates) and keeps it in a vector register for
+// the whole loop.  Passing these inputs through an empty asm statement at the
+// top of each iteration makes them opaque, so derived values are formed next to
+// their use, as in straight-line code.
+__device__ inline void opaque(Phys& P) {
+  asm volatile("" : "+s"(P.tau), "+s"(P.inv_tau_g), "+s"(P.alpha), "+s"(P.beta), "+s"(P.kappa),
+               "+s"(P.wet));
+  asm volatile("" : "+s"(P.rho_l), "+s"(P.rho_g), "+s"(P.nu_l), "+s"(P.nu_g), "+s"(P.chi_a));
+  asm volatile("" : "+s"(P.Fb[0]), "+s"(P.Fb[1]), "+s"(P.Fb[2]), "+s"(P.scale_f),
+               "+s"(P.scale_g));
+}
+__device__ inline void opaque(int& a, int& b) { asm volatile("" : "+v"(a), "+v"(b)); }
 
 // ------------------------------------------------------------------ k_phi
 template <class L, int S, bool O = false>
@@ -427,12 +448,20 @@ struct Macro {
 // post-collision value is handed to the sinks as soon as it is formed:
 // put_g0(g*_0), put_g(i, g*_i) for i >= 1, put_f(i, f*_i); returns
 // s = u . grad phi (the next step's s_prev).
-template <class L, int S, class GetSp, class PutG0, class PutG, class PutF>
+//
+// The collision keeps sum_i g_i = phi and the sources sum to -(1.5 s - 0.5
+// s_prev), since sum_i w_i k_i = -1.  With FP32 or FP16 moving populations
+// (stored_g(v): v as it will be read back) the FP64 rest population is formed
+// from that balance, g*_0 = g_0 + sum_{i>0} (g_i - stored g*_i) - (1.5 s -
+// 0.5 s_prev), which equals Eq. (BGK) for i = 0 up to rounding and makes the
+// stored sum over a node change by exactly the source in FP64: the storage
+// rounding of the moving populations then never changes the phi mass.
+template <class L, int S, class GetSp, class PutG0, class PutG, class PutF, class StoredG>
 __device__ inline ComputeT<S> collide_post(const ComputeT<S>* f, double g0, const ComputeT<S>* g,
                                            ComputeT<S> ph, ComputeT<S> m, ComputeT<S> gx,
                                            ComputeT<S> gy, ComputeT<S> gz, bool wall,
                                            const Phys& P, GetSp&& get_sp, PutG0&& put_g0, PutG&& put_g,
-                                           PutF&& put_f) {
+                                           PutF&& put_f, StoredG&& stored_g) {
   using C = ComputeT<S>;
   constexpr int Q = L::Q;
   const C inv_cs2 = C(3);
@@ -443,20 +472,32 @@ __device__ inline ComputeT<S> collide_post(const ComputeT<S>* f, double g0, cons
   const C srcf = C(1.5) * M.s - C(0.5) * sp;
   const C itg = C(P.inv_tau_g);
   const C am = C(P.alpha) * m;
-  // g_0 - g_0^eq = g_0 - phi + (1 - w_0) alpha mu = (1 - w_0) alpha mu - sum_{i>0} g_i,
-  // formed from small terms only so that g_0 (about phi) is rounded once.
-  C gsmall = C(0);
+  if constexpr (S == kF64) {
+    // g_0 - g_0^eq = g_0 - phi + (1 - w_0) alpha mu = (1 - w_0) alpha mu - sum_{i>0} g_i,
+    // formed from small terms only so that g_0 (about phi) is rounded once.
+    C gsmall = C(0);
 #pragma unroll
-  for (int i = 1; i < LG::Q; ++i) gsmall += g[i];
-  {
-    const C d0 = (C(1) - w0) * am - gsmall;
-    const C inc = w0 * C(LG::k(0)) * srcf - d0 * itg;
-    put_g0(g0 + (double)inc);
-  }
+    for (int i = 1; i < LG::Q; ++i) gsmall += g[i];
+    {
+      const C d0 = (C(1) - w0) * am - gsmall;
+      const C inc = w0 * C(LG::k(0)) * srcf - d0 * itg;
+      put_g0(g0 + (double)inc);
+    }
 #pragma unroll
-  for (int i = 1; i < LG::Q; ++i) {
-    const C wi = C(LG::w(i));
-    put_g(i, g[i] - (g[i] - wi * am) * itg + wi * C(LG::k(i)) * srcf);
+    for (int i = 1; i < LG::Q; ++i) {
+      const C wi = C(LG::w(i));
+      put_g(i, g[i] - (g[i] - wi * am) * itg + wi * C(LG::k(i)) * srcf);
+    }
+  } else {
+    double dsum = 0.0;          // sum_{i>0} (g_i - stored g*_i), exact in FP64
+#pragma unroll
+    for (int i = 1; i < LG::Q; ++i) {
+      const C wi = C(LG::w(i));
+      const C v = g[i] - (g[i] - wi * am) * itg + wi * C(LG::k(i)) * srcf;
+      put_g(i, v);
+      dsum += (double)g[i] - (double)stored_g(v);
+    }
+    put_g0(g0 + dsum - (double)srcf);
   }
   // hydrodynamic collision
   C tau = C(P.tau);
@@ -515,7 +556,8 @@ __device__ inline void node_update(const ComputeT<S>* f, double g0, const Comput
       [&](int i, C v) {
         if (i == 0) FS::store_rest(fdst, n, typename FS::R(v), nt);
         else FS::store(fdst, i, n, v, P.scale_f, nt);
-      });
+      },
+      [&](C v) { return GS::as_stored(v, P.scale_g); });
   sprev[n] = s;
 }
 
@@ -570,6 +612,46 @@ struct StepTile {
   static constexpr int TX = 64, TY = BY * KY, TZ = D3 ? BZ * KZ : 1;
   static constexpr int LX = TX + 4, LY = TY + 4, LZ = D3 ? TZ + 4 : 1;
   static constexpr int NL = LX * LY * LZ;
+};
+
+// Dispatch order of a tile grid over the 8 XCDs.  The hardware deals the
+// workgroups of a launch to the XCDs round-robin (workgroup b to XCD b % 8),
+// and each XCD has its own L2.
+//   mode 0: workgroup b takes tile b (x fastest, then y, then z).
+//   mode 1: each XCD takes one contiguous run of tiles.
+//   mode 2: tiles are grouped in chunks of whole x-rows of tiles, kXcdRows rows
+//           in y at one z position, and the chunks are dealt to the XCDs
+//           round-robin: the tiles of a chunk (x- and y-neighbours) run on one
+//           XCD at the same time and share its L2 (halo rows, the cache lines
+//           that straddle two tiles in x), while every XCD still gets an even
+//           share of the domain.  The grid is padded to whole rounds of 8
+//           chunks; the extra workgroups get tile -1 and return at once.
+constexpr int kXcdRows = 2;
+struct TileOrder {
+  int nbx, nby, nbz, mode;
+  __host__ __device__ int ncy() const { return (nby + kXcdRows - 1) / kXcdRows; }
+  __host__ __device__ int chunk() const { return nbx * kXcdRows; }
+  __host__ __device__ unsigned grid() const {
+    const long long n = (long long)nbx * nby * nbz;
+    if (mode != 2) return (unsigned)n;
+    const long long nch = (long long)ncy() * nbz;
+    return (unsigned)(((nch + 7) / 8) * 8 * chunk());
+  }
+  __host__ __device__ int tile(int b) const {
+    if (mode == 1) {
+      const int n = nbx * nby * nbz;
+      const int per = n / 8, rem = n % 8, xcd = b % 8, k = b / 8;
+      return (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+    }
+    if (mode == 2) {
+      const int cs = chunk(), k = b / 8, c = (k / cs) * 8 + b % 8, p = k % cs;
+      if (c >= ncy() * nbz) return -1;
+      const int by = (c % ncy()) * kXcdRows + p / nbx;
+      if (by >= nby) return -1;
+      return p % nbx + nbx * (by + nby * (c / ncy()));
+    }
+    return b;
+  }
 };
 
 // Advance the tile with origin (x0, y0, z0) of one case by one step; sphi and
@@ -732,9 +814,8 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
 }
 
 
-// One launch per time step: workgroup b updates tile b (x-fastest order).
-// Workgroups are dealt to the 8 XCDs round-robin; with xcd_order each XCD
-// takes a contiguous run of tiles instead.
+// One launch per time step: one workgroup per tile, in the XCD order P.xcd_order
+// selects (TileOrder).
 template <class L, int S, int BY, int BZ, int KY, int KZ, bool O>
 __global__ __launch_bounds__(64 * BY * BZ) void k_step(
     const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
@@ -744,12 +825,8 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_step(
   __shared__ typename T::C sphi[T::NL];
   __shared__ uint32_t sw[T::NL];
   const int nbx = (G.PX + T::TX - 1) / T::TX, nby = (G.PY + T::TY - 1) / T::TY;
-  const int nb = gridDim.x;
-  int b = blockIdx.x;
-  if (P.xcd_order) {
-    const int per = nb / 8, rem = nb % 8, xcd = b % 8, k = b / 8;
-    b = (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
-  }
+  const int b = TileOrder{nbx, nby, (G.PZ + T::TZ - 1) / T::TZ, P.xcd_order}.tile(blockIdx.x);
+  if (b < 0) return;
   step_tile<L, S, BY, BZ, KY, KZ, O>((b % nbx) * T::TX, ((b / nbx) % nby) * T::TY,
                                   (b / (nbx * nby)) * T::TZ, nodes, fsrc, gsrc, fdst, gdst, sprev,
                                   G, P, sphi, sw);
@@ -856,7 +933,7 @@ __device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __rest
 }
 
 template <class L, int S, int BY, int BZ, bool O>
-__global__ __launch_bounds__(64 * BY * BZ) void k_stepB(
+__global__ __launch_bounds__(64 * BY * BZ, 7) void k_stepB(
     const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
     const void* __restrict__ gsrc, void* __restrict__ fdst, void* __restrict__ gdst,
     ComputeT<S>* __restrict__ sprev, const ComputeT<S>* __restrict__ phi, Geo G, Phys P) {
@@ -866,12 +943,8 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_stepB(
   __shared__ uint32_t sw[NL];
   const int TZ = D3 ? BZ : 1;
   const int nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY;
-  const int nb = gridDim.x;
-  int b = blockIdx.x;
-  if (P.xcd_order) {
-    const int per = nb / 8, rem = nb % 8, xcd = b % 8, k = b / 8;
-    b = (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
-  }
+  const int b = TileOrder{nbx, nby, (G.PZ + TZ - 1) / TZ, P.xcd_order}.tile(blockIdx.x);
+  if (b < 0) return;
   stepB_tile<L, S, BY, BZ, O>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ, nodes,
                            fsrc, gsrc, fdst, gdst, sprev, phi, G, P, sphi, sw);
 }
@@ -915,8 +988,9 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
                                   void* __restrict__ fdst, void* __restrict__ gdst,
                                   ComputeT<S>* __restrict__ sprev,
                                   const ComputeT<S>* __restrict__ phi, const Geo& G,
-                                  const Phys& P, ComputeT<S>* sphi, uint32_t* sw) {
+                                  const Phys& P0, ComputeT<S>* sphi, uint32_t* sw) {
   static_assert(L::D == 3, "z marching is for D3Q19");
+  Phys P = P0;        // made opaque once per plane (opaque())
   using C = ComputeT<S>;
   using GS = Set<S, true, L::G::Q, O>;
   using FS = Set<S, false, L::Q, O>;
@@ -924,7 +998,7 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
   constexpr int LX = 68, LY = TY + 4, PL = LX * LY;
   constexpr int NT = 64 * TY;
   const int lane = threadIdx.x, ty = threadIdx.y;
-  const int tid = lane + 64 * ty;
+  int tid = lane + 64 * ty;            // made opaque once per plane, with x and y
   const int P3[3] = {G.PX, G.PY, G.PZ};
   // ring slot of plane z (z >= z0 - 2)
   auto slot = [&](int z) { return (z - z0 + 2) % 5; };
@@ -997,11 +1071,16 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
   fill_ghosts(z0);
   __syncthreads();
   for (int z = z0; z < z0 + TZ; ++z) {
+    P = P0;
+    opaque(P);
+    tid = lane + 64 * ty;
+    asm volatile("" : "+v"(tid));
     load_plane(z + 2);
     __syncthreads();
     fill_ghosts(z + 1);
     __syncthreads();
-    const int x = x0 + lane, y = y0 + ty;
+    int x = x0 + lane, y = y0 + ty;
+    opaque(x, y);
     if (x < G.PX && y < G.PY && z < G.PZ) {
       const int t = (2 + lane) + LX * (2 + ty);
       const int s0 = slot(z) * PL, sm = slot(z - 1) * PL, sp = slot(z + 1) * PL;
@@ -1055,8 +1134,340 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
   }
 }
 
+// ------------------------------------------------------------------ fused z-marching step (3D)
+// One launch per step, g read once.  A workgroup of (64, TY) threads owns a
+// column of 64 x TY x TZ nodes and walks it along z; thread (lane, ty) owns
+// the nodes (x0 + lane, y0 + ty, z) of every plane.  LDS holds a ring of raw /
+// ghost-filled phi planes and a ring of node-word planes, each over the window
+// W2 = 68 x (TY + 4) (the tile and two halo layers in x and y).  Iteration j
+// collides plane j:
+//   S1  node words of plane j + 3 into the word ring (and whether a ghost lies
+//       in the window W1 = tile + one halo layer of that plane);
+//   S2  raw phi of plane j + 1 over W1 (over W2 when a ghost is in W1 of plane
+//       j, j + 1 or j + 2): the owned node pulls its g and keeps it for the
+//       collision of the next iteration; halo nodes pull g and keep only phi;
+//   S3  raw phi of plane j + 2 at the fluid / boundary nodes the ghosts of plane
+//       j + 1 read (their 3 x 3 x 3 blocks reach plane j + 2);
+//   S4  ghost means of plane j + 1 over W1;
+//   S5  collision of plane j: f pulled, g kept from the previous iteration, mu
+//       and grad phi from the phi planes j - 1, j, j + 1.
+// The arithmetic per node is that of k_phi + k_mu + k_collide, in the same
+// order, so all step kernels give bit-identical results.
+template <int TY>
+struct MarchTile {
+  static constexpr int LX = 68, LY = TY + 4, PL = LX * LY;
+  static constexpr int NPHI = 5, NWORD = 6;        // ring slots
+  static constexpr int NL_PHI = NPHI * PL, NL_WORD = NWORD * PL;
+};
+
+template <class L, int S, int TY, int TZ, bool O = false>
+__device__ inline void stepZ_tile(int x0, int y0, int z0, const uint32_t* __restrict__ nodes,
+                                  const void* __restrict__ fsrc, const void* __restrict__ gsrc,
+                                  void* __restrict__ fdst, void* __restrict__ gdst,
+                                  ComputeT<S>* __restrict__ sprev, const Geo& G, const Phys& P0,
+                                  ComputeT<S>* sphi, uint32_t* sw) {
+  static_assert(L::D == 3, "z marching is for 3D lattices");
+  // physics constants and owned coordinates, made opaque once per plane (opaque())
+  Phys P = P0;
+  int xo = x0 + threadIdx.x, yo = y0 + threadIdx.y;
+  using C = ComputeT<S>;
+  using GS = Set<S, true, L::G::Q, O>;
+  using FS = Set<S, false, L::Q, O>;
+  constexpr int Q = L::Q, QG = L::G::Q;
+  constexpr int LX = 68, LY = TY + 4, PL = LX * LY, NT = 64 * TY;
+  const int lane = threadIdx.x, ty = threadIdx.y;
+  const int tid = lane + 64 * ty;
+  const int z1 = (z0 + TZ < G.PZ) ? z0 + TZ : G.PZ;     // last plane + 1 of the column
+  // ring slots (planes below z0 - 2 are never held)
+  auto pslot = [&](int z) { return ((z - z0 + 10) % 5) * PL; };
+  auto wslot = [&](int z) { return ((z - z0 + 12) % 6) * PL; };
+  // plane z in the padded grid (periodic wrap), or -1 outside a closed axis
+  auto zof = [&](int z) -> int {
+    if (G.per[2]) {
+      z %= G.PZ;
+      return z < 0 ? z + G.PZ : z;
+    }
+    return (z >= 0 && z < G.PZ) ? z : -1;
+  };
+  // padded coordinates of window entry m (wrapping periodic axes); false outside
+  auto exy = [&](int m, int& qx, int& qy) -> bool {
+    qx = x0 - 2 + m % LX;
+    qy = y0 - 2 + m / LX;
+    if (G.per[0]) {
+      qx %= G.PX;
+      if (qx < 0) qx += G.PX;
+    } else if (qx < 0 || qx >= G.PX) {
+      return false;
+    }
+    if (G.per[1]) {
+      qy %= G.PY;
+      if (qy < 0) qy += G.PY;
+    } else if (qy < 0 || qy >= G.PY) {
+      return false;
+    }
+    return true;
+  };
+  // raw phi of window entry m of plane qz (same arithmetic as k_phi); the word
+  // of an entry outside the grid is 0
+  auto raw_entry = [&](const uint32_t* wp, int m, int qz) -> C {
+    const uint32_t w = wp[m];
+    if (!(w & kZeta)) return C(0);
+    int qx, qy;
+    exy(m, qx, qy);
+    const nidx n = G.idx(qx, qy, qz);
+    nidx nb[Q];
+    neighbours<L>(G, qx, qy, qz, nb);
+    C small = C(0);
+#pragma unroll
+    for (int i = 1; i < QG; ++i) small += pull<typename L::G, GS>(gsrc, i, n, nb, w, P.scale_g);
+    return C(GS::load_rest(gsrc, n) + (double)small);
+  };
+  // S1: node words of plane z over W2; returns whether this thread saw a ghost in W1
+  auto load_words = [&](int z) -> bool {
+    uint32_t* wp = sw + wslot(z);
+    const int qz = zof(z);
+    bool ghost = false;
+    for (int m = tid; m < PL; m += NT) {
+      int qx, qy;
+      uint32_t w = 0;
+      if (qz >= 0 && exy(m, qx, qy)) w = nodes[G.idx(qx, qy, qz)];
+      wp[m] = w;
+      const int lx = m % LX, ly = m / LX;
+      if (lx >= 1 && lx < LX - 1 && ly >= 1 && ly < LY - 1) ghost |= (w & kGhost) != 0;
+    }
+    return ghost;
+  };
+  // the tile node (x0 + lane, y0 + ty) is owned (its pulls are kept) when it lies
+  // in the padded grid; other tile entries wrap (periodic) or are outside
+  const bool own_xy = (xo < G.PX) && (yo < G.PY);
+  const int tt = (2 + lane) + LX * (2 + ty);            // window entry of the owned node
+  // S2: raw phi of plane z over W1 (and the outer ring when ring2); the owned
+  // node's pulled g go to (g0k, gk)
+  auto raw_plane = [&](int z, bool ring2, double& g0k, C* gk) {
+    C* fp = sphi + pslot(z);
+    const uint32_t* wp = sw + wslot(z);
+    const int qz = zof(z);
+    {
+      const uint32_t w = wp[tt];
+      C ph = C(0);
+      g0k = 0.0;
+      if (own_xy && qz >= 0 && (w & kZeta)) {
+        const nidx n = G.idx(xo, yo, qz);
+        nidx nb[Q];
+        neighbours<L>(G, xo, yo, qz, nb);
+        C small = C(0);
+#pragma unroll
+        for (int i = 1; i < QG; ++i) {
+          gk[i] = pull<typename L::G, GS>(gsrc, i, n, nb, w, P.scale_g);
+          small += gk[i];
+        }
+        g0k = GS::load_rest(gsrc, n);
+        ph = C(g0k + (double)small);
+      } else if (!own_xy && qz >= 0) {
+        ph = raw_entry(wp, tt, qz);
+      }
+      fp[tt] = ph;
+    }
+    // first halo layer: rows 1 and TY + 2 (x 1..66), then x = 1 and 66 of rows 2..TY + 1
+    constexpr int NR1 = 2 * 66 + 2 * TY;
+    for (int r = tid; r < NR1; r += NT) {
+      int lx, ly;
+      if (r < 132) {
+        ly = r < 66 ? 1 : TY + 2;
+        lx = 1 + r % 66;
+      } else {
+        const int k = r - 132;
+        ly = 2 + (k >> 1);
+        lx = (k & 1) ? 66 : 1;
+      }
+      const int m = lx + LX * ly;
+      fp[m] = qz >= 0 ? raw_entry(wp, m, qz) : C(0);
+    }
+    if (ring2) {
+      // outer layer: rows 0 and LY - 1, then x = 0 and 67 of rows 1..LY - 2
+      constexpr int NR2 = 2 * LX + 2 * (LY - 2);
+      for (int r = tid; r < NR2; r += NT) {
+        int lx, ly;
+        if (r < 2 * LX) {
+          ly = r < LX ? 0 : LY - 1;
+          lx = r % LX;
+        } else {
+          const int k = r - 2 * LX;
+          ly = 1 + (k >> 1);
+          lx = (k & 1) ? LX - 1 : 0;
+        }
+        const int m = lx + LX * ly;
+        fp[m] = qz >= 0 ? raw_entry(wp, m, qz) : C(0);
+      }
+    }
+  };
+  // S3: raw phi of plane z at the zeta = 1 entries next to (in x, y) a ghost of
+  // the adjacent plane zg inside W1 (the entries that ghost's mean reads)
+  auto raw_support = [&](int z, int zg) {
+    C* fp = sphi + pslot(z);
+    const uint32_t* wp = sw + wslot(z);
+    const uint32_t* wq = sw + wslot(zg);
+    const int qz = zof(z);
+    if (qz < 0) return;
+    for (int m = tid; m < PL; m += NT) {
+      if (!(wp[m] & kZeta)) continue;
+      const int lx = m % LX, ly = m / LX;
+      bool near = false;
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int ax = lx + dx, ay = ly + dy;
+          if (ax >= 1 && ax < LX - 1 && ay >= 1 && ay < LY - 1)
+            near |= (wq[ax + LX * ay] & kGhost) != 0;
+        }
+      if (near) fp[m] = raw_entry(wp, m, qz);
+    }
+  };
+  // S4: ghost means of plane z over W1 (same order as ghost_mean)
+  auto fill_ghosts = [&](int z) {
+    const int sm = pslot(z - 1), s0 = pslot(z), sp = pslot(z + 1);
+    const int wm = wslot(z - 1), w0 = wslot(z), wpl = wslot(z + 1);
+    for (int m = tid; m < 66 * (TY + 2); m += NT) {
+      const int t = (1 + m % 66) + LX * (1 + m / 66);
+      if (!(sw[w0 + t] & kGhost)) continue;
+      const int pb[3] = {sm, s0, sp}, wb[3] = {wm, w0, wpl};
+      C num = C(0);
+      int den = 0;
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int t2 = t + dx + LX * dy;
+            if (sw[wb[dz] + t2] & kZeta) {
+              num += sphi[pb[dz] + t2];
+              ++den;
+            }
+          }
+      if (den > 0) sphi[s0 + t] = ghost_value(num / C(den), C(P.chi_a));
+    }
+  };
+
+  // prologue: words of planes z0 - 2 .. z0 + 2, with the ghost flags of z0 - 1 .. z0 + 2
+  bool gm1, g0f, g1f, g2f;
+  {
+    (void)load_words(z0 - 2);
+    const bool a = load_words(z0 - 1), b = load_words(z0), c = load_words(z0 + 1),
+               d = load_words(z0 + 2);
+    gm1 = __syncthreads_or(a);
+    g0f = __syncthreads_or(b);
+    g1f = __syncthreads_or(c);
+    g2f = __syncthreads_or(d);
+  }
+  // raw phi: plane z0 - 2 where the ghosts of z0 - 1 read it, z0 - 1 over W2,
+  // z0 over W1 (W2 near ghosts) with the owned pulls kept, and z0 + 1 where the
+  // ghosts of z0 read it
+  double g0c = 0.0, g0n = 0.0;
+  C gc[QG], gn[QG];
+#pragma unroll
+  for (int i = 0; i < QG; ++i) gc[i] = gn[i] = C(0);
+  if (gm1) raw_support(z0 - 2, z0 - 1);
+  {
+    C* fp = sphi + pslot(z0 - 1);
+    const uint32_t* wp = sw + wslot(z0 - 1);
+    const int qz = zof(z0 - 1);
+    for (int m = tid; m < PL; m += NT) fp[m] = qz >= 0 ? raw_entry(wp, m, qz) : C(0);
+  }
+  raw_plane(z0, gm1 || g0f || g1f, g0c, gc);
+  if (g0f) raw_support(z0 + 1, z0);
+  __syncthreads();
+  if (gm1) fill_ghosts(z0 - 1);
+  if (g0f) fill_ghosts(z0);
+  __syncthreads();
+
+  for (int j = z0; j < z1; ++j) {
+    P = P0;
+    opaque(P);
+    xo = x0 + lane;
+    yo = y0 + ty;
+    opaque(xo, yo);
+    // S1
+    const bool g3 = load_words(j + 3);
+    // S2, S3
+    raw_plane(j + 1, g0f || g1f || g2f, g0n, gn);
+    if (g1f) raw_support(j + 2, j + 1);
+    const bool g3f = __syncthreads_or(g3);
+    // S4
+    if (g1f) fill_ghosts(j + 1);
+    __syncthreads();
+    // S5
+    const int qz = zof(j);
+    const uint32_t w = sw[wslot(j) + tt];
+    if (own_xy && (w & kZeta)) {
+      const nidx n = G.idx(xo, yo, qz);
+      nidx nb[Q];
+      neighbours<L>(G, xo, yo, qz, nb);
+      C f[Q];
+      f[0] = C(FS::load_rest(fsrc, n));
+#pragma unroll
+      for (int i = 1; i < Q; ++i) f[i] = pull<L, FS>(fsrc, i, n, nb, w, P.scale_f);
+      const int sm = pslot(j - 1), s0 = pslot(j), sp = pslot(j + 1);
+      const int wm = wslot(j - 1), w0 = wslot(j), wpl = wslot(j + 1);
+      auto pat = [&](int i) {
+        return (L::cz(i) < 0 ? sm : (L::cz(i) > 0 ? sp : s0)) + tt + L::cx(i) + LX * L::cy(i);
+      };
+      auto wat = [&](int i) {
+        return (L::cz(i) < 0 ? wm : (L::cz(i) > 0 ? wpl : w0)) + tt + L::cx(i) + LX * L::cy(i);
+      };
+      // mu (same arithmetic as mu_at) and grad phi
+      const C ph = sphi[s0 + tt];
+      C lap = C(0), ex = C(0), ey = C(0), ez = C(0);
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const C wi = C(L::w(i));
+        lap += C(2) * wi * (sphi[pat(i)] - ph);
+        const C e = (sw[wat(i)] & kFluid) ? C(1) : C(0);
+        ex += wi * C(L::cx(i)) * e;
+        ey += wi * C(L::cy(i)) * e;
+        ez += wi * C(L::cz(i)) * e;
+      }
+      const C inv_cs2 = C(3);
+      lap *= inv_cs2;
+      ex *= inv_cs2;
+      ey *= inv_cs2;
+      ez *= inv_cs2;
+      const C av = sqrt(ex * ex + ey * ey + ez * ez);
+      const C m = C(4) * C(P.beta) * ph * (ph - C(1)) * (ph - C(0.5)) - C(P.kappa) * lap -
+                  av * wet_of<L::D, C>(w, P) * (ph - ph * ph);
+      C gx, gy, gz;
+      grad_of<L, C>([&](int i) { return sphi[pat(i)]; }, gx, gy, gz);
+      node_update<L, S, 0, O>(f, g0c, gc, ph, m, gx, gy, gz, w, n, fdst, gdst, sprev, nullptr,
+                              nullptr, G, P, P.nt_store);
+    }
+    // the next plane's pulls become the current ones
+    g0c = g0n;
+#pragma unroll
+    for (int i = 0; i < QG; ++i) gc[i] = gn[i];
+    g0f = g1f;
+    g1f = g2f;
+    g2f = g3f;
+  }
+}
+
 template <class L, int S, int TY, int TZ, bool O>
-__global__ __launch_bounds__(64 * TY) void k_stepC(
+__global__ __launch_bounds__(64 * TY, 4) void k_stepZ(
+    const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
+    const void* __restrict__ gsrc, void* __restrict__ fdst, void* __restrict__ gdst,
+    ComputeT<S>* __restrict__ sprev, Geo G, Phys P) {
+  using T = MarchTile<TY>;
+  __shared__ ComputeT<S> sphi[T::NL_PHI];
+  __shared__ uint32_t sw[T::NL_WORD];
+  const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY;
+  const int b = TileOrder{nbx, nby, (G.PZ + TZ - 1) / TZ, P.xcd_order}.tile(blockIdx.x);
+  if (b < 0) return;
+  stepZ_tile<L, S, TY, TZ, O>((b % nbx) * 64, ((b / nbx) % nby) * TY, (b / (nbx * nby)) * TZ,
+                              nodes, fsrc, gsrc, fdst, gdst, sprev, G, P, sphi, sw);
+}
+
+template <class L, int S, int TY, int TZ, bool O>
+__global__ __launch_bounds__(64 * TY, 5) void k_stepC(
     const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
     const void* __restrict__ gsrc, void* __restrict__ fdst, void* __restrict__ gdst,
     ComputeT<S>* __restrict__ sprev, const ComputeT<S>* __restrict__ phi, Geo G, Phys P) {
@@ -1064,7 +1475,8 @@ __global__ __launch_bounds__(64 * TY) void k_stepC(
   __shared__ ComputeT<S> sphi[T::NL];
   __shared__ uint32_t sw[T::NL];
   const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY;
-  const int b = blockIdx.x;
+  const int b = TileOrder{nbx, nby, (G.PZ + TZ - 1) / TZ, P.xcd_order}.tile(blockIdx.x);
+  if (b < 0) return;
   stepC_tile<L, S, TY, TZ, O>((b % nbx) * 64, ((b / nbx) % nby) * TY, (b / (nbx * nby)) * TZ, nodes,
                            fsrc, gsrc, fdst, gdst, sprev, phi, G, P, sphi, sw);
 }
@@ -1156,7 +1568,7 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_phi_group(
 }
 
 template <class L, int S, int BY, int BZ, bool PERSIST = false>
-__global__ __launch_bounds__(64 * BY * BZ) void k_stepB_group(
+__global__ __launch_bounds__(64 * BY * BZ, 7) void k_stepB_group(
     const TileEntry* __restrict__ table, const int* __restrict__ ntiles,
     const CaseDesc* __restrict__ cases, int parity) {
   constexpr bool D3 = (L::D == 3);
@@ -1180,7 +1592,7 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_stepB_group(
 }
 
 template <class L, int S, int TY, int TZ, bool PERSIST = false>
-__global__ __launch_bounds__(64 * TY) void k_stepC_group(
+__global__ __launch_bounds__(64 * TY, 5) void k_stepC_group(
     const TileEntry* __restrict__ table, const int* __restrict__ ntiles,
     const CaseDesc* __restrict__ cases, int parity) {
   using T = ColumnTile<L, S, TY, TZ>;
@@ -1197,6 +1609,28 @@ __global__ __launch_bounds__(64 * TY) void k_stepC_group(
                              cd.nodes, cd.f[c], cd.g[c], cd.f[1 - c], cd.g[1 - c],
                              static_cast<ComputeT<S>*>(cd.s),
                              static_cast<const ComputeT<S>*>(cd.phi), G, cd.P, sphi, sw);
+    __syncthreads();
+  });
+}
+
+// Batched fused z-marching step: one column segment per table entry.
+template <class L, int S, int TY, int TZ, bool PERSIST = false>
+__global__ __launch_bounds__(64 * TY, 4) void k_stepZ_group(
+    const TileEntry* __restrict__ table, const int* __restrict__ ntiles,
+    const CaseDesc* __restrict__ cases, int parity) {
+  using T = MarchTile<TY>;
+  __shared__ ComputeT<S> sphi[T::NL_PHI];
+  __shared__ uint32_t sw[T::NL_WORD];
+  for_entries<PERSIST>(*ntiles, [&](int e) {
+    const TileEntry te = table[e];
+    const CaseDesc& cd = cases[te.case_id];
+    const Geo G = cd.G;
+    const int c = cd.cur0 ^ parity;
+    const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY;
+    const int b = te.tile;
+    stepZ_tile<L, S, TY, TZ, true>((b % nbx) * 64, ((b / nbx) % nby) * TY, (b / (nbx * nby)) * TZ,
+                                   cd.nodes, cd.f[c], cd.g[c], cd.f[1 - c], cd.g[1 - c],
+                                   static_cast<ComputeT<S>*>(cd.s), G, cd.P, sphi, sw);
     __syncthreads();
   });
 }
@@ -1267,19 +1701,39 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
+// Mass of node n in FP64 from the stored populations: the FP64 rest population
+// of g plus the moving ones (pulled as for phi) summed in FP64.  With FP32 or
+// FP16 moving populations this is the exact mass of the stored state, which
+// the compute-type phi (rounded to FP32) is not.
+template <class L, int S>
+__device__ inline double node_mass(const void* __restrict__ gsrc, const Geo& G, int x, int y,
+                                   int z, nidx n, uint32_t w, float scale_g) {
+  using GS = Set<S, true, L::G::Q, false>;   // 64-bit offsets: any buffer size
+  nidx nb[L::Q];
+  neighbours<L>(G, x, y, z, nb);
+  double small = 0.0;
+#pragma unroll
+  for (int i = 1; i < L::G::Q; ++i)
+    small += (double)pull<typename L::G, GS>(gsrc, i, n, nb, w, scale_g);
+  return GS::load_rest(gsrc, n) + small;
+}
+
 // Contribution of node (x, y, z) to a diagnostics record.  Interface points lie
 // on edges (x, x + e_a) inside the domain between two zeta = 1 nodes where
-// exactly one phi is below 1/2 (no periodic seam).
-template <class L, class C>
+// exactly one phi is below 1/2 (no periodic seam).  The mass is taken from the
+// stored populations (node_mass).
+template <class L, int S>
 __device__ inline void node_contrib(double* acc, const uint32_t* __restrict__ nodes,
-                                    const C* __restrict__ phi, const C* __restrict__ s,
-                                    C* __restrict__ snap, int x, int y, int z, const Geo& G,
-                                    const Wall& W, int update_snap) {
+                                    const void* __restrict__ gsrc,
+                                    const ComputeT<S>* __restrict__ phi,
+                                    const ComputeT<S>* __restrict__ s,
+                                    ComputeT<S>* __restrict__ snap, int x, int y, int z,
+                                    const Geo& G, float scale_g, const Wall& W, int update_snap) {
   const nidx n = G.idx(x, y, z);
   const uint32_t w = nodes[n];
   if (!(w & kZeta)) return;
   const double ph = (double)phi[n];
-  acc[kRecMass] += ph;
+  acc[kRecMass] += node_mass<L, S>(gsrc, G, x, y, z, n, w, scale_g);
   acc[kRecS] += (double)s[n];
   const double sn = (double)snap[n];
   acc[kRecResid] = fmax(acc[kRecResid], fabs(ph - sn));
@@ -1297,7 +1751,7 @@ __device__ inline void node_contrib(double* acc, const uint32_t* __restrict__ no
     const double p2 = (double)phi[n2];
     if ((ph < 0.5) == (p2 < 0.5)) continue;
     const double t = (0.5 - ph) / (p2 - ph);
-    add_point<C>(acc, W, X + (a == 0 ? t : 0.0), Y + (a == 1 ? t : 0.0), Z + (a == 2 ? t : 0.0));
+    add_point<ComputeT<S>>(acc, W, X + (a == 0 ? t : 0.0), Y + (a == 1 ? t : 0.0), Z + (a == 2 ? t : 0.0));
   }
 }
 
@@ -1324,15 +1778,18 @@ __device__ inline void block_record(double* acc, double* out) {
 }
 
 // One partial record per workgroup (grid over the padded nodes).
-template <class L, class C>
-__global__ void k_reduce_partial(const uint32_t* __restrict__ nodes, const C* __restrict__ phi,
-                                 const C* __restrict__ s, C* __restrict__ snap,
-                                 double* __restrict__ partial, Geo G, Wall W, int update_snap) {
+template <class L, int S>
+__global__ void k_reduce_partial(const uint32_t* __restrict__ nodes, const void* __restrict__ gsrc,
+                                 const ComputeT<S>* __restrict__ phi,
+                                 const ComputeT<S>* __restrict__ s, ComputeT<S>* __restrict__ snap,
+                                 double* __restrict__ partial, Geo G, float scale_g, Wall W,
+                                 int update_snap) {
   double acc[kRecN];
 #pragma unroll
   for (int k = 0; k < kRecN; ++k) acc[k] = 0.0;
   int x, y, z;
-  if (node_coords(G, x, y, z)) node_contrib<L, C>(acc, nodes, phi, s, snap, x, y, z, G, W, update_snap);
+  if (node_coords(G, x, y, z))
+    node_contrib<L, S>(acc, nodes, gsrc, phi, s, snap, x, y, z, G, scale_g, W, update_snap);
   const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
   block_record(acc, partial + b * kRecN);
 }
@@ -1464,12 +1921,13 @@ __global__ __launch_bounds__(256) void k_phi_group_all(const TileEntry* __restri
   }
 }
 
-template <class L, class C>
+template <class L, int S>
 __global__ __launch_bounds__(256) void k_reduce_group(const TileEntry* __restrict__ table,
                                                        const int* __restrict__ ntiles,
                                                        const CaseDesc* __restrict__ cases,
-                                                       double* __restrict__ partial, int tx,
-                                                       int ty, int tz, int update_snap) {
+                                                       int parity, double* __restrict__ partial,
+                                                       int tx, int ty, int tz, int update_snap) {
+  using C = ComputeT<S>;
   const int n = *ntiles;
   const int tid = threadIdx.x;
   for (int e = blockIdx.x; e < n; e += gridDim.x) {
@@ -1485,9 +1943,9 @@ __global__ __launch_bounds__(256) void k_reduce_group(const TileEntry* __restric
     for (int m = tid; m < tx * ty * tz; m += 256) {
       const int x = x0 + m % tx, y = y0 + (m / tx) % ty, z = z0 + m / (tx * ty);
       if (x >= G.PX || y >= G.PY || z >= G.PZ) continue;
-      node_contrib<L, C>(acc, cd.nodes, static_cast<const C*>(cd.phi),
+      node_contrib<L, S>(acc, cd.nodes, cd.g[cd.cur0 ^ parity], static_cast<const C*>(cd.phi),
                          static_cast<const C*>(cd.s), static_cast<C*>(cd.snap), x, y, z, G,
-                         cd.W, update_snap);
+                         cd.P.scale_g, cd.W, update_snap);
     }
     block_record(acc, partial + (long long)e * kRecN);
   }

@@ -292,7 +292,7 @@ class Case:
                "pflbm_set_fp16_scales")
 
     def set_step_options(self, xcd_order=True, nontemporal=False):
-        _check(lib.pflbm_set_step_options(self.h, int(bool(xcd_order)), int(bool(nontemporal))),
+        _check(lib.pflbm_set_step_options(self.h, int(xcd_order), int(bool(nontemporal))),
                "pflbm_set_step_options")
 
     def set_step_kernel(self, variant):

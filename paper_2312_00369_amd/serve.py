@@ -4,10 +4,14 @@ Requests arrive over time (each carries its arrival time).  A request is
 admitted, first come first served, as soon as its HBM footprint fits the free
 budget and a slot is free; admitted cases join the running group of their
 lattice and storage at the next chunk boundary and advance together with the
-cases already resident.  After every chunk the groups are polled: cases that
-are steady (max |phi(t) - phi(t - chunk)| <= steady_tol), non-finite, or at
-their step cap (the request's "max_steps", else the server's) leave, their
-memory is freed and waiting requests are admitted.
+cases already resident.  Each group has its own stream (default priority):
+a chunk is launched on every group before any of them is polled, so groups of
+different lattices (2D and 3D) run on the device at the same time.  A chunk is
+at most `chunk_steps` steps and never takes a case past its step cap.  After
+every chunk the groups are polled: cases that are steady (max |phi(t) -
+phi(t - chunk)| <= steady_tol), non-finite, or at their step cap (the
+request's "max_steps", else the server's) leave, their memory is freed and
+waiting requests are admitted.
 
 The executor is an interface (`Executor`): `GpuExecutor` drives the HIP
 library; tests drive the same scheduler with a fake executor and clock.
@@ -36,7 +40,8 @@ class Executor:
         raise NotImplementedError
 
     def step(self, nsteps):
-        """Advance every admitted case nsteps."""
+        """Advance every admitted case nsteps (asynchronous on the device is
+        fine: poll() waits)."""
         raise NotImplementedError
 
     def poll(self):
@@ -49,16 +54,17 @@ class Executor:
 
 
 class GpuExecutor(Executor):
-    """Cases on the GPU, one group per (lattice, storage)."""
+    """Cases on the GPU, one group per (lattice, storage), each group on a
+    stream of its own (default priority) so that the groups overlap."""
 
-    def __init__(self, stream=None, keep_fields=False, variant_2d=-1, variant_3d=-1):
+    def __init__(self, keep_fields=False, variant_2d=-1, variant_3d=-1):
         from . import pflbm as P
         self.P = P
         self.groups = {}
+        self.streams = {}
         self.cases = {}
         self.keep_fields = keep_fields
         self.variants = {P.D2Q9: variant_2d, P.D3Q19: variant_3d, P.D3Q19_D3Q7: variant_3d}
-        self.stream = stream
         self._next = 0
 
     def now(self):
@@ -77,13 +83,15 @@ class GpuExecutor(Executor):
         return self.P.footprint(self.params(req))
 
     def admit(self, req):
+        import torch
         prm = self.params(req)
-        case = self.P.Case(prm, req["mask"], req["phi0"], stream=self.stream)
         gk = (prm.lattice, prm.storage)
         if gk not in self.groups:
-            g = self.P.Group(stream=self.stream)
+            self.streams[gk] = torch.cuda.Stream()          # default priority
+            g = self.P.Group(stream=self.streams[gk])
             g.set_tile(self.variants[prm.lattice], 0)
             self.groups[gk] = g
+        case = self.P.Case(prm, req["mask"], req["phi0"], stream=self.streams[gk])
         self.groups[gk].add(case)
         key = self._next
         self._next += 1
@@ -91,6 +99,7 @@ class GpuExecutor(Executor):
         return key
 
     def step(self, nsteps):
+        # every group's chunk is enqueued on its own stream before poll() waits
         for g in self.groups.values():
             if len(g.members):
                 g.step(nsteps)
@@ -146,6 +155,7 @@ class Server:
                                            key=lambda i: requests[i]["arrival_s"]))
         waiting = collections.deque()
         active = {}             # key -> request index
+        steps_done = {}         # key -> steps at the last poll
         used = 0
         fps = {}
         rec = [dict(index=i, arrival_s=requests[i]["arrival_s"],
@@ -182,7 +192,10 @@ class Server:
                     continue
                 break
             tb = clock()
-            ex.step(self.chunk)
+            # a chunk never takes a case past its step cap
+            left = min(int(requests[i].get("max_steps", self.max_steps)) - steps_done.get(k, 0)
+                       for k, i in active.items())
+            ex.step(max(1, min(self.chunk, left)))
             status = ex.poll()
             busy += clock() - tb
             done_t = clock()
@@ -190,6 +203,9 @@ class Server:
                 i = active.get(key)
                 if i is None:
                     continue
+                steps_done[key] = int(st["steps"])
+                if st.get("residual") is not None:
+                    rec[i].setdefault("residuals", []).append((int(st["steps"]), st["residual"]))
                 cap = int(requests[i].get("max_steps", self.max_steps))
                 finished = st["steady"] or st["nonfinite"] or st["steps"] >= cap
                 if not finished:

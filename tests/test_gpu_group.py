@@ -44,9 +44,9 @@ def test_group_alone_vs_mix_bitwise_2d(P, storage):
             assert np.array_equal(f[k], ref[k]), k
 
 
-@pytest.mark.parametrize("variant", [3, 5, 6])
+@pytest.mark.parametrize("variant", [3, 5, 6, 11, 12])
 def test_group_alone_vs_mix_bitwise_3d(P, variant):
-    """Fused (3) and split (5, 6) batched kernels."""
+    """Fused (3), split (5, 6) and fused z-marching (11, 12) batched kernels."""
     cs = [workloads.inclined_droplet_case_3d(n=n, radius=0.25 * n, theta=th, width=4.0)
           for n, th in ((18, 60.0), (26, 120.0), (22, 45.0))]
     g = P.Group()
@@ -60,9 +60,10 @@ def test_group_alone_vs_mix_bitwise_3d(P, variant):
         assert np.array_equal(m.fields()["phi"], ref["phi"])
 
 
-@pytest.mark.parametrize("variant", [3, 7, 8])
+@pytest.mark.parametrize("variant", [3, 7, 8, 12])
 def test_group_alone_vs_mix_bitwise_d3q7(P, variant):
-    """D3Q7 for g: batched fused (3), split (7) and z-marching (8) kernels."""
+    """D3Q7 for g: batched fused (3), split (7), z-marching split (8) and fused
+    z-marching (12) kernels."""
     cs = [workloads.inclined_droplet_case_3d(n=n, radius=0.25 * n, theta=th, width=4.0)
           for n, th in ((18, 60.0), (26, 120.0))]
     for c in cs:
@@ -218,7 +219,7 @@ def test_group_chi_cases_bitwise(P, variant):
 
 
 @pytest.mark.parametrize("lattice,variant", [("D2Q9", 1), ("D2Q9", 6), ("D3Q19", 3), ("D3Q19", 7),
-                                             ("D3Q19", 8)])
+                                             ("D3Q19", 8), ("D3Q19", 12)])
 def test_group_persistent_grid_equals_per_entry_grid(P, lattice, variant):
     """The persistent grid (a fixed grid striding over the table, blocks_per_cu
     > 0) and one workgroup per table entry (blocks_per_cu = 0) give the same

@@ -15,6 +15,8 @@ from tests.helpers import maxdiff, oracle_for, oracle_theta
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+# FP32 storage against the FP64 oracle: relative mass difference after 5000 steps
+FP32_MASS_TOL = 3e-9
 
 
 def _zeta(case):
@@ -95,6 +97,31 @@ def test_parity_fp32_flat_128x64_golden(P):
     assert abs(d["theta_deg"] - float(gold["theta"])) <= 0.5
     rel_mass = abs(d["mass"] - float(gold["mass"][-1])) / float(gold["mass"][-1])
     print(f"FP32 relative mass difference: {rel_mass:.3e}")
+    assert rel_mass <= FP32_MASS_TOL, rel_mass
+
+
+def test_theta_parity_fp64_on_a_moving_drop(P):
+    """Contact angle of the GPU diagnostics (moment reduction + host circle fit)
+    against the oracle's estimator on the oracle's fields, FP64, on a drop that
+    spreads from 90 deg towards the prescribed 60 deg: equal within 1e-6 deg
+    after the angle has moved by more than 5 deg (and at the start).""" 
+    import math
+    from oracle import diagnostics as odiag
+    W, sigma = 4.0, 1e-2
+    c = workloads.flat_droplet_case(96, 48, 15.0, 60.0, W, sigma)
+    g = P.Case.from_case(c, "f64", mobility=0.2)
+    o = oracle_for(c, mobility=0.2)
+    th0 = g.diagnostics()["theta_deg"]
+    o0 = odiag.contact_angle(o.fields()["phi"], o.domain(o.zeta), c["wall"], W)[0]
+    assert abs(th0 - o0) <= 1e-6, (th0, o0)
+    g.step(5000)
+    o.step(5000)
+    th = g.diagnostics()["theta_deg"]
+    ot = odiag.contact_angle(o.fields()["phi"], o.domain(o.zeta), c["wall"], W)[0]
+    print(f"theta: start {th0:.6f}, after 5000 steps GPU {th:.9f} oracle {ot:.9f}")
+    assert abs(th - th0) >= 5.0, (th0, th)
+    assert abs(th - ot) <= 1e-6, (th, ot)
+    assert math.isfinite(th)
 
 
 def test_parity_d3q19_fp64(P):
@@ -215,6 +242,42 @@ def test_checkpoint_resume_bitwise(P):
     assert np.array_equal(a.fields()["phi"], b.fields()["phi"])
 
 
+def test_checkpoint_keeps_fp16_scales(P):
+    """FP16-deviation checkpoints carry the scales the populations are stored
+    with: a blob taken after the scales moved resumes bit for bit in a fresh
+    case (initial scales), in the same case after a diagnostics call moved its
+    scales again, and in a group member."""
+    c = workloads.flat_droplet_case(96, 48, 14.0, 60.0, 4.0)
+    a = P.Case.from_case(c, "f16dev")
+    a.step(30)
+    sf, sg = a.fp16_scales()
+    a.set_fp16_scales(sf / 64, sg / 32)          # out of the band: the upkeep will move them
+    blob = a.get_state()
+    a.step(40)
+    ref = a.fields()["phi"]
+    b = P.Case.from_case(c, "f16dev")
+    b.set_state(blob)
+    assert b.fp16_scales() == (sf / 64, sg / 32)
+    b.step(40)
+    assert np.array_equal(b.fields()["phi"], ref)
+    a.diagnostics()                              # moves the scales back into the band
+    assert a.fp16_scales() != (sf / 64, sg / 32)
+    a.set_state(blob)
+    assert a.fp16_scales() == (sf / 64, sg / 32)
+    a.step(40)
+    assert np.array_equal(a.fields()["phi"], ref)
+    m = P.Case.from_case(c, "f16dev")
+    g = P.Group()
+    g.add(m)
+    g.step(6)
+    m.set_state(blob)
+    g.step(40)
+    assert m.steps == 70
+    assert np.array_equal(m.fields()["phi"], ref)
+    g.remove(m)
+    g.close()
+
+
 def test_workspace_create_matches(P):
     c = workloads.flat_droplet_case(96, 48, 14.0, 60.0, 4.0)
     a = P.Case.from_case(c, "f32")
@@ -268,6 +331,59 @@ def test_fused_step_equals_three_kernel_path_bitwise(P, lattice, storage):
         f = g.fields()
         for k in ("phi", "p", "u", "mu"):
             assert np.array_equal(f[k], fr[k]), (v, k)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
+def test_march_columns_bitwise(P, storage):
+    """The fused z-marching step (variants 11, 12: 64 x 4 or 64 x 8 columns of 32
+    planes) against the phi / mu / collide kernels, on domains taller than
+    one column segment: closed z with a staircase wall crossing segment
+    boundaries, periodic z, and periodic x with a ragged x edge."""
+    cases = []
+    c = workloads.inclined_droplet_case_3d(n=24, radius=6.0, theta=50.0, width=4.0)
+    # stretch the 24^3 case along z: 24 x 20 x 75, closed in x and z, periodic in y
+    nz = 75
+    mask = workloads.inclined_plane((24, 20, nz), (12.0, 30.0), 30.0)
+    phi0 = workloads.droplet((24, 20, nz), (12.0, 10.0, 30.0), 7.0, 4.0)
+    cases.append(dict(c, shape=(24, 20, nz), periodic=(False, True, False), mask=mask, phi0=phi0))
+    cases.append(dict(cases[0], periodic=(False, True, True)))
+    m2 = np.zeros((70, 11, 70), np.uint8)
+    m2[:3] = 1
+    cases.append(dict(c, shape=(70, 11, 70), periodic=(True, False, True), mask=m2,
+                      phi0=workloads.droplet((70, 11, 70), (35.0, 5.0, 8.0), 6.0, 4.0)))
+    for c in cases:
+        ref = P.Case.from_case(c, storage)
+        ref.set_step_kernel(-1)
+        ref.set_graph_chunk(0)
+        ref.step(12)
+        fr = ref.fields()
+        sr = ref.get_state()
+        for v in (11, 12):
+            g = P.Case.from_case(c, storage)
+            g.set_step_kernel(v)
+            g.set_graph_chunk(0)
+            g.step(12)
+            f = g.fields()
+            for k in ("phi", "p", "u", "mu"):
+                assert np.array_equal(f[k], fr[k]), (c["shape"], c["periodic"], v, k)
+            assert np.array_equal(g.get_state(), sr), (c["shape"], c["periodic"], v)
+
+
+@pytest.mark.parametrize("lattice,variants", [("D2Q9", (1, 6)), ("D3Q19", (7, 8, 12))])
+def test_xcd_orders_bitwise(P, lattice, variants):
+    """The three XCD dispatch orders (round-robin, contiguous runs, chunks of
+    tile rows; the chunked grid is padded with idle workgroups) only move work
+    between XCDs: the fields stay bit-identical."""
+    c = _geom(lattice)
+    for v in variants:
+        out = []
+        for xo in (0, 1, 2):
+            g = P.Case.from_case(c, "f32")
+            g.set_step_kernel(v)
+            g.set_step_options(xo, False)
+            g.step(16)
+            out.append(g.get_state())
+        assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2]), v
 
 
 @pytest.mark.parametrize("variant", [1, 3, 6])

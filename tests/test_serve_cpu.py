@@ -127,3 +127,15 @@ def test_per_request_cap_and_time_to_result():
     assert summ["by_lattice"]["D2Q9"] == dict(requests=2, steady=1, capped=1, nonfinite=0)
     assert summ["by_lattice"]["D3Q19"] == dict(requests=1, steady=0, capped=1, nonfinite=0)
     assert summ["utilisation"] == pytest.approx(1.0)
+
+
+def test_chunks_never_pass_a_step_cap():
+    """A cap that is not a multiple of the chunk: the last chunk is shortened,
+    so the capped case stops exactly at its cap (the others advance with it)."""
+    reqs = [_req(0, 0.0, 1, 10 ** 9), _req(1, 0.0, 1, 10 ** 9)]
+    reqs[0]["max_steps"] = 2500
+    ex = FakeExecutor()
+    rec, _ = Server(ex, budget_bytes=10, max_slots=4, chunk_steps=1000,
+                    max_steps=4000).run(reqs)
+    assert rec[0]["status"] == "step cap" and rec[0]["steps"] == 2500
+    assert rec[1]["status"] == "step cap" and rec[1]["steps"] == 4000

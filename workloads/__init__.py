@@ -290,9 +290,33 @@ def table1_case(theta, nx=256, ny=128):
     return c
 
 
-def serving_request(rng, idx, nx_range=(256, 1024), n3_range=(64, 192)):
+def _cap_centre(wall, foot, radius, theta):
+    """Centre of a circle / sphere of `radius` that meets `wall` at the contact
+    angle theta (degrees), on the fluid side: for a plane, at signed height
+    -R cos(theta) along the normal from `foot`, a point of the plane
+    (cos theta = -h / R); for a circle or sphere of radius R_w, at distance
+    d = sqrt(R^2 + R_w^2 - 2 R R_w cos theta) from its centre, straight above it
+    (cos theta = (R^2 + R_w^2 - d^2) / (2 R R_w))."""
+    ct = math.cos(math.radians(theta))
+    if wall["kind"] == "plane":
+        n = wall["normal"]
+        return tuple(foot[k] - radius * ct * n[k] for k in range(len(foot)))
+    c, rw = wall["center"], wall["radius"]
+    d = math.sqrt(radius * radius + rw * rw - 2.0 * radius * rw * ct)
+    up = [0.0] * len(c)
+    up[-1] = 1.0
+    return tuple(c[k] + d * up[k] for k in range(len(c)))
+
+
+def serving_request(rng, idx, nx_range=(256, 1024), n3_range=(64, 192), start="drop"):
     """One request of the serving workload: 2D (256x128 .. 1024x512) or 3D
-    (64^3 .. 192^3), geometry flat / inclined / curved, theta ~ U[30, 150]."""
+    (64^3 .. 192^3), geometry flat / inclined / curved, theta ~ U[30, 150].
+
+    start="drop": a circle / sphere of R = 0.2 N centred on the wall (it meets
+    the wall at 90 degrees and must spread or retract to theta).  start="cap":
+    the same radius placed so that it already meets the wall at theta, the
+    equilibrium shape of the method up to the interface profile; the request
+    then asks for the steady state near that shape."""
     th = float(rng.uniform(30.0, 150.0))
     geom = ["flat", "inclined", "curved"][int(rng.integers(0, 3))]
     if rng.uniform() < 0.5:
@@ -333,18 +357,31 @@ def serving_request(rng, idx, nx_range=(256, 1024), n3_range=(64, 192)):
             phi0 = droplet(shape, (n / 2, n / 2, center[2] + rs - 1.0), R, 5.0)
             wall = dict(kind="circle", center=center, radius=rs - 1.0)
         c = _case("D3Q19", shape, (False, False, False), mask, phi0, th, 1e-3, 5.0, wall)
-    c.update(storage="f32", geometry=geom, name=f"req-{idx:03d}-{geom}-{c['lattice']}")
+    if start == "cap":
+        sh = c["shape"]
+        R = 0.2 * (sh[1] if c["lattice"] == "D2Q9" else sh[0])
+        w = c["wall"]
+        if w["kind"] == "plane":
+            # the drop's foot: the plane's point below the middle of the domain
+            mid = np.array([0.5 * v for v in sh], dtype=np.float64)
+            p0, nrm = np.asarray(w["point"], float), np.asarray(w["normal"], float)
+            foot = tuple(mid - ((mid - p0) @ nrm) * nrm)
+        else:
+            foot = None
+        c["phi0"] = np.ascontiguousarray(droplet(sh, _cap_centre(w, foot, R, th), R, 5.0))
+    c.update(storage="f32", geometry=geom, start=start, name=f"req-{idx:03d}-{geom}-{c['lattice']}")
     return c
 
 
-def serving_requests(seed=4, n_requests=200, rate=20.0, nx_range=(256, 1024), n3_range=(64, 192)):
+def serving_requests(seed=4, n_requests=200, rate=20.0, nx_range=(256, 1024), n3_range=(64, 192),
+                     start="drop"):
     """Poisson arrivals (mean `rate` per second) of mixed serving requests."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
     for k in range(n_requests):
         t += float(rng.exponential(1.0 / rate))
-        c = serving_request(rng, k, nx_range, n3_range)
+        c = serving_request(rng, k, nx_range, n3_range, start=start)
         c["arrival_s"] = t
         out.append(c)
     return out
