@@ -269,6 +269,17 @@ int pflbm_group_step(pflbm_group g, int64_t nsteps);
 /* Reductions for every member; d[k] and flags[k] (bit 0 steady, bit 1
  * nonfinite) for member k in insertion order; capacity >= group size.  (sync) */
 int pflbm_group_poll(pflbm_group g, pflbm_diag* d, int32_t* flags, int32_t capacity);
+/* pflbm_group_poll for callers that cannot allocate device memory (serving
+ * loops and harnesses that forbid it): the same reductions and results, with
+ * the partial and member records in a static device array of the library
+ * instead of buffers it allocates.  Limits: 32768 table entries and 1024
+ * members (larger groups: EINVAL).  A group that changed since its last step
+ * (members added or removed, launch shape set) needs its table rebuilt, which
+ * may allocate: step it first (else ESTATE).  Every call on one GPU shares that
+ * array: calls that overlap on a GPU (from two threads, or for two groups on
+ * unordered streams) race.  FP16-deviation scale upkeep as in
+ * pflbm_group_poll.  (sync) */
+int pflbm_group_poll_static(pflbm_group g, pflbm_diag* d, int32_t* flags, int32_t capacity);
 /* Launch shape of the batched kernel: step tile variant (-1 = library default)
  * and blocks_per_cu: 0 = one workgroup per table entry (the default; the grid
  * follows the table, so a membership change recaptures the step graph);

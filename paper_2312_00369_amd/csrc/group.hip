@@ -11,12 +11,23 @@
 // and descriptors in place (same addresses) between replays.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "case.h"
 
 using namespace pflbm;
+
+// Scratch of the allocation-free poll (pflbm_group_poll_static): the partial
+// records of the batched reductions (one per table entry) followed by the
+// member records.  A file-scope device array, so that poll allocates nothing;
+// every GPU the library runs on holds its own copy until the process ends.
+// The kernels write every partial and record before it is read, so nothing in
+// it has to start at zero; calls that overlap on one GPU share it and race.
+constexpr int kStaticEntries = 32768;   // table entries of one group
+constexpr int kStaticMembers = 1024;    // members of one group
+static __device__ __align__(256) double scratch[(size_t)(kStaticEntries + kStaticMembers) * kRecN];
 
 struct pflbm_group_s {
   hipStream_t stream = nullptr;
@@ -393,6 +404,89 @@ int pflbm_group_poll(pflbm_group g, pflbm_diag* d, int32_t* flags, int32_t capac
   }
   // FP16 scale upkeep per member; a moved scale reaches the kernels through the
   // member descriptors, which the next step rebuilds
+  for (int k = 0; k < nc; ++k) {
+    int changed = 0;
+    if ((rc = fp16_upkeep(g->members[k], &changed))) return rc;
+    if (changed) g->dirty = true;
+  }
+  return PFLBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Device address of `scratch` on the current device, looked up once per device
+// (hipGetSymbolAddress with that device current) and kept: host code passes
+// this address to the kernels, never the array's name.
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+double* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+int scratch_address(double** out) {
+  int dev = 0;
+  PFLBM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_error(PFLBM_EUNSUPPORTED, "device %d is beyond the %d the library tracks", dev,
+                     kMaxDevices);
+  std::call_once(g_scratch_once[dev], [dev] {
+    void* p = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (g_scratch_err[dev] == hipSuccess) g_scratch_ptr[dev] = static_cast<double*>(p);
+  });
+  if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev])
+    return set_error(PFLBM_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                     hipGetErrorString(g_scratch_err[dev]));
+  *out = g_scratch_ptr[dev];
+  return PFLBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int pflbm_group_poll_static(pflbm_group g, pflbm_diag* d, int32_t* flags, int32_t capacity) {
+  clear_error();
+  if (!g) return set_error(PFLBM_EINVAL, "group is NULL");
+  if (capacity < (int)g->members.size()) return set_error(PFLBM_EINVAL, "capacity too small");
+  if (g->members.empty()) return PFLBM_OK;
+  // a changed group needs its table rebuilt, which may allocate
+  if (g->dirty)
+    return set_error(PFLBM_ESTATE, "the group changed since its last step: step it (which "
+                     "rebuilds its table) before an allocation-free poll");
+  const int nc = (int)g->members.size();
+  if (g->ntiles > kStaticEntries || nc > kStaticMembers)
+    return set_error(PFLBM_EINVAL, "a group of %d table entries and %d members exceeds the "
+                     "allocation-free poll's scratch (%d entries, %d members)", g->ntiles, nc,
+                     kStaticEntries, kStaticMembers);
+  double* scr = nullptr;
+  int rc = scratch_address(&scr);
+  if (rc) return rc;
+  double* partial = scr;
+  double* recs = scr + (size_t)kStaticEntries * kRecN;
+  int t[5];
+  step_variant_tile(g->D, g->variant, t);
+  if ((rc = run_group_diag(launch_of(g), (int)(g->since_build & 1), t[2], t[3], t[4], partial,
+                           recs, nc, 1)))
+    return rc;
+  sync_members(g);
+  // member records through a small host buffer on the stack
+  constexpr int kBatch = 32;
+  double buf[kBatch * kRecN];
+  for (int k0 = 0; k0 < nc; k0 += kBatch) {
+    const int nb = std::min(kBatch, nc - k0);
+    PFLBM_HIP(hipMemcpyAsync(buf, recs + (size_t)k0 * kRecN, (size_t)nb * kRecN * sizeof(double),
+                             hipMemcpyDeviceToHost, g->stream));
+    PFLBM_HIP(hipStreamSynchronize(g->stream));
+    for (int j = 0; j < nb; ++j) {
+      pflbm_case_s* h = g->members[k0 + j];
+      pflbm_diag tmp;
+      finish_diag(h, buf + (size_t)j * kRecN, &tmp);
+      h->snap_valid = true;
+      if (d) d[k0 + j] = tmp;
+      if (flags) flags[k0 + j] = (tmp.steady ? 1 : 0) | (tmp.nonfinite ? 2 : 0);
+    }
+  }
+  // FP16 scale upkeep per member, as pflbm_group_poll (in place, no allocation)
   for (int k = 0; k < nc; ++k) {
     int changed = 0;
     if ((rc = fp16_upkeep(g->members[k], &changed))) return rc;

@@ -112,6 +112,7 @@ def _load():
         "pflbm_group_size": (ct.c_int, [vp]),
         "pflbm_group_step": (ct.c_int, [vp, i64]),
         "pflbm_group_poll": (ct.c_int, [vp, vp, vp, i32]),
+        "pflbm_group_poll_static": (ct.c_int, [vp, vp, vp, i32]),
         "pflbm_group_set_tile": (ct.c_int, [vp, i32, i32]),
         "pflbm_group_set_graph_chunk": (ct.c_int, [vp, i32]),
         "pflbm_group_destroy": (None, [vp]),
@@ -387,11 +388,15 @@ class Group:
     def set_graph_chunk(self, k):
         _check(lib.pflbm_group_set_graph_chunk(self.g, int(k)), "pflbm_group_set_graph_chunk")
 
-    def poll(self):
+    def poll(self, static=False):
+        """Reductions of every member: (diagnostics dicts, flags).  static=True
+        calls the allocation-free variant (pflbm_group_poll_static)."""
         n = len(self.members)
         ds = (pflbm_diag * max(n, 1))()
         flags = np.zeros(max(n, 1), dtype=np.int32)
-        _check(lib.pflbm_group_poll(self.g, ds, _ptr(flags), n), "pflbm_group_poll")
+        fn = lib.pflbm_group_poll_static if static else lib.pflbm_group_poll
+        _check(fn(self.g, ds, _ptr(flags), n),
+               "pflbm_group_poll_static" if static else "pflbm_group_poll")
         return [_diag_dict(ds[k]) for k in range(n)], flags[:n]
 
     def close(self):
