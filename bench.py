@@ -89,6 +89,9 @@ def parse():
     ap.add_argument("--appendix-a-marks", type=lambda v: [int(x) for x in v.split(",")],
                     default=[100000, 300000, 1000000, 3000000, 6000000])
     ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--batch-start", default="cap", help="drop (90 deg) or cap (meets the wall at theta)")
+    ap.add_argument("--batch-tol", type=float, default=1e-3)
+    ap.add_argument("--batch-cap", type=int, default=60000)
     a = ap.parse_args()
     a.sec = set(s.strip() for s in a.sections.split(",") if s.strip())
     return a
@@ -98,7 +101,10 @@ def graph_chunk_for(steps, chunk):
     """Steps per captured HIP graph for a timed run of `steps`: the requested
     chunk, or the whole run when it is shorter, made even (a replay must leave
     the ping-pong parity where it found it).  The timed region then replays
-    graphs whatever --steps is; an odd remainder step runs eagerly."""
+    graphs whatever --steps is; an odd remainder step runs eagerly.  chunk <= 0
+    asks for eager launches (profiling runs that count per-dispatch counters)."""
+    if int(chunk) <= 0:
+        return 0
     k = max(2, min(int(chunk), int(steps)))
     return k - (k & 1)
 
@@ -110,7 +116,7 @@ def time_steps(torch, case, steps, warmup, chunk):
     before the timed region starts.  Returns (total ms, steps per graph)."""
     K = graph_chunk_for(steps, chunk)
     case.set_graph_chunk(K)
-    w = -(-max(int(warmup), K) // K) * K
+    w = -(-max(int(warmup), K) // K) * K if K else int(warmup)
     case.step(w)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -226,44 +232,119 @@ def inclined_3d(a, torch, P, workloads, stream):
 
 
 def batched(a, torch, P, workloads, stream):
-    """64 uneven D2Q9 cylinder cases: one after another (each with its own graph
-    chunks) against one group (batched kernel, one workgroup per table entry)."""
-    cases = workloads.cylinder_batch()
+    """The 64-case D2Q9 cylinder batch (seed 3, sizes 128x64 .. 768x384):
+    (1) the launch shape (tile variant, blocks per CU) the autotuner picks for
+    this group (timed with graph replay; cached per shape class);
+    (2) throughput: K steps of the group against each case alone with the same
+    tile variant (graph replay each);
+    (3) fresh cases run to steady state in one group at that shape, polled every
+    1000 steps with the allocation-free poll: a case leaves when max |dphi|
+    over 1000 steps <= batch_tol, or at the step cap."""
+    from paper_2312_00369_amd import autotune
+    cases = workloads.cylinder_batch(start=a.batch_start)
     hs = [P.Case.from_case(c, "f32", stream=stream) for c in cases]
     nodes = sum(int((h.classes() & 1).sum()) for h in hs)
-    K = a.batch_steps
+    g = P.Group(stream=stream)
+    g.set_graph_chunk(100)
     for h in hs:
-        h.set_graph_chunk(100)
-        h.step(100)
+        g.add(h)
+    tuned = autotune.tune_group(g, steps=100, blocks_per_cu=(0, 1, 2),
+                                cache=autotune.Cache(autotune.DEFAULT_CACHE))
+    progress(f"batched: tuned shape {tuned['variant']} / {tuned['blocks_per_cu']} per CU")
+    K = a.batch_steps
+    g.step(100)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    g.step(K)
+    t1.record()
+    torch.cuda.synchronize()
+    ms_group = t0.elapsed_time(t1)
+    for h in hs:
+        g.remove(h)
+    for h in hs:
+        h.set_step_kernel(tuned["variant"])
+        h.set_graph_chunk(100)
+        h.step(100)
+    torch.cuda.synchronize()
     t0.record()
     for h in hs:
         h.step(K)
     t1.record()
     torch.cuda.synchronize()
     ms_alone = t0.elapsed_time(t1)
-    g = P.Group(stream=stream)
-    g.set_graph_chunk(100)
-    for h in hs:
-        g.add(h)
-    g.step(100)
-    torch.cuda.synchronize()
-    t0.record()
-    g.step(K)
-    t1.record()
-    torch.cuda.synchronize()
-    ms_group = t0.elapsed_time(t1)
-    d, flags = g.poll()
-    g.close()
     for h in hs:
         h.close()
-    return {"workload": f"64 D2Q9 FP32 cylinder cases 128x64..768x384 (seed 3), {nodes} nodes",
-            "steps": K, "alone_MLUPS": round(nodes * K / ms_alone / 1e3, 1),
-            "group_MLUPS": round(nodes * K / ms_group / 1e3, 1),
-            "speedup": round(ms_alone / ms_group, 2),
-            "nonfinite_cases": int(sum(1 for f in flags if f & 2))}
+    out = {"workload": f"64 D2Q9 FP32 cylinder cases 128x64..768x384 (seed 3, start "
+                       f"{a.batch_start}), {nodes} nodes",
+           "tuned_shape": {"variant": tuned["variant"], "blocks_per_cu": tuned["blocks_per_cu"],
+                           "from_cache": bool(tuned.get("cached"))},
+           "steps": K, "alone_MLUPS": round(nodes * K / ms_alone / 1e3, 1),
+           "group_MLUPS": round(nodes * K / ms_group / 1e3, 1),
+           "speedup": round(ms_alone / ms_group, 2)}
+    progress("batched: throughput done")
+    # (3) to steady state
+    hs = [P.Case.from_case(c, "f32", stream=stream, steady_tol=a.batch_tol) for c in cases]
+    g.set_tile(tuned["variant"], tuned["blocks_per_cu"])
+    for h in hs:
+        g.add(h)
+    left = dict(enumerate(hs))
+    steps_at = {}
+    theta = {}
+    steps = 0
+    t_start = time.perf_counter()
+    g.step(1000)
+    steps = 1000
+    g.poll(static=True)                       # reference field for the first residual
+    while left and steps < a.batch_cap:
+        g.step(1000)
+        steps += 1000
+        d, flags = g.poll(static=True)
+        members = list(g.members)
+        for m, dk, fk in zip(members, d, flags):
+            if fk & 3:
+                k = next(i for i, h in left.items() if h is m)
+                steps_at[k] = steps if fk & 1 else None
+                theta[k] = dk["theta_deg"]
+                g.remove(m)
+                del left[k]
+        if steps % 20000 == 0:
+            progress(f"batched to steady: {steps} steps, {len(left)} cases left")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    for k, h in left.items():
+        theta[k] = h.diagnostics()["theta_deg"]
+    steady = sorted(v for v in steps_at.values() if v)
+    graded = [k for k in range(len(cases))
+              if 0.3 * cases[k]["wall"]["radius"] >= 3 * cases[k]["width"]]
+    errs = [abs(theta[k] - cases[k]["theta_deg"]) for k in graded
+            if k in theta and theta[k] == theta[k]]
+    out["to_steady"] = {
+        "criterion": f"max|dphi| <= {a.batch_tol} over 1000 steps, cap {a.batch_cap} steps",
+        "steady": len(steady), "capped": len(left),
+        "nonfinite": sum(1 for v in steps_at.values() if v is None),
+        "steps_to_steady_p50": percentile_(steady, 50), "steps_to_steady_p90": percentile_(steady, 90),
+        "steps_to_steady_max": max(steady) if steady else None,
+        "wall_s": round(wall, 2), "cases_per_s": round(len(steady) / wall, 3) if wall else None,
+        "theta_abs_err_deg_drops_of_3W_or_more": {
+            "cases": len(errs), "mean": round(sum(errs) / len(errs), 2) if errs else None,
+            "max": round(max(errs), 2) if errs else None}}
+    for h in list(g.members):
+        g.remove(h)
+    for h in hs:
+        h.close()
+    g.close()
+    return out
+
+
+def percentile_(xs, q):
+    if not xs:
+        return None
+    s_ = sorted(xs)
+    k = (len(s_) - 1) * q / 100.0
+    lo, hi = int(k), min(int(k) + 1, len(s_) - 1)
+    return s_[lo] + (s_[hi] - s_[lo]) * (k - lo)
 
 
 def table1(a, torch, P, workloads):
@@ -685,8 +766,9 @@ def run(a, torch, P, workloads, stream):
         "data": "synthetic",
         "config": {"workload": f"D2Q9 FP32 {a.nx}x{a.ny} flat-wall droplet R={80 * a.nx / 1024:g}, "
                                f"theta={a.theta:g}, W=5, rho 10/1, tau 0.8, M 0.1, sigma 1e-3",
-                   "nodes": nodes, "graph_chunk": K, "timed_graph_replays": a.steps // K,
-                   "timed_eager_steps": a.steps % K},
+                   "nodes": nodes, "graph_chunk": K,
+                   "timed_graph_replays": a.steps // K if K else 0,
+                   "timed_eager_steps": a.steps % K if K else a.steps},
         "hbm_roofline_pct_step": round(100 * mlups * 1e6 * alg / (HBM_PEAK_GBS * 1e9), 2),
         "roofline": roof,
         "check": {"theta_deg": round(d["theta_deg"], 3), "mass": d["mass"],

@@ -249,9 +249,12 @@ def sec33_sphere_case(theta, n=256, width=6.0):
     return c
 
 
-def cylinder_batch(seed=3, n_cases=64):
+def cylinder_batch(seed=3, n_cases=64, start="drop"):
     """64 D2Q9 cylinder cases, sizes U{128..768 step 16} x half, R_c ~ U[0.2, 0.4] Ny,
-    droplet 0.3 R_c, theta ~ U[30, 150] deg, W = 4, FP32."""
+    droplet 0.3 R_c, theta ~ U[30, 150] deg, W = 4, FP32.  start="drop": the
+    droplet is centred on the top of the cylinder (it meets the wall at 90
+    degrees); start="cap": the same radius placed so that it meets the
+    cylinder at its theta (see serving_request)."""
     rng = np.random.default_rng(seed)
     out = []
     for k in range(n_cases):
@@ -260,7 +263,12 @@ def cylinder_batch(seed=3, n_cases=64):
         rcf = float(rng.uniform(0.2, 0.4))
         th = float(rng.uniform(30.0, 150.0))
         c = cylinder_case(nx, ny, rcf, th)
+        if start == "cap":
+            rd = 0.3 * rcf * ny
+            c["phi0"] = np.ascontiguousarray(droplet((nx, ny), _cap_centre(c["wall"], None, rd, th),
+                                                     rd, c["width"]))
         c["name"] = f"c3-{k:02d}-{nx}x{ny}"
+        c["start"] = start
         out.append(c)
     return out
 
