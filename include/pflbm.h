@@ -134,6 +134,13 @@ int pflbm_classify(const pflbm_params* prm, const uint8_t* solid_mask, uint8_t* 
  * negative error code.  (no device work) */
 int pflbm_lattice_table(int32_t lattice, int32_t* c, double* w, int32_t* opp, double* k);
 
+/* beta and kappa of the free energy (Eq. bulk_energy with the gradient term)
+ * for surface tension sigma and interface width W: the planar equilibrium
+ * profile (Eq. initialphi) has W = sqrt(8 kappa / beta) and the tension is
+ * sqrt(2 kappa beta) / 6, so beta = 12 sigma / W and kappa = 3 sigma W / 2.
+ * EINVAL unless sigma and width are finite and positive.  (no device work) */
+int pflbm_beta_kappa(double sigma, double width, double* beta, double* kappa);
+
 /* ---------------------------------------------------------------- single case */
 
 /* Device bytes a case with these parameters needs (sync-free, host only). */
@@ -170,14 +177,19 @@ int pflbm_set_tile(pflbm_handle h, int32_t tx, int32_t ty, int32_t tz);
  * of five tile shapes; 5-7: the split step (a phi pass, then one kernel for
  * ghosts, mu and collide-stream) with one of three tile shapes; 8-10 (D3Q19
  * only): the split step whose second kernel marches along z over 64 x ty x tz
- * columns; -1: the three-kernel path (phi sum, mu stencil, collide-stream).  Defaults: 1 for
- * D2Q9, 7 for D3Q19.  Every path gives bit-identical results.  Drops any
+ * columns; 11-12 (D3Q19 only): the fused one-kernel step marching along z
+ * (phi planes formed from g in a rolling LDS window, g read once per step);
+ * -1: the three-kernel path (phi sum, mu stencil, collide-stream).  Defaults:
+ * 1 for D2Q9, 7 for D3Q19.  Every path gives bit-identical results.  Drops any
  * captured graph. */
 int pflbm_set_step_kernel(pflbm_handle h, int32_t variant);
 
-/* Scheduling options of the fused step (results do not depend on them):
- * xcd_order != 0 hands each of the 8 XCDs a contiguous run of tiles;
- * nontemporal != 0 writes f* and g* with streaming stores (both default off).
+/* Scheduling options of the step kernels (results do not depend on them).
+ * xcd_order: 0 = tile b to workgroup b (the hardware deals workgroups to the 8
+ * XCDs round-robin); 1 = each XCD takes one contiguous run of tiles; 2 = whole
+ * x-rows of tiles, two tile rows in y at a time, go to one XCD together, so
+ * that neighbouring tiles share its L2.  Other values: EINVAL.
+ * nontemporal != 0 writes f* and g* with streaming stores.  Both default 0.
  * Drops any captured graph. */
 int pflbm_set_step_options(pflbm_handle h, int32_t xcd_order, int32_t nontemporal);
 

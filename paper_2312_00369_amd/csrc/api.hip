@@ -74,8 +74,12 @@ int validate_and_derive(const pflbm_params* p, Derived* d) {
   G.PX = P[0];
   G.PY = P[1];
   G.PZ = P[2];
-  G.SX = (int)round_up((size_t)P[0], kBlk);   // rows start on a population block
-  d->N = (long long)G.SX * G.PY * G.PZ;
+  // rows of SX slots; on a walled x axis the first domain node starts a
+  // population block (slot offset XO = 63), and the last row's padding node
+  // spills into one extra block
+  G.SX = (int)round_up((size_t)P[0], kBlk);
+  G.XO = G.pad[0] ? kBlk - 1 : 0;
+  d->N = (long long)G.SX * G.PY * G.PZ + G.XO;
   if (d->N >= (1LL << 31))
     return set_error(PFLBM_EUNSUPPORTED, "padded grid of %lld nodes exceeds 2^31", d->N);
   G.NQ = (long long)round_up((size_t)d->N, 256);
@@ -163,7 +167,7 @@ Layout make_layout(const Derived& d, int storage, dim3 tile) {
   else if (d.Qg == 7) sizes(I19(), I7());
   else sizes(I19(), I19());
   const Geo& G = d.geo;
-  L.nparts = (long long)((G.PX + tile.x - 1) / tile.x) * ((G.PY + tile.y - 1) / tile.y) *
+  L.nparts = (long long)((G.PX + G.XO + tile.x - 1) / tile.x) * ((G.PY + tile.y - 1) / tile.y) *
              ((G.PZ + tile.z - 1) / tile.z);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -181,11 +185,12 @@ Layout make_layout(const Derived& d, int storage, dim3 tile) {
   L.mu = take(L.c_bytes);
   L.snap = take(L.c_bytes);
   // partial records for the smallest tile the library accepts (64 threads)
-  const size_t max_parts = (size_t)((G.PX + 63) / 64) * G.PY * G.PZ;
+  const size_t max_parts = (size_t)((G.PX + G.XO + 63) / 64) * G.PY * G.PZ;
   L.partial = take(max_parts * kRecN * sizeof(double));
   L.rec = take(kRecN * sizeof(double) * 2);
   L.popmax = take(2 * kPopmaxBlocks * sizeof(float));
   L.wet = take(kWetEntries * sizeof(double));
+  L.gblocks = take((NQ / kBlk) * sizeof(uint32_t));
   L.total = off;
   return L;
 }
@@ -481,10 +486,21 @@ int create_common(const pflbm_params* prm, const uint8_t* mask, const double* ph
   h->partial = reinterpret_cast<double*>(h->base + L.partial);
   h->rec = reinterpret_cast<double*>(h->base + L.rec);
   h->popmax = reinterpret_cast<float*>(h->base + L.popmax);
+  h->gblocks = reinterpret_cast<uint32_t*>(h->base + L.gblocks);
 
   std::vector<uint32_t> words;
   h->classes.assign((size_t)prm->nx * prm->ny * prm->nz, 0);
   classify_nodes(dv, mask, words, h->classes.data());
+  // blocks of 64 slots that hold a ghost node: the split step's ghost pass
+  // visits these only
+  std::vector<uint32_t> gblocks;
+  for (size_t b = 0; b * kBlk < words.size(); ++b) {
+    bool any = false;
+    for (size_t j = b * kBlk; j < std::min(words.size(), (b + 1) * kBlk); ++j)
+      any = any || (words[j] & kGhost) != 0;
+    if (any) gblocks.push_back((uint32_t)b);
+  }
+  h->nghost_blocks = (long long)gblocks.size();
   if (dv.phys.chi_a != 0.0 && (rc = check_axis_ghosts(dv, words))) return fail(rc);
   std::vector<double> wet;
   if ((rc = wet_table(dv, prm, mask, words, wet))) return fail(rc);
@@ -493,6 +509,9 @@ int create_common(const pflbm_params* prm, const uint8_t* mask, const double* ph
 #define CK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return fail(set_error(PFLBM_EDEVICE, "%s: %s", #x, hipGetErrorString(e_))); } while (0)
   CK(hipMemsetAsync(h->base, 0, L.total, h->stream));
   CK(hipMemcpyAsync(h->nodes, words.data(), words.size() * 4, hipMemcpyHostToDevice, h->stream));
+  if (!gblocks.empty())
+    CK(hipMemcpyAsync(h->gblocks, gblocks.data(), gblocks.size() * 4, hipMemcpyHostToDevice,
+                      h->stream));
   CK(hipMemcpyAsync(h->base + L.wet, wet.data(), wet.size() * sizeof(double),
                     hipMemcpyHostToDevice, h->stream));
   if ((rc = upload_phi0(h, phi0, words))) return fail(rc);
@@ -585,6 +604,22 @@ int pflbm_classify(const pflbm_params* prm, const uint8_t* mask, uint8_t* classe
   if (rc) return rc;
   std::vector<uint32_t> words;
   classify_nodes(dv, mask, words, classes);
+  return PFLBM_OK;
+}
+
+// Free-energy coefficients from surface tension and interface width: the
+// double well beta phi^2 (1 - phi)^2 with gradient energy kappa/2 |grad phi|^2
+// has the planar profile 1/2 + 1/2 tanh(2 x / W) with W = sqrt(8 kappa / beta)
+// (Eq. initialphi) and tension sigma = sqrt(2 kappa beta) / 6; solved for the
+// coefficients, beta = 12 sigma / W and kappa = 3 sigma W / 2.
+int pflbm_beta_kappa(double sigma, double width, double* beta, double* kappa) {
+  clear_error();
+  if (!beta || !kappa) return set_error(PFLBM_EINVAL, "beta and kappa are required");
+  if (!(sigma > 0.0) || !(width > 0.0) || !std::isfinite(sigma) || !std::isfinite(width))
+    return set_error(PFLBM_EINVAL, "sigma and width must be finite and positive (got %g, %g)",
+                     sigma, width);
+  *beta = 12.0 * sigma / width;
+  *kappa = 1.5 * sigma * width;
   return PFLBM_OK;
 }
 
@@ -906,7 +941,7 @@ int pflbm_get_state(pflbm_handle h, void* host, size_t bytes) {
   pflbm_state_size(h, &need);
   if (!host || bytes < need) return set_error(PFLBM_EINVAL, "state buffer too small (%zu < %zu)", bytes, need);
   StateHeader hd{};
-  std::memcpy(hd.magic, "PFLBMST2", 8);
+  std::memcpy(hd.magic, "PFLBMST3", 8);
   hd.f_bytes = h->lay.f_bytes;
   hd.g_bytes = h->lay.g_bytes;
   hd.c_bytes = h->lay.c_bytes;
@@ -938,7 +973,7 @@ int pflbm_set_state(pflbm_handle h, const void* host, size_t bytes) {
   if (!host || bytes < need) return set_error(PFLBM_EINVAL, "state buffer too small (%zu < %zu)", bytes, need);
   StateHeader hd;
   std::memcpy(&hd, host, sizeof hd);
-  if (std::memcmp(hd.magic, "PFLBMST2", 8) != 0 || hd.f_bytes != h->lay.f_bytes ||
+  if (std::memcmp(hd.magic, "PFLBMST3", 8) != 0 || hd.f_bytes != h->lay.f_bytes ||
       hd.g_bytes != h->lay.g_bytes ||
       hd.c_bytes != h->lay.c_bytes || hd.lattice != h->prm.lattice ||
       hd.storage != h->prm.storage || hd.nx != h->prm.nx || hd.ny != h->prm.ny || hd.nz != h->prm.nz)

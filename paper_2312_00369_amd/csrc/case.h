@@ -27,7 +27,7 @@ void clear_error();
   } while (0)
 
 struct Layout {
-  size_t nodes, f[2], g[2], s, phi, mu, snap, partial, rec, popmax, wet, total;
+  size_t nodes, f[2], g[2], s, phi, mu, snap, partial, rec, popmax, wet, gblocks, total;
   size_t f_bytes, g_bytes;   // one f buffer, one g buffer
   size_t c_bytes;     // one compute-type field
   long long nparts;   // reduction partial records
@@ -74,6 +74,8 @@ struct pflbm_case_s {
   double* rec = nullptr;
   float* popmax = nullptr;        // kPopmaxBlocks (f, g) pairs
   std::vector<uint8_t> classes;   // host copy of the domain classes
+  uint32_t* gblocks = nullptr;    // population blocks (64 slots) holding a ghost node, ascending
+  long long nghost_blocks = 0;    // their number (the split step's ghost pass is skipped at 0)
   int cur = 0;                    // buffer holding the current post-collision state
   int64_t step = 0;
   bool snap_valid = false;

@@ -2,14 +2,18 @@
 // batch), templated on lattice and storage, and the table of entry points
 // each per-lattice source file instantiates (engine_<lattice>.hip).
 #pragma once
+#include <algorithm>
+
 #include "case.h"
 
 namespace pflbm {
 
 namespace {
 
+// Grid of the one-thread-per-slot kernels: x runs over slots XO .. XO + PX - 1
+// of each row (node_coords subtracts XO).
 dim3 grid_of(const Geo& G, dim3 t) {
-  return dim3((G.PX + t.x - 1) / t.x, (G.PY + t.y - 1) / t.y, (G.PZ + t.z - 1) / t.z);
+  return dim3((G.PX + G.XO + t.x - 1) / t.x, (G.PY + t.y - 1) / t.y, (G.PZ + t.z - 1) / t.z);
 }
 
 template <class L, int S>
@@ -24,6 +28,17 @@ struct Engine {
     else
       hipLaunchKernelGGL((k_phi<L, S, false>), grid_of(G, h->tile), h->tile, 0, h->stream,
                          h->nodes, h->g[h->cur], static_cast<C*>(h->phi), G, h->dv.phys);
+    PFLBM_HIP(hipGetLastError());
+    return PFLBM_OK;
+  }
+
+  // ghost phi into the phi array (split step, after phi)
+  static int ghost(pflbm_case_s* h) {
+    if (!h->nghost_blocks) return PFLBM_OK;
+    const long long nb = h->nghost_blocks;
+    const unsigned grid = (unsigned)std::min<long long>((nb + 7) / 8, 2048);
+    hipLaunchKernelGGL((k_ghost<L, C>), dim3(grid), dim3(kGhostThreads), 0, h->stream, h->nodes,
+                       static_cast<C*>(h->phi), h->gblocks, (int)nb, h->dv.geo, h->dv.phys);
     PFLBM_HIP(hipGetLastError());
     return PFLBM_OK;
   }
@@ -64,8 +79,8 @@ struct Engine {
   static int step_v(pflbm_case_s* h) {
     const Geo& G = h->dv.geo;
     constexpr int TY = BY * KY, TZ = (L::D == 3) ? BZ * KZ : 1;
-    const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY, nbz = (G.PZ + TZ - 1) / TZ;
-    const dim3 grid(TileOrder{nbx, nby, nbz, h->dv.phys.xcd_order}.grid(), 1, 1);
+    const TileGrid TG(G, 64, TY, TZ);
+    const dim3 grid(TileOrder{TG.nx, TG.ny, TG.nz, h->dv.phys.xcd_order}.grid(), 1, 1);
     const dim3 block(64, BY, (L::D == 3) ? BZ : 1);
     const int c = h->cur;
     constexpr int bz = (L::D == 3) ? BZ : 1, kz = (L::D == 3) ? KZ : 1;
@@ -83,10 +98,11 @@ struct Engine {
   static int split_v(pflbm_case_s* h) {
     const Geo& G = h->dv.geo;
     int rc = phi(h);
+    if (!rc) rc = ghost(h);
     if (rc) return rc;
     constexpr int bz = (L::D == 3) ? BZ : 1;
-    const int nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY, nbz = (G.PZ + bz - 1) / bz;
-    const unsigned ngrid = TileOrder{nbx, nby, nbz, h->dv.phys.xcd_order}.grid();
+    const TileGrid TG(G, 64, BY, bz);
+    const unsigned ngrid = TileOrder{TG.nx, TG.ny, TG.nz, h->dv.phys.xcd_order}.grid();
     const int c = h->cur;
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(ngrid), dim3(64, BY, bz), 0, h->stream, h->nodes,
@@ -104,9 +120,10 @@ struct Engine {
     if constexpr (L::D == 3) {
       const Geo& G = h->dv.geo;
       int rc = phi(h);
+      if (!rc) rc = ghost(h);
       if (rc) return rc;
-      const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY, nbz = (G.PZ + TZ - 1) / TZ;
-      const unsigned ngrid = TileOrder{nbx, nby, nbz, h->dv.phys.xcd_order}.grid();
+      const TileGrid TG(G, 64, TY, TZ);
+      const unsigned ngrid = TileOrder{TG.nx, TG.ny, TG.nz, h->dv.phys.xcd_order}.grid();
       const int c = h->cur;
       auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(ngrid), dim3(64, TY), 0, h->stream, h->nodes,
@@ -125,8 +142,8 @@ struct Engine {
   static int march_v(pflbm_case_s* h) {
     if constexpr (L::D == 3) {
       const Geo& G = h->dv.geo;
-      const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY, nbz = (G.PZ + TZ - 1) / TZ;
-      const unsigned ngrid = TileOrder{nbx, nby, nbz, h->dv.phys.xcd_order}.grid();
+      const TileGrid TG(G, 64, TY, TZ);
+      const unsigned ngrid = TileOrder{TG.nx, TG.ny, TG.nz, h->dv.phys.xcd_order}.grid();
       const int c = h->cur;
       auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(ngrid), dim3(64, TY), 0, h->stream, h->nodes,
@@ -229,19 +246,22 @@ struct GroupEngine {
   template <int BY, int BZ>
   static int launch_split(const GroupLaunch& gl, int parity) {
     constexpr int bz = (L::D == 3) ? BZ : 1;
-    if (gl.persist) {
+    if (gl.persist)
       hipLaunchKernelGGL((k_phi_group<L, S, BY, bz, true>), dim3(gl.grid), dim3(64, BY, bz), 0,
                          gl.stream, gl.table, gl.ntiles, gl.cases, parity);
-      PFLBM_HIP(hipGetLastError());
-      hipLaunchKernelGGL((k_stepB_group<L, S, BY, bz, true>), dim3(gl.grid), dim3(64, BY, bz), 0,
-                         gl.stream, gl.table, gl.ntiles, gl.cases, parity);
-    } else {
+    else
       hipLaunchKernelGGL((k_phi_group<L, S, BY, bz, false>), dim3(gl.grid), dim3(64, BY, bz), 0,
                          gl.stream, gl.table, gl.ntiles, gl.cases, parity);
-      PFLBM_HIP(hipGetLastError());
+    PFLBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_ghost_group<L, S>), dim3(gl.grid), dim3(kGhostThreads), 0, gl.stream,
+                       gl.table, gl.ntiles, gl.cases, 64, BY, bz);
+    PFLBM_HIP(hipGetLastError());
+    if (gl.persist)
+      hipLaunchKernelGGL((k_stepB_group<L, S, BY, bz, true>), dim3(gl.grid), dim3(64, BY, bz), 0,
+                         gl.stream, gl.table, gl.ntiles, gl.cases, parity);
+    else
       hipLaunchKernelGGL((k_stepB_group<L, S, BY, bz, false>), dim3(gl.grid), dim3(64, BY, bz),
                          0, gl.stream, gl.table, gl.ntiles, gl.cases, parity);
-    }
     PFLBM_HIP(hipGetLastError());
     return PFLBM_OK;
   }
@@ -250,6 +270,9 @@ struct GroupEngine {
     if constexpr (L::D == 3) {
       hipLaunchKernelGGL((k_phi_group_all<L, S>), dim3(gl.grid), dim3(256), 0, gl.stream,
                          gl.table, gl.ntiles, gl.cases, parity, 64, TY, TZ);
+      PFLBM_HIP(hipGetLastError());
+      hipLaunchKernelGGL((k_ghost_group<L, S>), dim3(gl.grid), dim3(kGhostThreads), 0, gl.stream,
+                         gl.table, gl.ntiles, gl.cases, 64, TY, TZ);
       PFLBM_HIP(hipGetLastError());
       if (gl.persist)
         hipLaunchKernelGGL((k_stepC_group<L, S, TY, TZ, true>), dim3(gl.grid), dim3(64, TY), 0,

@@ -97,7 +97,7 @@ int tiles_of(const pflbm_case_s* h, int variant) {
   int t[5];
   step_variant_tile(h->dv.D, variant, t);
   const Geo& G = h->dv.geo;
-  return ((G.PX + t[2] - 1) / t[2]) * ((G.PY + t[3] - 1) / t[3]) * ((G.PZ + t[4] - 1) / t[4]);
+  return TileGrid(G, t[2], t[3], t[4]).count();
 }
 
 int rebuild(pflbm_group_s* g) {

@@ -31,14 +31,42 @@ enum Storage { kF64 = 0, kF32 = 1, kF16Dev = 2 };
 // Node index within one case (the padded grid has fewer than 2^31 nodes).
 using nidx = uint32_t;
 
+// Node (x, y, z) of the padded grid sits in slot x + XO + SX (y + PY z).  On a
+// walled x axis XO = 63: the first domain node x = 1 then starts a 64-node
+// block, so a row of 64 k domain nodes fills k whole blocks and the two padding
+// nodes of consecutive rows share the block between them.  Without the offset
+// a 256-node row would spill one node into a fifth block, and every fifth
+// wavefront of a step would move whole cache lines for that one node.
 struct Geo {
   int PX, PY, PZ;    // padded extents: periodic axes as given, others + 2
-  int SX;            // x stride (>= PX, a multiple of 64); nodes x >= PX are dead
+  int SX;            // row stride in slots (>= PX, a multiple of 64)
   int per[3];        // periodic flags
   int pad[3];        // 0 periodic, 1 otherwise: domain x = padded x - pad
-  long long NQ;      // node slots (>= SX*PY*PZ, a multiple of 256); stride of u components
+  int XO;            // slot of x = 0 within its row: 63 on a walled x axis, else 0
+  long long NQ;      // node slots (>= SX*PY*PZ + XO, a multiple of 256); stride of u components
   __host__ __device__ nidx idx(int x, int y, int z) const {
-    return (nidx)x + (nidx)SX * ((nidx)y + (nidx)PY * (nidx)z);
+    return (nidx)(x + XO) + (nidx)SX * ((nidx)y + (nidx)PY * (nidx)z);
+  }
+};
+
+// Tiles of TX x TY x TZ nodes; tile b has indices (b % nx, (b / nx) % ny,
+// b / (nx ny)).  Along x the tiles start at the first domain node (the
+// padding layers of a walled axis hold no fluid or boundary node), so with
+// XO = 63 a 64-wide tile row is exactly one population block.  Along y and z
+// they start at the padding layer: the tile rows next to the walls then hold
+// fewer nodes, and on a small grid, where one round of workgroups makes up
+// the launch and its slowest tile sets the time, those wall tiles (which
+// also form ghost means) are not the largest.
+struct TileGrid {
+  int nx, ny, nz, ox, oy, oz, tx, ty, tz;
+  __host__ __device__ TileGrid(const Geo& G, int TX, int TY, int TZ)
+      : nx((G.PX - 2 * G.pad[0] + TX - 1) / TX), ny((G.PY + TY - 1) / TY),
+        nz((G.PZ + TZ - 1) / TZ), ox(G.pad[0]), oy(0), oz(0), tx(TX), ty(TY), tz(TZ) {}
+  __host__ __device__ int count() const { return nx * ny * nz; }
+  __host__ __device__ void origin(int b, int& x0, int& y0, int& z0) const {
+    x0 = ox + (b % nx) * tx;
+    y0 = oy + ((b / nx) % ny) * ty;
+    z0 = oz + (b / (nx * ny)) * tz;
   }
 };
 
@@ -195,11 +223,13 @@ __device__ inline typename SetT::C pull(const void* buf, int i, nidx n, const ni
   return bb ? SetT::load(buf, L::opp(i), n, scale) : SetT::load(buf, i, nb[L::opp(i)], scale);
 }
 
+// One thread per slot of the padded grid (x counted from slot 0 of the row, so
+// a 64-wide workgroup row covers one population block).
 __device__ inline bool node_coords(const Geo& G, int& x, int& y, int& z) {
-  x = blockIdx.x * blockDim.x + threadIdx.x;
+  x = blockIdx.x * blockDim.x + threadIdx.x - G.XO;
   y = blockIdx.y * blockDim.y + threadIdx.y;
   z = blockIdx.z * blockDim.z + threadIdx.z;
-  return x < G.PX && y < G.PY && z < G.PZ;
+  return x >= 0 && x < G.PX && y < G.PY && z < G.PZ;
 }
 
 // Inside a loop the compiler hoists every value derived from loop-invariant
@@ -280,6 +310,64 @@ __device__ inline C ghost_mean(const C* sphi, const uint32_t* sw, int t, int sx,
   return den > 0 ? ghost_value(num / C(den), chi_a) : C(0);
 }
 
+// The same ghost value read from the phi array (zeta = 1 entries of the 3^D
+// block around node (x, y, z), in the order ghost_mean takes them), for the
+// ghost pass of the split step.  Entries outside the padded grid, or in the
+// padding layer of a walled axis (never zeta = 1), read the node itself (a
+// ghost, so never counted): every load of the block is issued before the
+// first is used.
+template <class L, class C>
+__device__ inline C ghost_from(const uint32_t* __restrict__ nodes, const C* __restrict__ phi,
+                               const Geo& G, int x, int y, int z, C chi_a) {
+  constexpr int NZ = (L::D == 3) ? 3 : 1, NB = 9 * NZ;
+  const int P3[3] = {G.PX, G.PY, G.PZ}, c3[3] = {x, y, z};
+  const nidx self = G.idx(x, y, z);
+  // per axis: coordinates c - 1, c, c + 1 (wrapped on a periodic axis) and
+  // whether they are read
+  int qq[3][3];
+  bool vv[3][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      int q = c3[d] + s - 1;
+      if (d == 2 && L::D == 2) q = c3[d];
+      if (G.per[d]) {
+        q += (q < 0) ? P3[d] : 0;
+        q -= (q >= P3[d]) ? P3[d] : 0;
+        vv[d][s] = true;
+      } else {
+        vv[d][s] = q >= 1 && q < P3[d] - 1;
+      }
+      qq[d][s] = q;
+    }
+  }
+  nidx at[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const int sx = k % 3, sy = (k / 3) % 3, sz = (L::D == 3) ? k / 9 : 1;
+    const bool ok = vv[0][sx] && vv[1][sy] && vv[2][sz];
+    at[k] = ok ? G.idx(qq[0][sx], qq[1][sy], qq[2][sz]) : self;
+  }
+  uint32_t w[NB];
+  C v[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    w[k] = nodes[at[k]];
+    v[k] = phi[at[k]];
+  }
+  C num = C(0);
+  int den = 0;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    if (w[k] & kZeta) {
+      num += v[k];
+      ++den;
+    }
+  }
+  return den > 0 ? ghost_value(num / C(den), chi_a) : C(0);
+}
+
 // mu of Eq. (chemical_potencial2) at a zeta = 1 entry: isotropic Laplacian
 // (Eq. Laplace) of phi and a_v = |grad eps| (Eq. avvv) from the neighbours.
 // Wall coefficient sqrt(2 kappa beta) cos(theta) of Eq. (chemical_potencial2) at
@@ -352,7 +440,7 @@ __global__ void k_mu(const uint32_t* __restrict__ nodes, C* __restrict__ phi,
   const int NL = LX * LY * LZ;
   C* sphi = reinterpret_cast<C*>(smem);
   uint32_t* sw = reinterpret_cast<uint32_t*>(sphi + NL);
-  const int ox = blockIdx.x * TX - H, oy = blockIdx.y * TY - H, oz = blockIdx.z * TZ - HZ;
+  const int ox = blockIdx.x * TX - H - G.XO, oy = blockIdx.y * TY - H, oz = blockIdx.z * TZ - HZ;
   const int tid = threadIdx.x + TX * (threadIdx.y + TY * threadIdx.z);
   const int nthr = TX * TY * TZ;
 
@@ -824,21 +912,107 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_step(
   using T = StepTile<L, S, BY, BZ, KY, KZ>;
   __shared__ typename T::C sphi[T::NL];
   __shared__ uint32_t sw[T::NL];
-  const int nbx = (G.PX + T::TX - 1) / T::TX, nby = (G.PY + T::TY - 1) / T::TY;
-  const int b = TileOrder{nbx, nby, (G.PZ + T::TZ - 1) / T::TZ, P.xcd_order}.tile(blockIdx.x);
+  const TileGrid TG(G, T::TX, T::TY, T::TZ);
+  const int b = TileOrder{TG.nx, TG.ny, TG.nz, P.xcd_order}.tile(blockIdx.x);
   if (b < 0) return;
-  step_tile<L, S, BY, BZ, KY, KZ, O>((b % nbx) * T::TX, ((b / nbx) % nby) * T::TY,
-                                  (b / (nbx * nby)) * T::TZ, nodes, fsrc, gsrc, fdst, gdst, sprev,
-                                  G, P, sphi, sw);
+  int x0, y0, z0;
+  TG.origin(b, x0, y0, z0);
+  step_tile<L, S, BY, BZ, KY, KZ, O>(x0, y0, z0, nodes, fsrc, gsrc, fdst, gdst, sprev, G, P, sphi,
+                                  sw);
 }
 
 // ------------------------------------------------------------------ split step
-// Two launches per step: k_phi writes phi, then this kernel loads phi and the
-// node words of the tile with a two-node halo into LDS (4 bytes per entry, from
-// L2), fills ghosts, evaluates mu and grad phi from LDS, pulls f and g and
-// collides.  One thread per node; workgroup (64, BY, BZ).  g is read twice per
-// step, but nothing is recomputed on the halo, which suits D3Q19 where a
-// one-node halo around a 64 x 4 x 4 tile already has 1.3 times its nodes.
+// ------------------------------------------------------------------ ghost pass
+// Between the phi pass and the collide pass of the split step: the ghost
+// nodes' phi (Sec. 2.2.2; Appendix A with chi_a != 0) into the phi array, from
+// the zeta = 1 values the phi pass wrote.  The collide pass then reads phi of
+// the tile and one halo layer as it stands, with no ghost means of its own.
+//
+// A workgroup of kGhostThreads takes one tile's box: the tile widened by the
+// padding layer where it meets a face of the padded grid, so that the tiles of
+// a case cover every ghost node once.  It lists the box's ghost nodes in LDS,
+// kGhostChunk entries at a time, and then evaluates them with every lane busy
+// (a walled x face holds one ghost node per row, which a one-thread-per-node
+// pass would leave alone in its wavefront).
+constexpr int kGhostThreads = 256, kGhostChunk = 1024;
+template <class L, class C>
+__device__ inline void ghost_box(const uint32_t* __restrict__ nodes, C* __restrict__ phi,
+                                 const Geo& G, C chi_a, const TileGrid& TG, int b, int* list,
+                                 int* count) {
+  int o[3];
+  TG.origin(b, o[0], o[1], o[2]);
+  const int P3[3] = {G.PX, G.PY, G.PZ}, T3[3] = {TG.tx, TG.ty, TG.tz},
+            org[3] = {TG.ox, TG.oy, TG.oz};
+  int lo[3], ext[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = (o[d] == org[d]) ? 0 : o[d];
+    const int hi = (o[d] + T3[d] >= P3[d] - G.pad[d]) ? P3[d] : o[d] + T3[d];
+    ext[d] = hi - lo[d];
+  }
+  const int nbox = ext[0] * ext[1] * ext[2];
+  auto coords = [&](int m, int& x, int& y, int& z) {
+    x = lo[0] + m % ext[0];
+    y = lo[1] + (m / ext[0]) % ext[1];
+    z = lo[2] + m / (ext[0] * ext[1]);
+  };
+  for (int c0 = 0; c0 < nbox; c0 += kGhostChunk) {
+    if (threadIdx.x == 0) *count = 0;
+    __syncthreads();
+    const int c1 = c0 + kGhostChunk < nbox ? c0 + kGhostChunk : nbox;
+    for (int m = c0 + (int)threadIdx.x; m < c1; m += kGhostThreads) {
+      int x, y, z;
+      coords(m, x, y, z);
+      if (nodes[G.idx(x, y, z)] & kGhost) list[atomicAdd(count, 1)] = m;
+    }
+    __syncthreads();
+    const int cnt = *count;
+    for (int j = threadIdx.x; j < cnt; j += kGhostThreads) {
+      int x, y, z;
+      coords(list[j], x, y, z);
+      phi[G.idx(x, y, z)] = ghost_from<L, C>(nodes, phi, G, x, y, z, chi_a);
+    }
+    __syncthreads();
+  }
+}
+
+// Single case: one wavefront per listed population block (64 slots that hold
+// at least one ghost node; the list is built with the node classes), each lane
+// one slot.  Wavefronts stride over the list, two blocks at a time so that the
+// node-word loads of both are in flight together.
+template <class L, class C>
+__global__ __launch_bounds__(kGhostThreads) void k_ghost(const uint32_t* __restrict__ nodes,
+                                                          C* __restrict__ phi,
+                                                          const uint32_t* __restrict__ blocks,
+                                                          int nblocks, Geo G, Phys P) {
+  const int lane = threadIdx.x % 64;
+  const int nw = gridDim.x * (kGhostThreads / 64);
+  const C chi_a = C(P.chi_a);
+  for (int e = blockIdx.x * (kGhostThreads / 64) + threadIdx.x / 64; e < nblocks; e += 2 * nw) {
+    uint32_t slot[2], w[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int ek = e + k * nw;
+      slot[k] = ek < nblocks ? blocks[ek] * (uint32_t)kBlk + lane : 0u;
+      w[k] = ek < nblocks ? nodes[slot[k]] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (!(w[k] & kGhost)) continue;
+      // (x, y, z) of the slot: slot = x + XO + SX (y + PY z)
+      const int r = (int)slot[k] - G.XO;
+      const int x = r % G.SX, row = r / G.SX;
+      const int y = row % G.PY, z = row / G.PY;
+      phi[slot[k]] = ghost_from<L, C>(nodes, phi, G, x, y, z, chi_a);
+    }
+  }
+}
+
+// Split step, second launch: phi and the node words of the tile and a
+// one-node halo into LDS (4 bytes per entry, mostly from L2; ghost entries
+// carry the ghost pass's values), mu and grad phi from LDS, f and g pulled,
+// both sets collided.  One thread per node; workgroup (64, BY, BZ).  g is read
+// twice per step (phi pass and here), but nothing is recomputed on the halo.
 template <class L, int S, int BY, int BZ, bool O = false>
 __device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __restrict__ nodes,
                                   const void* __restrict__ fsrc, const void* __restrict__ gsrc,
@@ -852,16 +1026,17 @@ __device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __rest
   constexpr int Q = L::Q;
   constexpr bool D3 = (L::D == 3);
   constexpr int TX = 64, TY = BY, TZ = D3 ? BZ : 1;
-  constexpr int LX = TX + 4, LY = TY + 4, LZ = D3 ? TZ + 4 : 1;
+  constexpr int LX = TX + 2, LY = TY + 2, LZ = D3 ? TZ + 2 : 1;
   constexpr int SX = LX, SXY = LX * LY, NL = LX * LY * LZ;
-  constexpr int HZ = D3 ? 2 : 0;
+  constexpr int HZ = D3 ? 1 : 0;
   constexpr int NT = 64 * BY * (D3 ? BZ : 1);
   const int lane = threadIdx.x, ty = threadIdx.y, tz = D3 ? threadIdx.z : 0;
   const int tid = lane + 64 * (ty + BY * tz);
   const int P3[3] = {G.PX, G.PY, G.PZ};
-  // word and phi of LDS entry (lx, ly, lz); zeta = 0 entries hold phi = 0
-  auto load_entry = [&](int lx, int ly, int lz) -> uint32_t {
-    int q[3] = {x0 - 2 + lx, y0 - 2 + ly, z0 - HZ + lz};
+  // entries that are neither zeta = 1 nor ghost hold phi = 0
+  for (int m = tid; m < NL; m += NT) {
+    const int lx = m % LX, ly = (m / LX) % LY, lz = m / (LX * LY);
+    int q[3] = {x0 - 1 + lx, y0 - 1 + ly, z0 - HZ + lz};
     bool ok = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -877,39 +1052,15 @@ __device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __rest
     if (ok) {
       const nidx n = G.idx(q[0], q[1], q[2]);
       w = nodes[n];
-      if (w & kZeta) v = phi[n];
+      if (w & (kZeta | kGhost)) v = phi[n];
     }
-    const int m = lx + SX * ly + SXY * lz;
     sw[m] = w;
     sphi[m] = v;
-    return w;
-  };
-  // tile and first halo layer; the second layer only where ghost means need it
-  constexpr int H1X = TX + 2, H1Y = TY + 2, H1Z = D3 ? TZ + 2 : 1;
-  constexpr int N1 = H1X * H1Y * H1Z;
-  bool ghost_near = false;
-  for (int m = tid; m < N1; m += NT) {
-    const int lx = 1 + m % H1X, ly = 1 + (m / H1X) % H1Y, lz = (D3 ? 1 : 0) + m / (H1X * H1Y);
-    ghost_near |= (load_entry(lx, ly, lz) & kGhost) != 0;
   }
-  if (__syncthreads_or(ghost_near)) {
-    for (int m = tid; m < NL; m += NT) {
-      const int lx = m % LX, ly = (m / LX) % LY, lz = m / (LX * LY);
-      const bool ring2 = lx == 0 || lx == LX - 1 || ly == 0 || ly == LY - 1 ||
-                         (D3 && (lz == 0 || lz == LZ - 1));
-      if (ring2) load_entry(lx, ly, lz);
-    }
-    __syncthreads();
-    for (int m = tid; m < N1; m += NT) {
-      const int lx = 1 + m % H1X, ly = 1 + (m / H1X) % H1Y, lz = (D3 ? 1 : 0) + m / (H1X * H1Y);
-      const int t = lx + SX * ly + SXY * lz;
-      if (sw[t] & kGhost) sphi[t] = ghost_mean<L, C>(sphi, sw, t, SX, SXY, C(P.chi_a));
-    }
-    __syncthreads();
-  }
+  __syncthreads();
   const int x = x0 + lane, y = y0 + ty, z = z0 + tz;
   if (x >= G.PX || y >= G.PY || z >= G.PZ) return;
-  const int t = (2 + lane) + SX * (2 + ty) + SXY * (HZ + tz);
+  const int t = (1 + lane) + SX * (1 + ty) + SXY * (HZ + tz);
   const uint32_t w = sw[t];
   if (!(w & kZeta)) return;
   const nidx n = G.idx(x, y, z);
@@ -938,15 +1089,16 @@ __global__ __launch_bounds__(64 * BY * BZ, 7) void k_stepB(
     const void* __restrict__ gsrc, void* __restrict__ fdst, void* __restrict__ gdst,
     ComputeT<S>* __restrict__ sprev, const ComputeT<S>* __restrict__ phi, Geo G, Phys P) {
   constexpr bool D3 = (L::D == 3);
-  constexpr int NL = 68 * (BY + 4) * (D3 ? BZ + 4 : 1);
+  constexpr int NL = 66 * (BY + 2) * (D3 ? BZ + 2 : 1);
   __shared__ ComputeT<S> sphi[NL];
   __shared__ uint32_t sw[NL];
   const int TZ = D3 ? BZ : 1;
-  const int nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY;
-  const int b = TileOrder{nbx, nby, (G.PZ + TZ - 1) / TZ, P.xcd_order}.tile(blockIdx.x);
+  const TileGrid TG(G, 64, BY, TZ);
+  const int b = TileOrder{TG.nx, TG.ny, TG.nz, P.xcd_order}.tile(blockIdx.x);
   if (b < 0) return;
-  stepB_tile<L, S, BY, BZ, O>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ, nodes,
-                           fsrc, gsrc, fdst, gdst, sprev, phi, G, P, sphi, sw);
+  int x0, y0, z0;
+  TG.origin(b, x0, y0, z0);
+  stepB_tile<L, S, BY, BZ, O>(x0, y0, z0, nodes, fsrc, gsrc, fdst, gdst, sprev, phi, G, P, sphi, sw);
 }
 
 // phi of the tile nodes (64 x BY x BZ) from pulled g, same arithmetic as k_phi.
@@ -970,16 +1122,19 @@ __device__ inline void phi_tile(int x0, int y0, int z0, const uint32_t* __restri
 }
 
 // ------------------------------------------------------------------ z-marching split step (3D)
-// Second pass of the split step for D3Q19, marching along z.  A workgroup of
+// Second launch of the split step for D3Q19, marching along z.  A workgroup of
 // (64, TY) threads owns a column of 64 x TY x TZ nodes and walks it one z
-// plane at a time.  LDS holds a ring of five phi / node-word planes (z-2 ..
-// z+2, each 68 x (TY+4) with a two-node halo in x and y): a new plane is loaded
-// per step, ghost means are filled one plane ahead, and the plane z is
-// collided.  Rows shared by consecutive planes of the pulls come from cache,
-// so neighbouring tiles along z no longer refetch them.
+// plane at a time.  LDS holds a ring of four phi / node-word planes, each
+// 66 x (TY+2) (the tile and a one-node halo in x and y; ghost entries carry
+// the ghost pass's values).  Iteration z stores plane z + 1 (loaded into
+// registers during the previous iteration), requests plane z + 2, and after
+// one barrier collides plane z from planes z - 1, z, z + 1.  Plane z + 1
+// overwrites the slot of plane z - 3, which no thread still reads, so one
+// barrier per plane suffices.  Rows shared by consecutive planes of the pulls
+// come from cache, so neighbouring tiles along z do not refetch them.
 template <class L, int S, int TY, int TZ>
 struct ColumnTile {
-  static constexpr int LX = 68, LY = TY + 4, PLANE = LX * LY, NL = 5 * PLANE;
+  static constexpr int LX = 66, LY = TY + 2, PLANE = LX * LY, NL = 4 * PLANE;
 };
 
 template <class L, int S, int TY, int TZ, bool O = false>
@@ -988,23 +1143,23 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
                                   void* __restrict__ fdst, void* __restrict__ gdst,
                                   ComputeT<S>* __restrict__ sprev,
                                   const ComputeT<S>* __restrict__ phi, const Geo& G,
-                                  const Phys& P0, ComputeT<S>* sphi, uint32_t* sw) {
+                                  const Phys& P, ComputeT<S>* sphi, uint32_t* sw) {
   static_assert(L::D == 3, "z marching is for D3Q19");
-  Phys P = P0;        // made opaque once per plane (opaque())
   using C = ComputeT<S>;
   using GS = Set<S, true, L::G::Q, O>;
   using FS = Set<S, false, L::Q, O>;
   constexpr int Q = L::Q;
-  constexpr int LX = 68, LY = TY + 4, PL = LX * LY;
+  constexpr int LX = 66, LY = TY + 2, PL = LX * LY;
   constexpr int NT = 64 * TY;
+  constexpr int KP = (PL + NT - 1) / NT;   // plane entries per thread
   const int lane = threadIdx.x, ty = threadIdx.y;
   int tid = lane + 64 * ty;            // made opaque once per plane, with x and y
   const int P3[3] = {G.PX, G.PY, G.PZ};
-  // ring slot of plane z (z >= z0 - 2)
-  auto slot = [&](int z) { return (z - z0 + 2) % 5; };
-  auto load_plane = [&](int z) {
-    C* fp = sphi + slot(z) * PL;
-    uint32_t* wp = sw + slot(z) * PL;
+  // ring slot of plane z (z >= z0 - 1)
+  auto slot = [&](int z) { return (z - z0 + 1) & 3; };
+  // node words and phi of this thread's entries of plane z into registers (phi
+  // whatever the word, masked when it goes to LDS, so the loads are independent)
+  auto issue_plane = [&](int z, uint32_t (&hw)[KP], C (&hv)[KP]) {
     int qz = z;
     bool zok = true;
     if (G.per[2]) {
@@ -1013,9 +1168,14 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
     } else if (qz < 0 || qz >= P3[2]) {
       zok = false;
     }
-    for (int m = tid; m < PL; m += NT) {
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int m = tid + k * NT;
+      hw[k] = 0u;
+      hv[k] = C(0);
+      if (m >= PL) continue;
       const int lx = m % LX, ly = m / LX;
-      int q[2] = {x0 - 2 + lx, y0 - 2 + ly};
+      int q[2] = {x0 - 1 + lx, y0 - 1 + ly};
       bool ok = zok;
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
@@ -1026,111 +1186,87 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
           ok = false;
         }
       }
-      uint32_t w = 0;
-      C v = C(0);
       if (ok) {
         const nidx n = G.idx(q[0], q[1], qz);
-        w = nodes[n];
-        if (w & kZeta) v = phi[n];
+        hw[k] = nodes[n];
+        hv[k] = phi[n];
       }
-      wp[m] = w;
-      fp[m] = v;
     }
   };
-  // ghost means of plane z over the tile and its first halo layer in x, y.
-  // ghost_mean walks the 3x3x3 block with strides (1, LX, PL): planes z-1, z,
-  // z+1 must sit in consecutive slots, which the ring does not guarantee, so the
-  // block is gathered explicitly here.
-  auto fill_ghosts = [&](int z) {
-    const int sm = slot(z - 1) * PL, s0 = slot(z) * PL, sp = slot(z + 1) * PL;
-    for (int m = tid; m < 66 * (TY + 2); m += NT) {
-      const int lx = 1 + m % 66, ly = 1 + m / 66;
-      const int t = lx + LX * ly;
-      if (!(sw[s0 + t] & kGhost)) continue;
-      C num = C(0);
-      int den = 0;
-      const int base[3] = {sm, s0, sp};
+  // entries that are neither zeta = 1 nor ghost hold phi = 0
+  auto commit_plane = [&](int z, const uint32_t (&hw)[KP], const C (&hv)[KP]) {
+    C* fp = sphi + slot(z) * PL;
+    uint32_t* wp = sw + slot(z) * PL;
 #pragma unroll
-      for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-          for (int dx = -1; dx <= 1; ++dx) {
-            const int t2 = base[dz] + t + dx + LX * dy;
-            if (sw[t2] & kZeta) {
-              num += sphi[t2];
-              ++den;
-            }
-          }
-      if (den > 0) sphi[s0 + t] = ghost_value(num / C(den), C(P.chi_a));
+    for (int k = 0; k < KP; ++k) {
+      const int m = tid + k * NT;
+      if (m >= PL) continue;
+      wp[m] = hw[k];
+      fp[m] = (hw[k] & (kZeta | kGhost)) ? hv[k] : C(0);
     }
   };
-  for (int z = z0 - 2; z <= z0 + 1; ++z) load_plane(z);
-  __syncthreads();
-  fill_ghosts(z0 - 1);
-  fill_ghosts(z0);
-  __syncthreads();
+  uint32_t hw[KP];
+  C hv[KP];
+  issue_plane(z0 - 1, hw, hv);
+  commit_plane(z0 - 1, hw, hv);
+  issue_plane(z0, hw, hv);
+  commit_plane(z0, hw, hv);
+  issue_plane(z0 + 1, hw, hv);
   for (int z = z0; z < z0 + TZ; ++z) {
-    P = P0;
-    opaque(P);
     tid = lane + 64 * ty;
     asm volatile("" : "+v"(tid));
-    load_plane(z + 2);
-    __syncthreads();
-    fill_ghosts(z + 1);
+    commit_plane(z + 1, hw, hv);
+    if (z + 2 <= z0 + TZ) issue_plane(z + 2, hw, hv);
     __syncthreads();
     int x = x0 + lane, y = y0 + ty;
     opaque(x, y);
-    if (x < G.PX && y < G.PY && z < G.PZ) {
-      const int t = (2 + lane) + LX * (2 + ty);
-      const int s0 = slot(z) * PL, sm = slot(z - 1) * PL, sp = slot(z + 1) * PL;
-      const uint32_t w = sw[s0 + t];
-      if (w & kZeta) {
-        const nidx n = G.idx(x, y, z);
-        nidx nb[Q];
-        neighbours<L>(G, x, y, z, nb);
-        C f[Q], g[L::G::Q];
-        f[0] = C(FS::load_rest(fsrc, n));
-        const double g0 = GS::load_rest(gsrc, n);
-        g[0] = C(0);
+    if (x >= G.PX || y >= G.PY || z >= G.PZ) continue;
+    const int t = (1 + lane) + LX * (1 + ty);
+    const int s0 = slot(z) * PL, sm = slot(z - 1) * PL, sp = slot(z + 1) * PL;
+    const uint32_t w = sw[s0 + t];
+    if (!(w & kZeta)) continue;
+    const nidx n = G.idx(x, y, z);
+    nidx nb[Q];
+    neighbours<L>(G, x, y, z, nb);
+    C f[Q], g[L::G::Q];
+    f[0] = C(FS::load_rest(fsrc, n));
+    const double g0 = GS::load_rest(gsrc, n);
+    g[0] = C(0);
 #pragma unroll
-        for (int i = 1; i < Q; ++i) {
-          f[i] = pull<L, FS>(fsrc, i, n, nb, w, P.scale_f);
-          if (i < L::G::Q) g[i] = pull<typename L::G, GS>(gsrc, i, n, nb, w, P.scale_g);
-        }
-        // neighbour entry for lattice direction i
-        auto at = [&](int i) {
-          const int sl = L::cz(i) < 0 ? sm : (L::cz(i) > 0 ? sp : s0);
-          return sl + t + L::cx(i) + LX * L::cy(i);
-        };
-        // mu (same arithmetic as mu_at) and grad phi
-        const C ph = sphi[s0 + t];
-        C lap = C(0), ex = C(0), ey = C(0), ez = C(0);
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-          const int t2 = at(i);
-          const C wi = C(L::w(i));
-          lap += C(2) * wi * (sphi[t2] - ph);
-          const C e = (sw[t2] & kFluid) ? C(1) : C(0);
-          ex += wi * C(L::cx(i)) * e;
-          ey += wi * C(L::cy(i)) * e;
-          ez += wi * C(L::cz(i)) * e;
-        }
-        const C inv_cs2 = C(3);
-        lap *= inv_cs2;
-        ex *= inv_cs2;
-        ey *= inv_cs2;
-        ez *= inv_cs2;
-        const C av = sqrt(ex * ex + ey * ey + ez * ez);
-        const C m = C(4) * C(P.beta) * ph * (ph - C(1)) * (ph - C(0.5)) - C(P.kappa) * lap -
-                    av * wet_of<L::D, C>(w, P) * (ph - ph * ph);
-        C gx, gy, gz;
-        grad_of<L, C>([&](int i) { return sphi[at(i)]; }, gx, gy, gz);
-        node_update<L, S, 0, O>(f, g0, g, ph, m, gx, gy, gz, w, n, fdst, gdst, sprev, nullptr,
-                             nullptr, G, P, P.nt_store);
-      }
+    for (int i = 1; i < Q; ++i) {
+      f[i] = pull<L, FS>(fsrc, i, n, nb, w, P.scale_f);
+      if (i < L::G::Q) g[i] = pull<typename L::G, GS>(gsrc, i, n, nb, w, P.scale_g);
     }
-    __syncthreads();
+    // neighbour entry for lattice direction i
+    auto at = [&](int i) {
+      const int sl = L::cz(i) < 0 ? sm : (L::cz(i) > 0 ? sp : s0);
+      return sl + t + L::cx(i) + LX * L::cy(i);
+    };
+    // mu (same arithmetic as mu_at) and grad phi
+    const C ph = sphi[s0 + t];
+    C lap = C(0), ex = C(0), ey = C(0), ez = C(0);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int t2 = at(i);
+      const C wi = C(L::w(i));
+      lap += C(2) * wi * (sphi[t2] - ph);
+      const C e = (sw[t2] & kFluid) ? C(1) : C(0);
+      ex += wi * C(L::cx(i)) * e;
+      ey += wi * C(L::cy(i)) * e;
+      ez += wi * C(L::cz(i)) * e;
+    }
+    const C inv_cs2 = C(3);
+    lap *= inv_cs2;
+    ex *= inv_cs2;
+    ey *= inv_cs2;
+    ez *= inv_cs2;
+    const C av = sqrt(ex * ex + ey * ey + ez * ez);
+    const C m = C(4) * C(P.beta) * ph * (ph - C(1)) * (ph - C(0.5)) - C(P.kappa) * lap -
+                av * wet_of<L::D, C>(w, P) * (ph - ph * ph);
+    C gx, gy, gz;
+    grad_of<L, C>([&](int i) { return sphi[at(i)]; }, gx, gy, gz);
+    node_update<L, S, 0, O>(f, g0, g, ph, m, gx, gy, gz, w, n, fdst, gdst, sprev, nullptr,
+                         nullptr, G, P, P.nt_store);
   }
 }
 
@@ -1459,11 +1595,12 @@ __global__ __launch_bounds__(64 * TY, 4) void k_stepZ(
   using T = MarchTile<TY>;
   __shared__ ComputeT<S> sphi[T::NL_PHI];
   __shared__ uint32_t sw[T::NL_WORD];
-  const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY;
-  const int b = TileOrder{nbx, nby, (G.PZ + TZ - 1) / TZ, P.xcd_order}.tile(blockIdx.x);
+  const TileGrid TG(G, 64, TY, TZ);
+  const int b = TileOrder{TG.nx, TG.ny, TG.nz, P.xcd_order}.tile(blockIdx.x);
   if (b < 0) return;
-  stepZ_tile<L, S, TY, TZ, O>((b % nbx) * 64, ((b / nbx) % nby) * TY, (b / (nbx * nby)) * TZ,
-                              nodes, fsrc, gsrc, fdst, gdst, sprev, G, P, sphi, sw);
+  int x0, y0, z0;
+  TG.origin(b, x0, y0, z0);
+  stepZ_tile<L, S, TY, TZ, O>(x0, y0, z0, nodes, fsrc, gsrc, fdst, gdst, sprev, G, P, sphi, sw);
 }
 
 template <class L, int S, int TY, int TZ, bool O>
@@ -1474,11 +1611,12 @@ __global__ __launch_bounds__(64 * TY, 5) void k_stepC(
   using T = ColumnTile<L, S, TY, TZ>;
   __shared__ ComputeT<S> sphi[T::NL];
   __shared__ uint32_t sw[T::NL];
-  const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY;
-  const int b = TileOrder{nbx, nby, (G.PZ + TZ - 1) / TZ, P.xcd_order}.tile(blockIdx.x);
+  const TileGrid TG(G, 64, TY, TZ);
+  const int b = TileOrder{TG.nx, TG.ny, TG.nz, P.xcd_order}.tile(blockIdx.x);
   if (b < 0) return;
-  stepC_tile<L, S, TY, TZ, O>((b % nbx) * 64, ((b / nbx) % nby) * TY, (b / (nbx * nby)) * TZ, nodes,
-                           fsrc, gsrc, fdst, gdst, sprev, phi, G, P, sphi, sw);
+  int x0, y0, z0;
+  TG.origin(b, x0, y0, z0);
+  stepC_tile<L, S, TY, TZ, O>(x0, y0, z0, nodes, fsrc, gsrc, fdst, gdst, sprev, phi, G, P, sphi, sw);
 }
 
 // ------------------------------------------------------------------ batched step
@@ -1538,10 +1676,9 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_step_group(
     const CaseDesc& cd = cases[te.case_id];
     const Geo G = cd.G;
     const int c = cd.cur0 ^ parity;
-    const int nbx = (G.PX + T::TX - 1) / T::TX, nby = (G.PY + T::TY - 1) / T::TY;
-    const int b = te.tile;
-    step_tile<L, S, BY, BZ, KY, KZ, true>((b % nbx) * T::TX, ((b / nbx) % nby) * T::TY,
-                                    (b / (nbx * nby)) * T::TZ, cd.nodes, cd.f[c], cd.g[c],
+    int x0, y0, z0;
+    TileGrid(G, T::TX, T::TY, T::TZ).origin(te.tile, x0, y0, z0);
+    step_tile<L, S, BY, BZ, KY, KZ, true>(x0, y0, z0, cd.nodes, cd.f[c], cd.g[c],
                                     cd.f[1 - c], cd.g[1 - c], static_cast<ComputeT<S>*>(cd.s), G,
                                     cd.P, sphi, sw);
     __syncthreads();   // the next tile reuses the LDS arrays
@@ -1560,10 +1697,9 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_phi_group(
     const CaseDesc& cd = cases[te.case_id];
     const Geo G = cd.G;
     const int c = cd.cur0 ^ parity;
-    const int nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY;
-    const int b = te.tile;
-    phi_tile<L, S, BY, BZ, true>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ,
-                           cd.nodes, cd.g[c], static_cast<ComputeT<S>*>(cd.phi), G, cd.P);
+    int x0, y0, z0;
+    TileGrid(G, 64, BY, TZ).origin(te.tile, x0, y0, z0);
+    phi_tile<L, S, BY, BZ, true>(x0, y0, z0, cd.nodes, cd.g[c], static_cast<ComputeT<S>*>(cd.phi), G, cd.P);
   });
 }
 
@@ -1572,7 +1708,7 @@ __global__ __launch_bounds__(64 * BY * BZ, 7) void k_stepB_group(
     const TileEntry* __restrict__ table, const int* __restrict__ ntiles,
     const CaseDesc* __restrict__ cases, int parity) {
   constexpr bool D3 = (L::D == 3);
-  constexpr int NL = 68 * (BY + 4) * (D3 ? BZ + 4 : 1);
+  constexpr int NL = 66 * (BY + 2) * (D3 ? BZ + 2 : 1);
   __shared__ ComputeT<S> sphi[NL];
   __shared__ uint32_t sw[NL];
   const int TZ = D3 ? BZ : 1;
@@ -1581,10 +1717,9 @@ __global__ __launch_bounds__(64 * BY * BZ, 7) void k_stepB_group(
     const CaseDesc& cd = cases[te.case_id];
     const Geo G = cd.G;
     const int c = cd.cur0 ^ parity;
-    const int nbx = (G.PX + 63) / 64, nby = (G.PY + BY - 1) / BY;
-    const int b = te.tile;
-    stepB_tile<L, S, BY, BZ, true>((b % nbx) * 64, ((b / nbx) % nby) * BY, (b / (nbx * nby)) * TZ,
-                             cd.nodes, cd.f[c], cd.g[c], cd.f[1 - c], cd.g[1 - c],
+    int x0, y0, z0;
+    TileGrid(G, 64, BY, TZ).origin(te.tile, x0, y0, z0);
+    stepB_tile<L, S, BY, BZ, true>(x0, y0, z0, cd.nodes, cd.f[c], cd.g[c], cd.f[1 - c], cd.g[1 - c],
                              static_cast<ComputeT<S>*>(cd.s),
                              static_cast<const ComputeT<S>*>(cd.phi), G, cd.P, sphi, sw);
     __syncthreads();
@@ -1603,10 +1738,9 @@ __global__ __launch_bounds__(64 * TY, 5) void k_stepC_group(
     const CaseDesc& cd = cases[te.case_id];
     const Geo G = cd.G;
     const int c = cd.cur0 ^ parity;
-    const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY;
-    const int b = te.tile;
-    stepC_tile<L, S, TY, TZ, true>((b % nbx) * 64, ((b / nbx) % nby) * TY, (b / (nbx * nby)) * TZ,
-                             cd.nodes, cd.f[c], cd.g[c], cd.f[1 - c], cd.g[1 - c],
+    int x0, y0, z0;
+    TileGrid(G, 64, TY, TZ).origin(te.tile, x0, y0, z0);
+    stepC_tile<L, S, TY, TZ, true>(x0, y0, z0, cd.nodes, cd.f[c], cd.g[c], cd.f[1 - c], cd.g[1 - c],
                              static_cast<ComputeT<S>*>(cd.s),
                              static_cast<const ComputeT<S>*>(cd.phi), G, cd.P, sphi, sw);
     __syncthreads();
@@ -1626,13 +1760,31 @@ __global__ __launch_bounds__(64 * TY, 4) void k_stepZ_group(
     const CaseDesc& cd = cases[te.case_id];
     const Geo G = cd.G;
     const int c = cd.cur0 ^ parity;
-    const int nbx = (G.PX + 63) / 64, nby = (G.PY + TY - 1) / TY;
-    const int b = te.tile;
-    stepZ_tile<L, S, TY, TZ, true>((b % nbx) * 64, ((b / nbx) % nby) * TY, (b / (nbx * nby)) * TZ,
-                                   cd.nodes, cd.f[c], cd.g[c], cd.f[1 - c], cd.g[1 - c],
+    int x0, y0, z0;
+    TileGrid(G, 64, TY, TZ).origin(te.tile, x0, y0, z0);
+    stepZ_tile<L, S, TY, TZ, true>(x0, y0, z0, cd.nodes, cd.f[c], cd.g[c], cd.f[1 - c], cd.g[1 - c],
                                    static_cast<ComputeT<S>*>(cd.s), G, cd.P, sphi, sw);
     __syncthreads();
   });
+}
+
+// Batched ghost pass: one table entry's tile box (ghost_box) at a time.
+template <class L, int S>
+__global__ __launch_bounds__(kGhostThreads) void k_ghost_group(const TileEntry* __restrict__ table,
+                                                                const int* __restrict__ ntiles,
+                                                                const CaseDesc* __restrict__ cases,
+                                                                int tx, int ty, int tz) {
+  using C = ComputeT<S>;
+  __shared__ int list[kGhostChunk];
+  __shared__ int count;
+  const int n = *ntiles;
+  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+    const TileEntry te = table[e];
+    const CaseDesc& cd = cases[te.case_id];
+    const Geo G = cd.G;
+    ghost_box<L, C>(cd.nodes, static_cast<C*>(cd.phi), G, C(cd.P.chi_a), TileGrid(G, tx, ty, tz),
+                    te.tile, list, &count);
+  }
 }
 
 // ------------------------------------------------------------------ init
@@ -1902,9 +2054,8 @@ __global__ __launch_bounds__(256) void k_phi_group_all(const TileEntry* __restri
     const Geo G = cd.G;
     const void* gsrc = cd.g[cd.cur0 ^ parity];
     C* phi = static_cast<C*>(cd.phi);
-    const int nbx = (G.PX + tx - 1) / tx, nby = (G.PY + ty - 1) / ty;
-    const int b = te.tile;
-    const int x0 = (b % nbx) * tx, y0 = ((b / nbx) % nby) * ty, z0 = (b / (nbx * nby)) * tz;
+    int x0, y0, z0;
+    TileGrid(G, tx, ty, tz).origin(te.tile, x0, y0, z0);
     for (int m = tid; m < tx * ty * tz; m += 256) {
       const int x = x0 + m % tx, y = y0 + (m / tx) % ty, z = z0 + m / (tx * ty);
       if (x >= G.PX || y >= G.PY || z >= G.PZ) continue;
@@ -1934,9 +2085,8 @@ __global__ __launch_bounds__(256) void k_reduce_group(const TileEntry* __restric
     const TileEntry te = table[e];
     const CaseDesc& cd = cases[te.case_id];
     const Geo G = cd.G;
-    const int nbx = (G.PX + tx - 1) / tx, nby = (G.PY + ty - 1) / ty;
-    const int b = te.tile;
-    const int x0 = (b % nbx) * tx, y0 = ((b / nbx) % nby) * ty, z0 = (b / (nbx * nby)) * tz;
+    int x0, y0, z0;
+    TileGrid(G, tx, ty, tz).origin(te.tile, x0, y0, z0);
     double acc[kRecN];
 #pragma unroll
     for (int k = 0; k < kRecN; ++k) acc[k] = 0.0;

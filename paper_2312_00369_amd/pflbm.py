@@ -87,6 +87,7 @@ def _load():
         "pflbm_footprint": (ct.c_int, [P(pflbm_params), P(sz)]),
         "pflbm_classify": (ct.c_int, [P(pflbm_params), vp, vp]),
         "pflbm_lattice_table": (ct.c_int, [i32, vp, vp, vp, vp]),
+        "pflbm_beta_kappa": (ct.c_int, [ct.c_double, ct.c_double, P(ct.c_double), P(ct.c_double)]),
         "pflbm_create": (ct.c_int, [P(pflbm_params), vp, vp, vp, P(vp)]),
         "pflbm_create_in": (ct.c_int, [P(pflbm_params), vp, vp, vp, vp, sz, P(vp)]),
         "pflbm_step": (ct.c_int, [vp, i64]),
@@ -140,8 +141,12 @@ def _ptr(a):
 
 
 def beta_kappa(sigma, width):
-    """beta = 12 sigma / W, kappa = 3 sigma W / 2 (double-well profile and Young's law)."""
-    return 12.0 * sigma / width, 1.5 * sigma * width
+    """Free-energy coefficients for surface tension and interface width, from the
+    library (pflbm_beta_kappa)."""
+    b, k = ct.c_double(), ct.c_double()
+    _check(lib.pflbm_beta_kappa(float(sigma), float(width), ct.byref(b), ct.byref(k)),
+           "pflbm_beta_kappa")
+    return b.value, k.value
 
 
 def make_params(lattice, shape, periodic, theta_deg, beta, kappa, storage="f32", tau=0.8,

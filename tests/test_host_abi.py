@@ -308,3 +308,20 @@ def test_sec32_incline_3d_geometry(P):
         n_ = c["wall"]["normal"]
         assert abs(math.hypot(*n_) - 1) < 1e-12 and abs(-n_[0] / n_[2] - slope) < 1e-12
         assert P.classify(P.params_from_case(c, "f32"), m).any()
+
+
+def test_beta_kappa_from_the_library(P):
+    """pflbm_beta_kappa: the planar profile width sqrt(8 kappa/beta) and the
+    tension sqrt(2 kappa beta)/6 come back as W and sigma, the values equal the
+    oracle's, and non-positive or non-finite inputs are refused."""
+    from oracle.model import beta_kappa as oracle_bk
+    for sigma, W in ((1e-3, 4.0), (1e-3, 5.0), (5e-2, 3.0), (1e-2, 8.0)):
+        b, k = P.beta_kappa(sigma, W)
+        assert np.sqrt(8.0 * k / b) == pytest.approx(W, rel=1e-14)
+        assert np.sqrt(2.0 * k * b) / 6.0 == pytest.approx(sigma, rel=1e-14)
+        assert (b, k) == oracle_bk(sigma, W)
+    for sigma, W in ((0.0, 4.0), (1e-3, -1.0), (float("nan"), 4.0), (1e-3, float("inf"))):
+        with pytest.raises(P.PflbmError) as e:
+            P.beta_kappa(sigma, W)
+        assert e.value.code == -1
+    assert P.lib.pflbm_beta_kappa(1e-3, 4.0, None, None) == -1

@@ -68,8 +68,9 @@ def test_group_poll_static_refusals(P):
     g.step(2)
     g.poll(static=True)
     g.remove(m)
-    # more table entries than the static scratch holds (64 x 8 tiles of a 4096 x 4096 case)
-    big = workloads.flat_droplet_case(4096, 4096, 100.0, 70.0, 4.0)
+    # more table entries than the static scratch holds (32768): a 4096 x 4160 case
+    # has 64 x 520 tiles of 64 x 8 nodes
+    big = workloads.flat_droplet_case(4096, 4160, 100.0, 70.0, 4.0)
     mb = P.Case.from_case(big, "f32")
     g.add(mb)
     g.step(2)
