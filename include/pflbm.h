@@ -189,8 +189,9 @@ int pflbm_set_step_kernel(pflbm_handle h, int32_t variant);
  * XCDs round-robin); 1 = each XCD takes one contiguous run of tiles; 2 = whole
  * x-rows of tiles, two tile rows in y at a time, go to one XCD together, so
  * that neighbouring tiles share its L2.  Other values: EINVAL.
- * nontemporal != 0 writes f* and g* with streaming stores.  Both default 0.
- * Drops any captured graph. */
+ * nontemporal != 0 writes f* and g* with streaming stores.  Defaults:
+ * xcd_order 2 for D3Q19 cases, 0 for D2Q9; nontemporal 0.  Drops any captured
+ * graph. */
 int pflbm_set_step_options(pflbm_handle h, int32_t xcd_order, int32_t nontemporal);
 
 /* Number of step variants for a lattice (see pflbm_set_step_kernel); if tiles

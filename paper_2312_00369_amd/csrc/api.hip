@@ -110,7 +110,9 @@ int validate_and_derive(const pflbm_params* p, Derived* d) {
   ph.nu_l = p->nu_l;
   ph.nu_g = p->nu_g;
   ph.visc_var = var ? 1 : 0;
-  ph.xcd_order = 0;
+  // 3D step kernels: tile rows dealt to the XCDs in chunks (TileOrder mode 2),
+  // which lets neighbouring tiles share an L2; 2D: round-robin
+  ph.xcd_order = D == 3 ? 2 : 0;
   ph.nt_store = 0;
   for (int a = 0; a < 3; ++a) ph.Fb[a] = (a < D) ? p->body_force[a] : 0.0;
   // FP16 codec scales (powers of two): stored magnitudes of about 2^13 for the
@@ -491,14 +493,22 @@ int create_common(const pflbm_params* prm, const uint8_t* mask, const double* ph
   std::vector<uint32_t> words;
   h->classes.assign((size_t)prm->nx * prm->ny * prm->nz, 0);
   classify_nodes(dv, mask, words, h->classes.data());
-  // blocks of 64 slots that hold a ghost node: the split step's ghost pass
-  // visits these only
+  // blocks of 64 slots that hold a ghost node off the padding faces of a
+  // walled x axis: the split step's ghost pass visits these, and the faces
+  // (all of whose ghost nodes it visits directly)
   std::vector<uint32_t> gblocks;
-  for (size_t b = 0; b * kBlk < words.size(); ++b) {
-    bool any = false;
-    for (size_t j = b * kBlk; j < std::min(words.size(), (b + 1) * kBlk); ++j)
-      any = any || (words[j] & kGhost) != 0;
-    if (any) gblocks.push_back((uint32_t)b);
+  {
+    const Geo& G = dv.geo;
+    for (size_t b = 0; b * kBlk < words.size(); ++b) {
+      bool any = false;
+      for (size_t j = b * kBlk; j < std::min(words.size(), (b + 1) * kBlk); ++j) {
+        if (!(words[j] & kGhost)) continue;
+        h->nghost += 1;
+        const long long x = ((long long)j - G.XO) % G.SX;
+        any = any || G.per[0] || (x != 0 && x != G.PX - 1);
+      }
+      if (any) gblocks.push_back((uint32_t)b);
+    }
   }
   h->nghost_blocks = (long long)gblocks.size();
   if (dv.phys.chi_a != 0.0 && (rc = check_axis_ghosts(dv, words))) return fail(rc);

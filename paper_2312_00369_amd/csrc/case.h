@@ -74,8 +74,9 @@ struct pflbm_case_s {
   double* rec = nullptr;
   float* popmax = nullptr;        // kPopmaxBlocks (f, g) pairs
   std::vector<uint8_t> classes;   // host copy of the domain classes
-  uint32_t* gblocks = nullptr;    // population blocks (64 slots) holding a ghost node, ascending
-  long long nghost_blocks = 0;    // their number (the split step's ghost pass is skipped at 0)
+  long long nghost = 0;           // ghost nodes (the split step's ghost pass is skipped at 0)
+  uint32_t* gblocks = nullptr;    // population blocks (64 slots) holding a ghost node off the
+  long long nghost_blocks = 0;    // padding faces of a walled x axis, ascending; their number
   int cur = 0;                    // buffer holding the current post-collision state
   int64_t step = 0;
   bool snap_valid = false;

@@ -34,11 +34,14 @@ struct Engine {
 
   // ghost phi into the phi array (split step, after phi)
   static int ghost(pflbm_case_s* h) {
-    if (!h->nghost_blocks) return PFLBM_OK;
+    if (!h->nghost) return PFLBM_OK;
+    const Geo& G = h->dv.geo;
     const long long nb = h->nghost_blocks;
-    const unsigned grid = (unsigned)std::min<long long>((nb + 7) / 8, 2048);
-    hipLaunchKernelGGL((k_ghost<L, C>), dim3(grid), dim3(kGhostThreads), 0, h->stream, h->nodes,
-                       static_cast<C*>(h->phi), h->gblocks, (int)nb, h->dv.geo, h->dv.phys);
+    const int face_wg = G.per[0] ? 0 : (2 * G.PY * G.PZ + kGhostThreads - 1) / kGhostThreads;
+    const int list_wg = (int)std::min<long long>((nb + 7) / 8, 2048);
+    hipLaunchKernelGGL((k_ghost<L, C>), dim3(face_wg + list_wg), dim3(kGhostThreads), 0,
+                       h->stream, h->nodes, static_cast<C*>(h->phi), h->gblocks, (int)nb, face_wg,
+                       G, h->dv.phys);
     PFLBM_HIP(hipGetLastError());
     return PFLBM_OK;
   }

@@ -976,19 +976,34 @@ __device__ inline void ghost_box(const uint32_t* __restrict__ nodes, C* __restri
   }
 }
 
-// Single case: one wavefront per listed population block (64 slots that hold
-// at least one ghost node; the list is built with the node classes), each lane
-// one slot.  Wavefronts stride over the list, two blocks at a time so that the
-// node-word loads of both are in flight together.
+// Single case, two kinds of workgroup in one launch.  The first nface_wg take
+// the padding faces of a walled x axis, one face node per lane (2 per row,
+// lanes over consecutive rows); each such face node sits alone in its
+// population block.  The others take the listed population blocks (64 slots
+// holding a ghost off those faces; the list is built with the node classes),
+// one wavefront per block, each lane one slot, wavefronts striding over the
+// list two blocks at a time so that the node-word loads of both are in flight
+// together.
 template <class L, class C>
 __global__ __launch_bounds__(kGhostThreads) void k_ghost(const uint32_t* __restrict__ nodes,
                                                           C* __restrict__ phi,
                                                           const uint32_t* __restrict__ blocks,
-                                                          int nblocks, Geo G, Phys P) {
-  const int lane = threadIdx.x % 64;
-  const int nw = gridDim.x * (kGhostThreads / 64);
+                                                          int nblocks, int nface_wg, Geo G,
+                                                          Phys P) {
   const C chi_a = C(P.chi_a);
-  for (int e = blockIdx.x * (kGhostThreads / 64) + threadIdx.x / 64; e < nblocks; e += 2 * nw) {
+  if ((int)blockIdx.x < nface_wg) {
+    const int i = blockIdx.x * kGhostThreads + threadIdx.x;
+    const int row = i >> 1;
+    if (row >= G.PY * G.PZ) return;
+    const int x = (i & 1) ? G.PX - 1 : 0, y = row % G.PY, z = row / G.PY;
+    const nidx n = G.idx(x, y, z);
+    if (nodes[n] & kGhost) phi[n] = ghost_from<L, C>(nodes, phi, G, x, y, z, chi_a);
+    return;
+  }
+  const int lane = threadIdx.x % 64;
+  const int nw = (gridDim.x - nface_wg) * (kGhostThreads / 64);
+  const int w0 = (blockIdx.x - nface_wg) * (kGhostThreads / 64) + threadIdx.x / 64;
+  for (int e = w0; e < nblocks; e += 2 * nw) {
     uint32_t slot[2], w[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -1002,6 +1017,7 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(const uint32_t* __restr
       // (x, y, z) of the slot: slot = x + XO + SX (y + PY z)
       const int r = (int)slot[k] - G.XO;
       const int x = r % G.SX, row = r / G.SX;
+      if (nface_wg > 0 && (x == 0 || x == G.PX - 1)) continue;   // the face phase's
       const int y = row % G.PY, z = row / G.PY;
       phi[slot[k]] = ghost_from<L, C>(nodes, phi, G, x, y, z, chi_a);
     }
