@@ -851,18 +851,38 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
     }
     sphi[t] = ph;
   }
-  // 4. second halo layer, only where ghost means need it
+  // 4. second halo layer, only where ghost means need it: the ghost means of
+  // step 5 read a second-layer entry only from the 3^D block of a ghost of
+  // the tile or the first layer, so the other entries are left out (a flat
+  // wall needs a few entries at the tile's x ends, not a row of phi from g)
   if (need2) {
     for (int m = tid; m < NL; m += NT) {
       const int lx = m % LX, ly = (m / LX) % LY, lz = m / (LX * LY);
       const bool ring2 = lx == 0 || lx == LX - 1 || ly == 0 || ly == LY - 1 ||
                          (D3 && (lz == 0 || lz == LZ - 1));
       if (!ring2) continue;
-      int q[3];
-      const long long n = gnode(lx, ly, lz, q);
-      const uint32_t w = n >= 0 ? nodes[n] : 0u;
+      bool near = false;
+#pragma unroll
+      for (int dz = (D3 ? -1 : 0); dz <= (D3 ? 1 : 0); ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int ax = lx + dx, ay = ly + dy, az = lz + dz;
+            if (ax < 1 || ax > LX - 2 || ay < 1 || ay > LY - 2 || (D3 && (az < 1 || az > LZ - 2)))
+              continue;
+            near = near || (sw[ax + SX * ay + SXY * az] & kGhost) != 0;
+          }
+      uint32_t w = 0u;
+      C v = C(0);
+      if (near) {
+        int q[3];
+        const long long n = gnode(lx, ly, lz, q);
+        w = n >= 0 ? nodes[n] : 0u;
+        if (w & kZeta) v = phi_of(n, w, q);
+      }
       sw[m] = w;
-      sphi[m] = (w & kZeta) ? phi_of(n, w, q) : C(0);
+      sphi[m] = v;
     }
   }
   __syncthreads();
