@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--steps-3d", type=int, default=400)
     ap.add_argument("--err-steps-3d", type=int, default=2000)
     ap.add_argument("--chunk-3d", type=int, default=20)
-    ap.add_argument("--variant-3d", default="7,8",
+    ap.add_argument("--variant-3d", default="7,7",
                     help="step variants (FP32,FP16-dev) for the 256^3 D3Q19 workload")
     ap.add_argument("--variant-d3q7", default="7,8",
                     help="step variants (FP32,FP16-dev) for the 3D workload with D3Q7 for g")
