@@ -75,6 +75,8 @@ def parse():
                     default=[60.0, 90.0, 120.0, 140.0])
     ap.add_argument("--table1-3d-max-steps", type=int, default=1200000)
     ap.add_argument("--table1-3d-phase", default="", help="'' (D3Q19 for g) or D3Q7")
+    ap.add_argument("--table1-3d-start", default="centred",
+                    help="centred (the paper's start) or cap (the drop meets the plate at theta)")
     ap.add_argument("--incline3d-n", type=int, default=128)
     ap.add_argument("--incline3d-angles", type=lambda v: [float(x) for x in v.split(",")],
                     default=[60.0, 120.0])
@@ -88,6 +90,10 @@ def parse():
                     help="step cap of the incline2d / cylinder2d sections")
     ap.add_argument("--appendix-a-marks", type=lambda v: [int(x) for x in v.split(",")],
                     default=[100000, 300000, 1000000, 3000000, 6000000])
+    ap.add_argument("--theta0-max-steps", type=int, default=4000000,
+                    help="step cap of the thetacheck section for configs[0]")
+    ap.add_argument("--theta1-max-steps", type=int, default=1000000,
+                    help="step cap of the thetacheck section for configs[1]")
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--batch-start", default="cap", help="drop (90 deg) or cap (meets the wall at theta)")
     ap.add_argument("--batch-tol", type=float, default=1e-3)
@@ -432,6 +438,71 @@ def _angle_sweep(torch, P, cases, max_steps, chunk=100000, label="sweep"):
                 fits=[(d["centre"], d["radius"]) for d in last])
 
 
+def theta_check(a, torch, P, workloads):
+    """configs[0] (128x64 FP64, theta 60) and configs[1] (1024x512 FP32, theta
+    30..150) against their prescribed contact angles, each case started two
+    ways: as specified (a circle centred on the wall plane, i.e. at 90 deg) and
+    as the cap of the same radius that meets the wall at theta.  Each set runs
+    as one group until every angle moved less than 0.02 deg over the last two
+    polls (100k steps apart) or the step cap; theta is reported at the
+    specified step count (5000 and 50k) and along the way."""
+    out = {}
+    sets = (("configs0", "f64", [(128, 64, 20.0, 60.0, 4.0)], 5000, a.theta0_max_steps),
+            ("configs1", "f32", [(1024, 512, 80.0, th, 5.0) for th in (30.0, 60.0, 90.0, 120.0, 150.0)],
+             50000, a.theta1_max_steps))
+    for name, st, specs, at, cap in sets:
+        cases, labels = [], []
+        for nx, ny, R, th, W in specs:
+            for start in ("centred", "cap"):
+                c = (workloads.flat_droplet_case(nx, ny, R, th, W) if start == "centred"
+                     else workloads.flat_cap_case(nx, ny, R, th, W))
+                cases.append(c)
+                labels.append((th, start))
+        g = P.Group()
+        ms = [P.Case.from_case(c, st) for c in cases]
+        mass0 = [m.diagnostics()["mass"] for m in ms]
+        for m in ms:
+            g.add(m)
+        g.set_graph_chunk(1000)
+        hist, marks, steps, t0, t_said = [], {}, 0, time.perf_counter(), time.perf_counter()
+        for k in (at, 100000 - at):
+            g.step(k)
+            steps += k
+            diags, _ = g.poll()
+            marks[str(steps)] = [round(d["theta_deg"], 3) for d in diags]
+        while steps < cap:
+            g.step(100000)
+            steps += 100000
+            diags, _ = g.poll()
+            hist.append([d["theta_deg"] for d in diags])
+            if steps in (200000, 500000, 1000000, 2000000, 4000000):
+                marks[str(steps)] = [round(t, 3) for t in hist[-1]]
+            if len(hist) >= 3 and all(abs(x - y) < 0.02 for x, y in zip(hist[-1], hist[-3])):
+                break
+            if time.perf_counter() - t_said > 30.0:
+                progress(f"thetacheck {name}: {steps} steps")
+                t_said = time.perf_counter()
+        torch.cuda.synchronize()
+        final = [d for d in g.poll()[0]]
+        marks[str(steps)] = [round(d["theta_deg"], 3) for d in final]
+        rows = []
+        for (th, start), d, m0 in zip(labels, final, mass0):
+            rows.append({"prescribed": th, "start": start,
+                         f"theta_at_{at}": marks[str(at)][len(rows)],
+                         "theta_final": round(d["theta_deg"], 3),
+                         "error_final": round(d["theta_deg"] - th, 3),
+                         "rel_mass_change": abs(d["mass"] - m0) / m0})
+        for m in ms:
+            g.remove(m)
+            m.close()
+        g.close()
+        out[name] = {"storage": st, "steps": steps, "wall_s": round(time.perf_counter() - t0, 1),
+                     "converged": steps < cap, "angles": rows, "theta_history": marks}
+    out["workload"] = ("configs[0]: 128x64 D2Q9 FP64, R = 20, theta 60, W = 4; configs[1]: 1024x512 "
+                       "D2Q9 FP32, R = 80, theta 30..150, W = 5; sigma 1e-3, M 0.1, rho 10/1, tau 0.8")
+    return out
+
+
 def incline_2d(a, torch, P, workloads):
     """Sec. 3.2 in 2D: drops on the staircase incline y = slope x (slopes 1, 0.5,
     0.25; theta 30..150; W = 4), plus W = 6 and 8 at slope 0.25 for theta = 90
@@ -473,7 +544,7 @@ def table1_3d(a, torch, P, workloads):
     n = tuple(int(v) for v in a.table1_3d_shape.split("x"))
     paper = _json.load(open(os.path.join(ROOT, "tests", "golden", "table1_2d_paper.json")))
     p3 = dict(zip(paper["prescribed_deg"], paper.get("paper_3d_deg", [None] * 11)))
-    cs = [workloads.table1_case_3d(th, n) for th in a.table1_3d_angles]
+    cs = [workloads.table1_case_3d(th, n, start=a.table1_3d_start) for th in a.table1_3d_angles]
     if a.table1_3d_phase:
         for c in cs:
             c["phase_lattice"] = a.table1_3d_phase
@@ -484,7 +555,8 @@ def table1_3d(a, torch, P, workloads):
             for th, t in zip(a.table1_3d_angles, r.pop("final"))]
     lat = "D3Q19/" + a.table1_3d_phase if a.table1_3d_phase else "D3Q19"
     return dict(workload=f"Sec. 3.1 plate in 3D at {n[0]}x{n[1]}x{n[2]}, {lat} FP32, "
-                         f"R = {cs[0]['radius']}, sigma 0.005, M 0.01, W 4", angles=rows, **r)
+                         f"R = {cs[0]['radius']}, sigma 0.005, M 0.01, W 4, start {a.table1_3d_start}",
+                angles=rows, **r)
 
 
 def incline_3d(a, torch, P, workloads):
@@ -694,6 +766,10 @@ def main():
     if "serve" in a.sec:
         with torch.cuda.stream(stream):
             line["served"] = served(a, torch, P, workloads)
+    if "thetacheck" in a.sec:
+        with torch.cuda.stream(stream):
+            line["theta_check"] = theta_check(a, torch, P, workloads)
+        progress("thetacheck done")
     if "table1" in a.sec:
         with torch.cuda.stream(stream):
             line["table1_2d"] = table1(a, torch, P, workloads)

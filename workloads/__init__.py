@@ -98,6 +98,16 @@ def flat_droplet_case(nx=128, ny=64, radius=20.0, theta=60.0, width=4.0,
     return _case(lattice, shape, (True, False), mask, phi0, theta, sigma, width, wall)
 
 
+def flat_cap_case(nx=128, ny=64, radius=20.0, theta=60.0, width=4.0, sigma=1e-3):
+    """As flat_droplet_case, but the circle of `radius` is placed so that it
+    meets the wall plane y = -0.5 at theta (the equilibrium shape up to the
+    interface profile) instead of being centred on it."""
+    c = flat_droplet_case(nx, ny, radius, theta, width, sigma)
+    centre = _cap_centre(c["wall"], (nx / 2.0, -0.5), radius, theta)
+    c["phi0"] = np.ascontiguousarray(droplet((nx, ny), centre, radius, width), dtype=np.float64)
+    return c
+
+
 def flat_128x64_fp64():
     """128 x 64 D2Q9, FP64, R = 20, theta = 60 deg, W = 4, sigma = 1e-3, 5000 steps."""
     c = flat_droplet_case(128, 64, 20.0, 60.0, 4.0)
@@ -148,19 +158,24 @@ def cylinder_case(nx, ny, rc_frac, theta, width=4.0, sigma=1e-3, drop_frac=0.3):
                  storage="f32", name=f"cyl-{nx}x{ny}")
 
 
-def table1_case_3d(theta, n=(256, 256, 128)):
+def table1_case_3d(theta, n=(256, 256, 128), start="centred"):
     """The 3D flat-plate test of Sec. 3.1: Nx x Ny x Nz, periodic on every side,
     D3Q19 FP32; the plate as in 2D (0.25 Nz thick, 0.05 Nz above the bottom) and
     a drop of R = 50 (scaled with Nz / 128) centred at (Nx/2, Ny/2, 0.25 Nz), the
     centre the paper prints; rows below the plate's top row start dry.  The wall
-    plane of the angle fit is half a node below the plate's top row."""
+    plane of the angle fit is half a node below the plate's top row.
+    start="cap": the sphere of the same R placed so that it meets that plane at
+    theta (the equilibrium shape up to the interface profile)."""
     nx, ny, nz = n
     z_lo, thick = round(0.05 * nz), round(0.25 * nz)
     mask = np.zeros((nz, ny, nx), dtype=np.uint8)
     mask[z_lo:z_lo + thick] = 1
     z_wall = z_lo + thick - 1.5
     R = {10.0: 30.0, 20.0: 40.0}.get(float(theta), 50.0) * nz / 128.0
-    phi0 = droplet(n, (nx / 2.0, ny / 2.0, 0.25 * nz), R, 4.0)
+    centre = (nx / 2.0, ny / 2.0, 0.25 * nz)
+    if start == "cap":
+        centre = (nx / 2.0, ny / 2.0, z_wall - R * math.cos(math.radians(theta)))
+    phi0 = droplet(n, centre, R, 4.0)
     phi0[:z_lo + thick - 1] = 0.0
     wall = dict(kind="plane", point=(0.0, 0.0, z_wall), normal=(0.0, 0.0, 1.0))
     c = _case("D3Q19", n, (True, True, True), mask, phi0, theta, 0.005, 4.0, wall)
