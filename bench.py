@@ -94,6 +94,13 @@ def parse():
                     help="step cap of the thetacheck section for configs[0]")
     ap.add_argument("--theta1-max-steps", type=int, default=1000000,
                     help="step cap of the thetacheck section for configs[1]")
+    ap.add_argument("--incline3d-slopes", default="1,0.5,0.25")
+    ap.add_argument("--incline3d-start", default="paper", help="paper or cap")
+    ap.add_argument("--sphere-start", default="paper", help="paper or cap")
+    ap.add_argument("--sphere-phase", default="", help="'' (D3Q19 for g) or D3Q7")
+    ap.add_argument("--cylinder-starts", default="paper",
+                    help="cylinder2d starts: paper (the drop overlapping the cylinder's top), "
+                         "cap (the drop meeting the wall circle at theta), or both")
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--batch-start", default="cap", help="drop (90 deg) or cap (meets the wall at theta)")
     ap.add_argument("--batch-tol", type=float, default=1e-3)
@@ -522,17 +529,19 @@ def cylinder_2d(a, torch, P, workloads):
     """Sec. 3.3 in 2D: drops on a cylinder of R_s = 60 (W = 6), theta 30..150,
     as one group; theta from the circle fit against the wall circle."""
     import math
-    cs = [workloads.sec33_cylinder_case(th) for th in workloads.SEC3_ANGLES]
+    starts = [s_.strip() for s_ in a.cylinder_starts.split(",")]
+    combos = [(st_, th) for st_ in starts for th in workloads.SEC3_ANGLES]
+    cs = [workloads.sec33_cylinder_case(th, start=st_) for st_, th in combos]
     r = _angle_sweep(torch, P, cs, a.sweep_max_steps, label="cylinder2d")
     rows = []
-    for c, th, t, (cen, R) in zip(cs, workloads.SEC3_ANGLES, r.pop("final"), r.pop("fits")):
+    for c, (st_, th), t, (cen, R) in zip(cs, combos, r.pop("final"), r.pop("fits")):
         # the same fitted circle against other readings of the wall radius
         d = math.hypot(cen[0] - c["wall"]["center"][0], cen[1] - c["wall"]["center"][1])
         alt = {}
         for rw in (59.5, 60.0):
             cs_ = (R * R + rw * rw - d * d) / (2.0 * R * rw)
             alt[f"theta_vs_R{rw}"] = round(math.degrees(math.acos(max(-1.0, min(1.0, cs_)))), 2)
-        rows.append(dict(prescribed=th, measured=round(t, 2), error=round(t - th, 2), **alt))
+        rows.append(dict(start=st_, prescribed=th, measured=round(t, 2), error=round(t - th, 2), **alt))
     return dict(workload="Sec. 3.3 2D cylinder R_s = 60, 256x256 D2Q9 FP32, R_i = 50, W = 6, "
                          "sigma 0.005, M 0.01, rho 10/1, nu 0.1", angles=rows, **r)
 
@@ -563,8 +572,10 @@ def incline_3d(a, torch, P, workloads):
     """Sec. 3.2 in 3D at reduced size (default 128^3, R = 25, W = 6): drops on
     the staircase plane z = slope x for slopes 1, 0.5, 0.25 and the angles of
     a.incline3d_angles, as one group (phase lattice a.incline3d_phase)."""
-    combos = [(s_, th) for s_ in workloads.SEC32_SLOPES for th in a.incline3d_angles]
-    cs = [workloads.sec32_incline_case_3d(th, s_, n=a.incline3d_n) for s_, th in combos]
+    slopes = [float(v) for v in a.incline3d_slopes.split(",")]
+    combos = [(s_, th) for s_ in slopes for th in a.incline3d_angles]
+    cs = [workloads.sec32_incline_case_3d(th, s_, n=a.incline3d_n, start=a.incline3d_start)
+          for s_, th in combos]
     if a.incline3d_phase:
         for c in cs:
             c["phase_lattice"] = a.incline3d_phase
@@ -574,21 +585,25 @@ def incline_3d(a, torch, P, workloads):
             for (s_, th), t in zip(combos, r.pop("final"))]
     lat = "D3Q19/" + a.incline3d_phase if a.incline3d_phase else "D3Q19"
     return dict(workload=f"Sec. 3.2 3D incline at {a.incline3d_n}^3, {lat} FP32, R = "
-                         f"{50 * a.incline3d_n / 256}, W 6, sigma 0.005, M 0.01",
-                angles=rows, **r)
+                         f"{50 * a.incline3d_n / 256}, W 6, sigma 0.005, M 0.01, "
+                         f"start {a.incline3d_start}", angles=rows, **r)
 
 
 def sphere_3d(a, torch, P, workloads):
     """Sec. 3.3 in 3D at reduced size (default 128^3: R_s = 30, R_i = 25,
     W = 6): drops on a sphere, the angles of a.sphere_angles as one group."""
-    cs = [workloads.sec33_sphere_case(th, n=a.sphere_n) for th in a.sphere_angles]
+    cs = [workloads.sec33_sphere_case(th, n=a.sphere_n, start=a.sphere_start) for th in a.sphere_angles]
+    if a.sphere_phase:
+        for c in cs:
+            c["phase_lattice"] = a.sphere_phase
     r = _angle_sweep(torch, P, cs, a.sphere_max_steps, label="sphere3d")
     r.pop("fits")
     rows = [{"prescribed": th, "measured": round(t, 2), "error": round(t - th, 2)}
             for th, t in zip(a.sphere_angles, r.pop("final"))]
+    lat = "D3Q19/" + a.sphere_phase if a.sphere_phase else "D3Q19"
     return dict(workload=f"Sec. 3.3 3D sphere at {a.sphere_n}^3 (R_s = {60 * a.sphere_n / 256}, "
-                         f"R_i = {50 * a.sphere_n / 256}), D3Q19 FP32, W 6, sigma 0.005, M 0.01",
-                angles=rows, **r)
+                         f"R_i = {50 * a.sphere_n / 256}), {lat} FP32, W 6, sigma 0.005, M 0.01, "
+                         f"start {a.sphere_start}", angles=rows, **r)
 
 
 def appendix_a(a, torch, P, workloads):

@@ -209,56 +209,72 @@ def sec32_incline_case(theta, slope, width=4.0, n=256):
     return c
 
 
-def sec32_incline_case_3d(theta, slope, n=256, width=6.0):
+def sec32_incline_case_3d(theta, slope, n=256, width=6.0, start="paper"):
     """Sec. 3.2 in 3D: an n^3 box, closed on all sides, solid below the plane
     z = slope x; a drop of R = 50 (scaled with n / 256) centred on the plane at
     (n/2, n/2, slope n/2).  The wall the angle is measured against is that plane
-    moved one node into the solid along its normal.  sigma = 0.005, M = 0.01,
-    rho 10/1, nu 0.1 in both phases, W = 6, D3Q19 FP32."""
+    moved one node into the solid along its normal.  start="cap": the sphere of
+    the same R placed so that it meets that wall at theta.  sigma = 0.005,
+    M = 0.01, rho 10/1, nu 0.1 in both phases, W = 6, D3Q19 FP32."""
     shape = (n, n, n)
     gam = math.atan(slope)
     mask = inclined_plane(shape, (0.0, 0.0), math.degrees(gam))
     nrm = (-math.sin(gam), 0.0, math.cos(gam))
     x0 = n / 2.0
     R = 50.0 * n / 256.0
-    phi0 = droplet(shape, (x0, n / 2.0, slope * x0), R, width)
     wall = dict(kind="plane", point=(-nrm[0], 0.0, -nrm[2]), normal=nrm)
+    centre = (x0, n / 2.0, slope * x0)
+    if start == "cap":
+        foot = tuple(centre[k] - nrm[k] for k in range(3))
+        centre = _cap_centre(wall, foot, R, theta)
+    phi0 = droplet(shape, centre, R, width)
     c = _case("D3Q19", shape, (False, False, False), mask, phi0, theta, 0.005, width, wall)
     c.update(mobility=0.01, storage="f32", radius=R,
              name=f"sec32-3d-slope{slope}-theta{int(theta)}")
     return c
 
 
-def sec33_cylinder_case(theta, width=6.0, n=256):
+def sec33_cylinder_case(theta, width=6.0, n=256, start="paper"):
     """Sec. 3.3 in 2D: a solid cylinder of radius R_s = 60 centred at
     (n/2, n/2 - 50) in an n x n box (scaled with n), periodic in x and closed in
     y; a drop of R_i = 50 centred at (n/2, n/2), inside the cylinder's top (only
     zeta = 1 nodes read phi0).  The wall circle of the angle fit has radius
-    R_s - 1.
+    R_s - 1.  start="cap": instead, a circle of radius 0.6 R_i placed so that
+    it meets the wall circle at theta (the equilibrium shape up to the interface
+    profile), so the contact line need not travel over the staircase.
     sigma = 0.005, M = 0.01, rho 10/1, nu 0.1 in both phases, W = 6."""
     shape = (n, n)
     k = n / 256.0
     rs, centre = 60.0 * k, (n / 2.0, n / 2.0 - 50.0 * k)
     mask = ball(shape, centre, rs)
-    phi0 = droplet(shape, (n / 2.0, n / 2.0), 50.0 * k, width)
     wall = dict(kind="circle", center=centre, radius=rs - 1.0)
+    if start == "cap":
+        r = 0.6 * 50.0 * k
+        phi0 = droplet(shape, _cap_centre(wall, None, r, theta), r, width)
+    else:
+        phi0 = droplet(shape, (n / 2.0, n / 2.0), 50.0 * k, width)
     c = _case("D2Q9", shape, (True, False), mask, phi0, theta, 0.005, width, wall)
     c.update(mobility=0.01, storage="f32", name=f"sec33-cylinder-theta{int(theta)}")
     return c
 
 
-def sec33_sphere_case(theta, n=256, width=6.0):
+def sec33_sphere_case(theta, n=256, width=6.0, start="paper"):
     """Sec. 3.3 in 3D: a solid sphere of radius R_s = 60 centred at
     (n/2, n/2, n/2 - 50) in an n^3 box (scaled with n / 256), periodic in x and
     y and closed in z; a drop of R_i = 50 centred at (n/2, n/2, n/2).  The wall
-    sphere of the angle fit has radius R_s - 1.  sigma = 0.005, M = 0.01,
+    sphere of the angle fit has radius R_s - 1.  start="cap": a sphere of radius
+    0.6 R_i placed so that it meets the wall sphere at theta.  sigma = 0.005, M = 0.01,
     rho 10/1, nu 0.1 in both phases, W = 6, D3Q19 FP32."""
     shape = (n, n, n)
     k = n / 256.0
     rs, centre = 60.0 * k, (n / 2.0, n / 2.0, n / 2.0 - 50.0 * k)
     mask = ball(shape, centre, rs)
-    phi0 = droplet(shape, (n / 2.0, n / 2.0, n / 2.0), 50.0 * k, width)
     wall = dict(kind="ball", center=centre, radius=rs - 1.0)
+    if start == "cap":
+        r = 0.6 * 50.0 * k
+        phi0 = droplet(shape, _cap_centre(wall, None, r, theta), r, width)
+    else:
+        phi0 = droplet(shape, (n / 2.0, n / 2.0, n / 2.0), 50.0 * k, width)
     c = _case("D3Q19", shape, (True, True, False), mask, phi0, theta, 0.005, width, wall)
     c.update(mobility=0.01, storage="f32", name=f"sec33-sphere-theta{int(theta)}")
     return c
