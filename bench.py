@@ -418,9 +418,17 @@ def _angle_sweep(torch, P, cases, max_steps, chunk=100000, label="sweep"):
     g.set_graph_chunk(1000)
     hist, marks, steps, t0 = [], {}, 0, time.perf_counter()
     t_said = t0
+    sub = min(chunk, 10000)
     while steps < max_steps:
-        g.step(chunk)
-        steps += chunk
+        # the chunk in synchronised parts, so that a long chunk of large cases
+        # still reports progress
+        for _ in range(chunk // sub):
+            g.step(sub)
+            torch.cuda.synchronize()
+            if time.perf_counter() - t_said > 30.0:
+                progress(f"{label}: {steps + sub} steps")
+                t_said = time.perf_counter()
+            steps += sub
         diags, _ = g.poll()
         last = diags
         hist.append([d["theta_deg"] for d in diags])
