@@ -947,8 +947,10 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_step(
 // nodes' phi (Sec. 2.2.2; Appendix A with chi_a != 0) into the phi array, from
 // the zeta = 1 values the phi pass wrote.  The collide pass then reads phi of
 // the tile and one halo layer as it stands, with no ghost means of its own.
+// A single case uses k_ghost (a block list built with the node classes); a
+// group uses k_ghost_group over its tile table:
 //
-// A workgroup of kGhostThreads takes one tile's box: the tile widened by the
+// a workgroup of kGhostThreads takes one tile's box, the tile widened by the
 // padding layer where it meets a face of the padded grid, so that the tiles of
 // a case cover every ghost node once.  It lists the box's ghost nodes in LDS,
 // kGhostChunk entries at a time, and then evaluates them with every lane busy
@@ -1069,8 +1071,18 @@ __device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __rest
   const int lane = threadIdx.x, ty = threadIdx.y, tz = D3 ? threadIdx.z : 0;
   const int tid = lane + 64 * (ty + BY * tz);
   const int P3[3] = {G.PX, G.PY, G.PZ};
-  // entries that are neither zeta = 1 nor ghost hold phi = 0
-  for (int m = tid; m < NL; m += NT) {
+  // every entry's node word and phi requested before any is stored, so the
+  // loads of a thread overlap (phi whatever the word; entries that are neither
+  // zeta = 1 nor ghost hold phi = 0 in LDS)
+  constexpr int KP = (NL + NT - 1) / NT;
+  uint32_t hw[KP];
+  C hv[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int m = tid + k * NT;
+    hw[k] = 0u;
+    hv[k] = C(0);
+    if (m >= NL) continue;
     const int lx = m % LX, ly = (m / LX) % LY, lz = m / (LX * LY);
     int q[3] = {x0 - 1 + lx, y0 - 1 + ly, z0 - HZ + lz};
     bool ok = true;
@@ -1083,15 +1095,18 @@ __device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __rest
         ok = false;
       }
     }
-    uint32_t w = 0;
-    C v = C(0);
     if (ok) {
       const nidx n = G.idx(q[0], q[1], q[2]);
-      w = nodes[n];
-      if (w & (kZeta | kGhost)) v = phi[n];
+      hw[k] = nodes[n];
+      hv[k] = phi[n];
     }
-    sw[m] = w;
-    sphi[m] = v;
+  }
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int m = tid + k * NT;
+    if (m >= NL) continue;
+    sw[m] = hw[k];
+    sphi[m] = (hw[k] & (kZeta | kGhost)) ? hv[k] : C(0);
   }
   __syncthreads();
   const int x = x0 + lane, y = y0 + ty, z = z0 + tz;
@@ -1623,8 +1638,17 @@ __device__ inline void stepZ_tile(int x0, int y0, int z0, const uint32_t* __rest
   }
 }
 
+// Waves per SIMD to ask of the register allocator for a workgroup of nt
+// threads: the largest multiple of the workgroup's waves per SIMD (nt / 256,
+// the four SIMDs of a CU sharing its wavefronts) up to cap.  Workgroups are
+// resident whole, so a 512-thread workgroup fits two per CU at 4 or at 5 waves
+// per SIMD, and 4 (128 VGPRs) costs nothing against 5 (96).
+constexpr int fill_waves(int nt, int cap) {
+  return nt <= 256 ? cap : cap / (nt / 256) * (nt / 256);
+}
+
 template <class L, int S, int TY, int TZ, bool O>
-__global__ __launch_bounds__(64 * TY, 4) void k_stepZ(
+__global__ __launch_bounds__(64 * TY, fill_waves(64 * TY, 4)) void k_stepZ(
     const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
     const void* __restrict__ gsrc, void* __restrict__ fdst, void* __restrict__ gdst,
     ComputeT<S>* __restrict__ sprev, Geo G, Phys P) {
@@ -1640,7 +1664,7 @@ __global__ __launch_bounds__(64 * TY, 4) void k_stepZ(
 }
 
 template <class L, int S, int TY, int TZ, bool O>
-__global__ __launch_bounds__(64 * TY, 5) void k_stepC(
+__global__ __launch_bounds__(64 * TY, fill_waves(64 * TY, 5)) void k_stepC(
     const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
     const void* __restrict__ gsrc, void* __restrict__ fdst, void* __restrict__ gdst,
     ComputeT<S>* __restrict__ sprev, const ComputeT<S>* __restrict__ phi, Geo G, Phys P) {
@@ -1763,7 +1787,7 @@ __global__ __launch_bounds__(64 * BY * BZ, 7) void k_stepB_group(
 }
 
 template <class L, int S, int TY, int TZ, bool PERSIST = false>
-__global__ __launch_bounds__(64 * TY, 5) void k_stepC_group(
+__global__ __launch_bounds__(64 * TY, fill_waves(64 * TY, 5)) void k_stepC_group(
     const TileEntry* __restrict__ table, const int* __restrict__ ntiles,
     const CaseDesc* __restrict__ cases, int parity) {
   using T = ColumnTile<L, S, TY, TZ>;
@@ -1785,7 +1809,7 @@ __global__ __launch_bounds__(64 * TY, 5) void k_stepC_group(
 
 // Batched fused z-marching step: one column segment per table entry.
 template <class L, int S, int TY, int TZ, bool PERSIST = false>
-__global__ __launch_bounds__(64 * TY, 4) void k_stepZ_group(
+__global__ __launch_bounds__(64 * TY, fill_waves(64 * TY, 4)) void k_stepZ_group(
     const TileEntry* __restrict__ table, const int* __restrict__ ntiles,
     const CaseDesc* __restrict__ cases, int parity) {
   using T = MarchTile<TY>;
