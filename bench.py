@@ -39,7 +39,12 @@ def parse():
     ap.add_argument("--ny", type=int, default=512)
     ap.add_argument("--chunk", type=int, default=100, help="steps per captured HIP graph")
     ap.add_argument("--profile-steps", type=int, default=200)
-    ap.add_argument("--variant", type=int, default=1, help="fused step tile variant")
+    ap.add_argument("--variant", default="tuned",
+                    help="2D step launch shape for the bench line: 'variant' or "
+                         "'variant:xcd_order', or 'tuned' for the autotuner's choice of "
+                         "variant on the shape (XCD order 0)")
+    ap.add_argument("--variant-twin", default="tuned",
+                    help="the same for the 8192x4096 twin")
     ap.add_argument("--sections", default="main,twin,3d,precision,batched,serve,cpu",
                     help="comma list of: main (the 1024x512 line), twin (8192x4096), 3d "
                          "(256^3 D3Q19), precision (each storage type against the stored FP64 "
@@ -162,12 +167,14 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name, nodes, prefix=""):
+def measured_traffic(name, nodes, prefix="", launch=None):
     """HBM bytes per launch sequence (one step) from a committed rocprofv3 counter
     summary, if it was taken on the current kernel source; else None.  The
     summary's `<prefix>fetch_kib_per_step` / `<prefix>write_kib_per_step` (or,
     for one-kernel steps, `fetch_kib_per_dispatch` / `write_kib_per_dispatch`)
-    are scaled by the copy-calibrated factors it records."""
+    are scaled by the copy-calibrated factors it records.  With `launch` (a
+    launch_shape record), the summary must have been taken on that step
+    variant and XCD order."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None, "no counter summary"
@@ -178,6 +185,12 @@ def measured_traffic(name, nodes, prefix=""):
             kv[k.strip().lstrip("- ")] = v.strip()
     if kv.get("kernel_source_sha1") != kernel_source_hash():
         return None, "kernel changed since the counters were taken"
+    if launch is not None:
+        want = f"{launch['variant']}:{launch['xcd_order']}"
+        got = kv.get("launch_shape", "")
+        got = got if ":" in got else got + ":0"
+        if got != want:
+            return None, f"counters taken on launch shape {got}, not {want}"
     fk = prefix + "fetch_kib_per_step" if prefix + "fetch_kib_per_step" in kv else "fetch_kib_per_dispatch"
     wk = prefix + "write_kib_per_step" if prefix + "write_kib_per_step" in kv else "write_kib_per_dispatch"
     if fk not in kv or wk not in kv:
@@ -827,10 +840,27 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def launch_shape(choice, case):
+    """Apply a 2D step variant: the given one, or ("tuned") the one the
+    autotuner picks on this case's shape, timing every variant with graph
+    replay in the D2Q9 default XCD order 0 (no cache, so every run tunes
+    afresh)."""
+    if str(choice) != "tuned":
+        v, _, xo = str(choice).partition(":")        # "variant" or "variant:xcd_order"
+        case.set_step_kernel(int(v))
+        case.set_step_options(int(xo or 0), False)
+        return {"variant": int(v), "xcd_order": int(xo or 0), "tuned": False}
+    from paper_2312_00369_amd import autotune
+    t = autotune.tune_case(case, steps=200, xcd_orders=(0,))
+    progress(f"tuned launch shape: variant {t['variant']}, XCD order {t['xcd_order']}")
+    return {"variant": t["variant"], "xcd_order": t["xcd_order"], "tuned": True,
+            "tuned_ms_per_step": round(t["ms"], 5)}
+
+
 def run(a, torch, P, workloads, stream):
     c = workloads.flat_1024x512_fp32(theta=a.theta, nx=a.nx, ny=a.ny)
     case = P.Case.from_case(c, "f32", stream=stream)
-    case.set_step_kernel(a.variant)
+    shape = launch_shape(a.variant, case)
     nodes = int((case.classes() & 1).sum())
     ms, K = time_steps(torch, case, a.steps, a.warmup, a.chunk)
     ms_step = ms / a.steps
@@ -845,7 +875,8 @@ def run(a, torch, P, workloads, stream):
     roof = roofline(alg, nodes, ms_step, "k_step (fused time step, one launch per step)")
     roof["eager_launch_avg_ms"] = round(float(kern_ms[3]), 5)
     if (a.nx, a.ny) == (1024, 512):
-        traffic, note = measured_traffic("k_step_d2q9_fp32_1024x512_counters.md", nodes)
+        traffic, note = measured_traffic("k_step_d2q9_fp32_1024x512_counters.md", nodes,
+                                         launch=shape)
         roof["traffic"] = traffic
         roof["traffic_note"] = note
         roof["cache_resident"] = ("the ~82 MB state fits the 256 MB Infinity Cache (MALL): the "
@@ -855,7 +886,7 @@ def run(a, torch, P, workloads, stream):
     # the three-kernel path on the same case, for reference
     case.set_step_kernel(-1)
     k3 = case.profile(a.profile_steps)
-    case.set_step_kernel(a.variant)
+    case.set_step_kernel(shape["variant"])
     roof["three_kernel_path_ms"] = {"k_phi": round(float(k3[0]), 5), "k_mu": round(float(k3[1]), 5),
                                     "k_collide": round(float(k3[2]), 5)}
     line = {
@@ -865,7 +896,7 @@ def run(a, torch, P, workloads, stream):
         "data": "synthetic",
         "config": {"workload": f"D2Q9 FP32 {a.nx}x{a.ny} flat-wall droplet R={80 * a.nx / 1024:g}, "
                                f"theta={a.theta:g}, W=5, rho 10/1, tau 0.8, M 0.1, sigma 1e-3",
-                   "nodes": nodes, "graph_chunk": K,
+                   "nodes": nodes, "graph_chunk": K, "launch_shape": shape,
                    "timed_graph_replays": a.steps // K if K else 0,
                    "timed_eager_steps": a.steps % K if K else a.steps},
         "hbm_roofline_pct_step": round(100 * mlups * 1e6 * alg / (HBM_PEAK_GBS * 1e9), 2),
@@ -879,18 +910,20 @@ def run(a, torch, P, workloads, stream):
         # HBM-bound twin: 8192 x 4096 (33.5 M nodes), same physics
         big = workloads.flat_1024x512_fp32(theta=a.theta, nx=8192, ny=4096)
         cb = P.Case.from_case(big, "f32", stream=stream)
-        cb.set_step_kernel(a.variant)
+        shape_b = launch_shape(a.variant_twin, cb)
         nb = int((cb.classes() & 1).sum())
         k = 400
         msb, Kb = time_steps(torch, cb, k, 20, a.chunk)
         kb = cb.profile(20)
         mlb = nb * k / (msb / 1e3) / 1e6
-        traffic, note = measured_traffic("k_step_d2q9_fp32_8192x4096_counters.md", nb)
+        traffic, note = measured_traffic("k_step_d2q9_fp32_8192x4096_counters.md", nb,
+                                         launch=shape_b)
         rb = roofline(alg, nb, msb / k, "k_step (fused time step, one launch per step)",
                       traffic=traffic)
         rb["traffic_note"] = note
         rb["target_frac"] = 0.70
-        line["dram_twin"] = {"workload": "D2Q9 FP32 8192x4096", "MLUPS": round(mlb, 1),
+        line["dram_twin"] = {"workload": "D2Q9 FP32 8192x4096", "launch_shape": shape_b,
+                             "MLUPS": round(mlb, 1),
                              "hbm_roofline_pct": round(100 * mlb * 1e6 * alg / (HBM_PEAK_GBS * 1e9), 2),
                              "ms_per_step": round(msb / k, 4), "graph_chunk": Kb,
                              "eager_launch_avg_ms": round(float(kb[3]), 4), "roofline": rb}

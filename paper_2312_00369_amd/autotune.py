@@ -78,13 +78,18 @@ def _torch_sync():
     torch.cuda.synchronize()
 
 
-def tune_case(case, steps=200, cache=None, arch=None, timer=None, sync=None):
-    """Pick the fastest (variant, xcd_order) for `case`; applies and returns it."""
+def tune_case(case, steps=200, cache=None, arch=None, timer=None, sync=None,
+              xcd_orders=XCD_ORDERS):
+    """Pick the fastest (variant, xcd_order) for `case` over every step variant
+    and the given XCD orders; applies and returns it.  A search over fewer
+    orders than XCD_ORDERS neither reads nor writes the cache."""
     timer = timer or _wall_timer
     sync = sync or _torch_sync
     arch = arch or gpu_arch()
     prm = case.params
     key = cache_key(arch, prm.lattice, prm.storage, case.shape)
+    if tuple(xcd_orders) != tuple(XCD_ORDERS):
+        cache = None
     if cache is not None and cache.get(key):
         best = cache.get(key)
         case.set_step_kernel(best["variant"])
@@ -94,7 +99,7 @@ def tune_case(case, steps=200, cache=None, arch=None, timer=None, sync=None):
     lattice = "D2Q9" if prm.lattice == _p.D2Q9 else "D3Q19"
     results = []
     for v in range(len(_p.step_variants(lattice))):
-        for xo in XCD_ORDERS:
+        for xo in xcd_orders:
             case.set_step_kernel(v)
             case.set_step_options(xo, False)
             sec = timer(case.step, steps, sync)

@@ -57,6 +57,18 @@ def test_tune_case_picks_fastest_restores_and_caches(P, tmp_path):
     assert out2["cached"] and c2.variant == 3 and c2.steps_done == 0
 
 
+def test_tune_case_over_fewer_xcd_orders_skips_the_cache(P, tmp_path):
+    path = tmp_path / "tune.json"
+    cache = autotune.Cache(str(path))
+    case = FakeCase(P)
+    out = autotune.tune_case(case, steps=10, cache=cache, arch="gfx950", timer=fake_timer,
+                             sync=lambda: None, xcd_orders=(0,))
+    assert out["variant"] == 3 and out["xcd_order"] == 0 and case.xcd == 0
+    assert {c["xcd_order"] for c in out["candidates"]} == {0}
+    assert len(out["candidates"]) == len(P.step_variants("D2Q9"))
+    assert not path.exists() or json.load(open(path)) == {}
+
+
 def test_shape_classes():
     assert autotune.shape_class((1024, 512)) == "2d-n2^19"
     assert autotune.shape_class((256, 256, 256)) == "3d-n2^24"
