@@ -189,6 +189,14 @@ struct Set {
 };
 
 // ------------------------------------------------------------------ indexing
+// q taken into [0, P) on a periodic axis: entries already inside skip the
+// integer division (a few lanes at the edges of a tile take it)
+__device__ inline int wrapq(int q, int P) {
+  if (q >= 0 && q < P) return q;
+  q %= P;
+  return q < 0 ? q + P : q;
+}
+
 __device__ inline int wrap1(int q, int P, int per) {
   if (per) {
     q += (q < 0) ? P : 0;
@@ -452,8 +460,7 @@ __global__ void k_mu(const uint32_t* __restrict__ nodes, C* __restrict__ phi,
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       if (G.per[d]) {
-        q[d] %= P3[d];
-        if (q[d] < 0) q[d] += P3[d];
+        q[d] = wrapq(q[d], P3[d]);
       } else {
         ok = ok && q[d] >= 0 && q[d] < P3[d];
       }
@@ -528,6 +535,26 @@ struct Macro {
   }
 };
 
+// a * b + c rounded once (the same in every kernel that inlines it, unlike a
+// contraction the compiler may or may not form)
+template <class C>
+__device__ inline C fmac(C a, C b, C c) {
+  if constexpr (std::is_same<C, float>::value) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+
+// c . (a, b, c3) for a lattice direction with components in {-1, 0, 1}: the
+// zero components are left out (a product with 0.0 is not folded away).
+template <class C>
+__device__ inline C cdot(int cx, int cy, int cz, C a, C b, C c3) {
+  C r = C(0);
+  bool any = false;
+  if (cx) { r = cx > 0 ? a : -a; any = true; }
+  if (cy) { r = any ? (cy > 0 ? r + b : r - b) : (cy > 0 ? b : -b); any = true; }
+  if (cz) { r = any ? (cz > 0 ? r + c3 : r - c3) : (cz > 0 ? c3 : -c3); }
+  return r;
+}
+
 // Collision of both sets at one node (sp = s of the previous step):
 // Eq. (BGK) with g_eq of Eq. (H_i) and G_i of Eq. (F_i) plus half its time
 // derivative, the latter a backward difference of s, so that
@@ -574,14 +601,14 @@ __device__ inline ComputeT<S> collide_post(const ComputeT<S>* f, double g0, cons
 #pragma unroll
     for (int i = 1; i < LG::Q; ++i) {
       const C wi = C(LG::w(i));
-      put_g(i, g[i] - (g[i] - wi * am) * itg + wi * C(LG::k(i)) * srcf);
+      put_g(i, fmac(wi * am - g[i], itg, g[i]) + C(LG::w(i) * LG::k(i)) * srcf);
     }
   } else {
     double dsum = 0.0;          // sum_{i>0} (g_i - stored g*_i), exact in FP64
 #pragma unroll
     for (int i = 1; i < LG::Q; ++i) {
       const C wi = C(LG::w(i));
-      const C v = g[i] - (g[i] - wi * am) * itg + wi * C(LG::k(i)) * srcf;
+      const C v = fmac(wi * am - g[i], itg, g[i]) + C(LG::w(i) * LG::k(i)) * srcf;
       put_g(i, v);
       dsum += (double)g[i] - (double)stored_g(v);
     }
@@ -593,19 +620,21 @@ __device__ inline ComputeT<S> collide_post(const ComputeT<S>* f, double g0, cons
   const C itau = C(1) / tau;
   const C ffac = C(1) - C(0.5) * itau;
   const C pc = M.p * inv_cs2;
+  const C uu15 = C(0.5) * inv_cs2 * M.uu;
+  const C ffac3 = ffac * inv_cs2;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const C wi = C(L::w(i));
-    const C cx = C(L::cx(i)), cy = C(L::cy(i)), cz = C(L::cz(i));
-    const C cu = cx * M.ux + cy * M.uy + cz * M.uz;
-    const C cF = cx * M.Fx + cy * M.Fy + cz * M.Fz;
-    const C cr = cx * M.rx + cy * M.ry + cz * M.rz;
-    const C si = wi * (cu * inv_cs2 + C(0.5) * cu * cu * inv_cs2 * inv_cs2 -
-                       C(0.5) * M.uu * inv_cs2);
-    const C feq = pc * (i == 0 ? wi - C(1) : wi) + M.rho * si;
-    // Eq. (GGi): u.grad rho + c.F/cs2 + [(c.u)(c.grad rho) - cs2 u.grad rho]/cs2
-    const C Fi = ffac * wi * (M.ugr + cF * inv_cs2 + (cu * cr - M.ugr * C(kCs2)) * inv_cs2);
-    put_f(i, f[i] - (f[i] - feq) * itau + Fi);
+    const C cu = cdot<C>(L::cx(i), L::cy(i), L::cz(i), M.ux, M.uy, M.uz);
+    const C cF = cdot<C>(L::cx(i), L::cy(i), L::cz(i), M.Fx, M.Fy, M.Fz);
+    const C cr = cdot<C>(L::cx(i), L::cy(i), L::cz(i), M.rx, M.ry, M.rz);
+    // velocity part of Eq. (feq_i): w_i [c.u/cs2 + (c.u)^2/(2 cs2^2) - u.u/(2 cs2)]
+    const C si = wi * fmac(C(4.5) * cu, cu, fmac(inv_cs2, cu, -uu15));
+    const C feq = fmac(M.rho, si, pc * C(i == 0 ? L::w(i) - 1.0 : L::w(i)));
+    // Eq. (GGi): u.grad rho + c.F/cs2 + [(c.u)(c.grad rho) - cs2 u.grad rho]/cs2,
+    // whose u.grad rho terms cancel: (c.F + (c.u)(c.grad rho))/cs2
+    const C Fi = (ffac3 * wi) * fmac(cu, cr, cF);
+    put_f(i, fmac(feq - f[i], itau, f[i]) + Fi);
   }
   return M.s;
 }
@@ -775,8 +804,7 @@ __device__ inline void step_tile(int x0, int y0, int z0, const uint32_t* __restr
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       if (G.per[d]) {
-        q[d] %= P3[d];
-        if (q[d] < 0) q[d] += P3[d];
+        q[d] = wrapq(q[d], P3[d]);
       } else if (q[d] < 0 || q[d] >= P3[d]) {
         return -1;
       }
@@ -1089,8 +1117,7 @@ __device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __rest
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       if (G.per[d]) {
-        q[d] %= P3[d];
-        if (q[d] < 0) q[d] += P3[d];
+        q[d] = wrapq(q[d], P3[d]);
       } else if (q[d] < 0 || q[d] >= P3[d]) {
         ok = false;
       }
@@ -1214,8 +1241,7 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
     int qz = z;
     bool zok = true;
     if (G.per[2]) {
-      qz %= P3[2];
-      if (qz < 0) qz += P3[2];
+      qz = wrapq(qz, P3[2]);
     } else if (qz < 0 || qz >= P3[2]) {
       zok = false;
     }
@@ -1231,8 +1257,7 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
         if (G.per[d]) {
-          q[d] %= P3[d];
-          if (q[d] < 0) q[d] += P3[d];
+          q[d] = wrapq(q[d], P3[d]);
         } else if (q[d] < 0 || q[d] >= P3[d]) {
           ok = false;
         }
@@ -1371,8 +1396,7 @@ __device__ inline void stepZ_tile(int x0, int y0, int z0, const uint32_t* __rest
   // plane z in the padded grid (periodic wrap), or -1 outside a closed axis
   auto zof = [&](int z) -> int {
     if (G.per[2]) {
-      z %= G.PZ;
-      return z < 0 ? z + G.PZ : z;
+      return wrapq(z, G.PZ);
     }
     return (z >= 0 && z < G.PZ) ? z : -1;
   };
@@ -1381,14 +1405,12 @@ __device__ inline void stepZ_tile(int x0, int y0, int z0, const uint32_t* __rest
     qx = x0 - 2 + m % LX;
     qy = y0 - 2 + m / LX;
     if (G.per[0]) {
-      qx %= G.PX;
-      if (qx < 0) qx += G.PX;
+      qx = wrapq(qx, G.PX);
     } else if (qx < 0 || qx >= G.PX) {
       return false;
     }
     if (G.per[1]) {
-      qy %= G.PY;
-      if (qy < 0) qy += G.PY;
+      qy = wrapq(qy, G.PY);
     } else if (qy < 0 || qy >= G.PY) {
       return false;
     }
