@@ -189,6 +189,26 @@ struct Set {
 };
 
 // ------------------------------------------------------------------ indexing
+// a * b + c rounded once (the same in every kernel that inlines it, unlike a
+// contraction the compiler may or may not form)
+template <class C>
+__device__ inline C fmac(C a, C b, C c) {
+  if constexpr (std::is_same<C, float>::value) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+
+// c . (a, b, c3) for a lattice direction with components in {-1, 0, 1}: the
+// zero components are left out (a product with 0.0 is not folded away).
+template <class C>
+__device__ inline C cdot(int cx, int cy, int cz, C a, C b, C c3) {
+  C r = C(0);
+  bool any = false;
+  if (cx) { r = cx > 0 ? a : -a; any = true; }
+  if (cy) { r = any ? (cy > 0 ? r + b : r - b) : (cy > 0 ? b : -b); any = true; }
+  if (cz) { r = any ? (cz > 0 ? r + c3 : r - c3) : (cz > 0 ? c3 : -c3); }
+  return r;
+}
+
 // q taken into [0, P) on a periodic axis: entries already inside skip the
 // integer division (a few lanes at the edges of a tile take it)
 __device__ inline int wrapq(int q, int P) {
@@ -391,20 +411,22 @@ __device__ inline C wet_of(uint32_t word, const Phys& P) {
   else return C(P.wet_tab[k]);
 }
 
-template <class L, class C>
-__device__ inline C mu_at(const C* sphi, const uint32_t* sw, int t, int sx, int sxy,
-                          const Phys& P) {
-  const C ph = sphi[t];
+// The same from accessors: phi_at(i) and word_at(i) give phi and the node word
+// at x + c_i, wet() the wall coefficient at x (called where the sum needs it).
+// Every kernel forms mu through this one function, so their results agree to
+// the bit.
+template <class L, class C, class PhiAt, class WordAt, class Wet>
+__device__ inline C mu_of(C ph, PhiAt&& phi_at, WordAt&& word_at, Wet&& wet, const Phys& P) {
   C lap = C(0), ex = C(0), ey = C(0), ez = C(0);
 #pragma unroll
   for (int i = 1; i < L::Q; ++i) {
-    const int t2 = t + L::cx(i) + sx * L::cy(i) + sxy * L::cz(i);
-    const C wi = C(L::w(i));
-    lap += C(2) * wi * (sphi[t2] - ph);
-    const C e = (sw[t2] & kFluid) ? C(1) : C(0);
-    ex += wi * C(L::cx(i)) * e;
-    ey += wi * C(L::cy(i)) * e;
-    ez += wi * C(L::cz(i)) * e;
+    lap = fmac(C(2 * L::w(i)), phi_at(i) - ph, lap);
+    // w_i c_i eps: eps is 0 or 1, so each product is exact and the fused form
+    // adds what the separate one would; zero components are left out
+    const C e = (word_at(i) & kFluid) ? C(1) : C(0);
+    if (L::cx(i)) ex = fmac(C(L::w(i) * L::cx(i)), e, ex);
+    if (L::cy(i)) ey = fmac(C(L::w(i) * L::cy(i)), e, ey);
+    if (L::cz(i)) ez = fmac(C(L::w(i) * L::cz(i)), e, ez);
   }
   const C inv_cs2 = C(3);
   lap *= inv_cs2;
@@ -413,7 +435,16 @@ __device__ inline C mu_at(const C* sphi, const uint32_t* sw, int t, int sx, int 
   ez *= inv_cs2;
   const C av = sqrt(ex * ex + ey * ey + ez * ez);
   return C(4) * C(P.beta) * ph * (ph - C(1)) * (ph - C(0.5)) - C(P.kappa) * lap -
-         av * wet_of<L::D, C>(sw[t], P) * (ph - ph * ph);
+         av * wet() * (ph - ph * ph);
+}
+
+template <class L, class C>
+__device__ inline C mu_at(const C* sphi, const uint32_t* sw, int t, int sx, int sxy,
+                          const Phys& P) {
+  auto off = [&](int i) { return t + L::cx(i) + sx * L::cy(i) + sxy * L::cz(i); };
+  return mu_of<L, C>(
+      sphi[t], [&](int i) { return sphi[off(i)]; }, [&](int i) { return sw[off(i)]; },
+      [&]() { return wet_of<L::D, C>(sw[t], P); }, P);
 }
 
 // grad phi of Eq. (gradient) from neighbour values v(i) = phi(x + c_i).
@@ -423,9 +454,9 @@ __device__ inline void grad_of(Fn v, C& gx, C& gy, C& gz) {
 #pragma unroll
   for (int i = 1; i < L::Q; ++i) {
     const C t = C(L::w(i)) * v(i);
-    gx += C(L::cx(i)) * t;
-    gy += C(L::cy(i)) * t;
-    gz += C(L::cz(i)) * t;
+    if (L::cx(i)) gx = L::cx(i) > 0 ? gx + t : gx - t;   // zero components left out
+    if (L::cy(i)) gy = L::cy(i) > 0 ? gy + t : gy - t;
+    if (L::cz(i)) gz = L::cz(i) > 0 ? gz + t : gz - t;
   }
   gx *= C(3);
   gy *= C(3);
@@ -517,9 +548,9 @@ struct Macro {
     C mx = C(0), my = C(0), mz = C(0), sumf = C(0);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      mx += C(L::cx(i)) * f[i];
-      my += C(L::cy(i)) * f[i];
-      mz += C(L::cz(i)) * f[i];
+      if (L::cx(i)) mx = L::cx(i) > 0 ? mx + f[i] : mx - f[i];   // zero components left out
+      if (L::cy(i)) my = L::cy(i) > 0 ? my + f[i] : my - f[i];
+      if (L::cz(i)) mz = L::cz(i) > 0 ? mz + f[i] : mz - f[i];
       sumf += f[i];
     }
     const C inv_rho = C(1) / rho;
@@ -534,26 +565,6 @@ struct Macro {
     s = ux * gx + uy * gy + uz * gz;                               // u . grad phi
   }
 };
-
-// a * b + c rounded once (the same in every kernel that inlines it, unlike a
-// contraction the compiler may or may not form)
-template <class C>
-__device__ inline C fmac(C a, C b, C c) {
-  if constexpr (std::is_same<C, float>::value) return __builtin_fmaf(a, b, c);
-  else return __builtin_fma(a, b, c);
-}
-
-// c . (a, b, c3) for a lattice direction with components in {-1, 0, 1}: the
-// zero components are left out (a product with 0.0 is not folded away).
-template <class C>
-__device__ inline C cdot(int cx, int cy, int cz, C a, C b, C c3) {
-  C r = C(0);
-  bool any = false;
-  if (cx) { r = cx > 0 ? a : -a; any = true; }
-  if (cy) { r = any ? (cy > 0 ? r + b : r - b) : (cy > 0 ? b : -b); any = true; }
-  if (cz) { r = any ? (cz > 0 ? r + c3 : r - c3) : (cz > 0 ? c3 : -c3); }
-  return r;
-}
 
 // Collision of both sets at one node (sp = s of the previous step):
 // Eq. (BGK) with g_eq of Eq. (H_i) and G_i of Eq. (F_i) plus half its time
@@ -1161,8 +1172,22 @@ __device__ inline void stepB_tile(int x0, int y0, int z0, const uint32_t* __rest
                        G, P, P.nt_store);
 }
 
+// Waves per SIMD to ask of the register allocator for a workgroup of nt
+// threads: the largest multiple of the workgroup's waves per SIMD (nt / 256,
+// the four SIMDs of a CU sharing its wavefronts) up to cap.  Workgroups are
+// resident whole, so a 512-thread workgroup fits two per CU at 4 or at 5 waves
+// per SIMD, and 4 (128 VGPRs) costs nothing against 5 (96).
+constexpr int fill_waves(int nt, int cap) {
+  return nt <= 256 ? cap : cap / (nt / 256) * (nt / 256);
+}
+
+// The collide pass of the split step: FP32 and FP64 take the occupancy-neutral
+// bound (a 512-thread workgroup: 80 VGPRs, no spills); FP16-deviation keeps 7
+// waves per SIMD (72 VGPRs), measured faster for its instruction-bound pass.
+constexpr int stepB_waves(int s, int nt) { return s == kF16Dev ? 7 : fill_waves(nt, 7); }
+
 template <class L, int S, int BY, int BZ, bool O>
-__global__ __launch_bounds__(64 * BY * BZ, 7) void k_stepB(
+__global__ __launch_bounds__(64 * BY * BZ, stepB_waves(S, 64 * BY * BZ)) void k_stepB(
     const uint32_t* __restrict__ nodes, const void* __restrict__ fsrc,
     const void* __restrict__ gsrc, void* __restrict__ fdst, void* __restrict__ gdst,
     ComputeT<S>* __restrict__ sprev, const ComputeT<S>* __restrict__ phi, Geo G, Phys P) {
@@ -1318,27 +1343,11 @@ __device__ inline void stepC_tile(int x0, int y0, int z0, const uint32_t* __rest
       const int sl = L::cz(i) < 0 ? sm : (L::cz(i) > 0 ? sp : s0);
       return sl + t + L::cx(i) + LX * L::cy(i);
     };
-    // mu (same arithmetic as mu_at) and grad phi
+    // mu and grad phi
     const C ph = sphi[s0 + t];
-    C lap = C(0), ex = C(0), ey = C(0), ez = C(0);
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const int t2 = at(i);
-      const C wi = C(L::w(i));
-      lap += C(2) * wi * (sphi[t2] - ph);
-      const C e = (sw[t2] & kFluid) ? C(1) : C(0);
-      ex += wi * C(L::cx(i)) * e;
-      ey += wi * C(L::cy(i)) * e;
-      ez += wi * C(L::cz(i)) * e;
-    }
-    const C inv_cs2 = C(3);
-    lap *= inv_cs2;
-    ex *= inv_cs2;
-    ey *= inv_cs2;
-    ez *= inv_cs2;
-    const C av = sqrt(ex * ex + ey * ey + ez * ez);
-    const C m = C(4) * C(P.beta) * ph * (ph - C(1)) * (ph - C(0.5)) - C(P.kappa) * lap -
-                av * wet_of<L::D, C>(w, P) * (ph - ph * ph);
+    const C m = mu_of<L, C>(
+        ph, [&](int i) { return sphi[at(i)]; }, [&](int i) { return sw[at(i)]; },
+        [&]() { return wet_of<L::D, C>(w, P); }, P);
     C gx, gy, gz;
     grad_of<L, C>([&](int i) { return sphi[at(i)]; }, gx, gy, gz);
     node_update<L, S, 0, O>(f, g0, g, ph, m, gx, gy, gz, w, n, fdst, gdst, sprev, nullptr,
@@ -1625,26 +1634,11 @@ __device__ inline void stepZ_tile(int x0, int y0, int z0, const uint32_t* __rest
       auto wat = [&](int i) {
         return (L::cz(i) < 0 ? wm : (L::cz(i) > 0 ? wpl : w0)) + tt + L::cx(i) + LX * L::cy(i);
       };
-      // mu (same arithmetic as mu_at) and grad phi
+      // mu and grad phi
       const C ph = sphi[s0 + tt];
-      C lap = C(0), ex = C(0), ey = C(0), ez = C(0);
-#pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        const C wi = C(L::w(i));
-        lap += C(2) * wi * (sphi[pat(i)] - ph);
-        const C e = (sw[wat(i)] & kFluid) ? C(1) : C(0);
-        ex += wi * C(L::cx(i)) * e;
-        ey += wi * C(L::cy(i)) * e;
-        ez += wi * C(L::cz(i)) * e;
-      }
-      const C inv_cs2 = C(3);
-      lap *= inv_cs2;
-      ex *= inv_cs2;
-      ey *= inv_cs2;
-      ez *= inv_cs2;
-      const C av = sqrt(ex * ex + ey * ey + ez * ez);
-      const C m = C(4) * C(P.beta) * ph * (ph - C(1)) * (ph - C(0.5)) - C(P.kappa) * lap -
-                  av * wet_of<L::D, C>(w, P) * (ph - ph * ph);
+      const C m = mu_of<L, C>(
+          ph, [&](int i) { return sphi[pat(i)]; }, [&](int i) { return sw[wat(i)]; },
+          [&]() { return wet_of<L::D, C>(w, P); }, P);
       C gx, gy, gz;
       grad_of<L, C>([&](int i) { return sphi[pat(i)]; }, gx, gy, gz);
       node_update<L, S, 0, O>(f, g0c, gc, ph, m, gx, gy, gz, w, n, fdst, gdst, sprev, nullptr,
@@ -1660,14 +1654,6 @@ __device__ inline void stepZ_tile(int x0, int y0, int z0, const uint32_t* __rest
   }
 }
 
-// Waves per SIMD to ask of the register allocator for a workgroup of nt
-// threads: the largest multiple of the workgroup's waves per SIMD (nt / 256,
-// the four SIMDs of a CU sharing its wavefronts) up to cap.  Workgroups are
-// resident whole, so a 512-thread workgroup fits two per CU at 4 or at 5 waves
-// per SIMD, and 4 (128 VGPRs) costs nothing against 5 (96).
-constexpr int fill_waves(int nt, int cap) {
-  return nt <= 256 ? cap : cap / (nt / 256) * (nt / 256);
-}
 
 template <class L, int S, int TY, int TZ, bool O>
 __global__ __launch_bounds__(64 * TY, fill_waves(64 * TY, 4)) void k_stepZ(
@@ -1786,7 +1772,7 @@ __global__ __launch_bounds__(64 * BY * BZ) void k_phi_group(
 }
 
 template <class L, int S, int BY, int BZ, bool PERSIST = false>
-__global__ __launch_bounds__(64 * BY * BZ, 7) void k_stepB_group(
+__global__ __launch_bounds__(64 * BY * BZ, stepB_waves(S, 64 * BY * BZ)) void k_stepB_group(
     const TileEntry* __restrict__ table, const int* __restrict__ ntiles,
     const CaseDesc* __restrict__ cases, int parity) {
   constexpr bool D3 = (L::D == 3);
