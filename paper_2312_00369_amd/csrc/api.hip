@@ -87,7 +87,6 @@ int validate_and_derive(const pflbm_params* p, Derived* d) {
   Phys& ph = d->phys;
   // nu = c_s^2 (tau_f - 1/2) (Sec. 2.1.2); M = c_s^2 alpha (tau_g - 1/2) (Eq. mobility)
   ph.tau = p->tau;
-  ph.inv_tau = 1.0 / p->tau;
   ph.inv_tau_g = 1.0 / tau_g;
   // c_s^2 of the velocity set of g: 1/3, or 1/4 for D3Q7 (Sec. 2.1.3)
   const double cs2_g = p->lattice == PFLBM_D3Q19_D3Q7 ? D3Q7::cs2 : kCs2;

@@ -72,7 +72,6 @@ struct TileGrid {
 
 struct Phys {
   double tau, inv_tau_g, alpha, beta, kappa, wet, rho_l, rho_g, nu_l, nu_g;
-  double inv_tau;          // 1 / tau, formed on the host (uniform viscosity)
   double chi_a;            // chi(phi) = chi_a (phi - phi^2) of the ghost rule; 0 = mean only
   const double* wet_tab;   // device table of wall coefficients for per-node contact angles
   double Fb[3];
@@ -270,8 +269,7 @@ __device__ inline bool node_coords(const Geo& G, int& x, int& y, int& z) {
 __device__ inline void opaque(Phys& P) {
   asm volatile("" : "+s"(P.tau), "+s"(P.inv_tau_g), "+s"(P.alpha), "+s"(P.beta), "+s"(P.kappa),
                "+s"(P.wet));
-  asm volatile("" : "+s"(P.rho_l), "+s"(P.rho_g), "+s"(P.nu_l), "+s"(P.nu_g), "+s"(P.chi_a),
-               "+s"(P.inv_tau));
+  asm volatile("" : "+s"(P.rho_l), "+s"(P.rho_g), "+s"(P.nu_l), "+s"(P.nu_g), "+s"(P.chi_a));
   asm volatile("" : "+s"(P.Fb[0]), "+s"(P.Fb[1]), "+s"(P.Fb[2]), "+s"(P.scale_f),
                "+s"(P.scale_g));
 }
@@ -563,7 +561,7 @@ struct Macro {
     ugr = ux * rx + uy * ry + uz * rz;                             // u . grad rho
     const C w0 = C(L::w(0));
     const C s0 = -w0 * uu * C(0.5) * inv_cs2;
-    p = (sumf + C(0.5) * ugr + rho * s0) * C(1.0 / (3.0 * (1.0 - L::w(0))));   // / (cs2^-1 (1 - w_0))
+    p = (sumf + C(0.5) * ugr + rho * s0) / (inv_cs2 * (C(1) - w0));
     s = ux * gx + uy * gy + uz * gz;                               // u . grad phi
   }
 };
@@ -628,9 +626,9 @@ __device__ inline ComputeT<S> collide_post(const ComputeT<S>* f, double g0, cons
     put_g0(g0 + dsum - (double)srcf);
   }
   // hydrodynamic collision
-  // 1/tau: per node with a phase-dependent viscosity, else the host's value
-  C itau = C(P.inv_tau);
-  if (P.visc_var) itau = C(1) / ((ph * C(P.nu_l - P.nu_g) + C(P.nu_g)) * inv_cs2 + C(0.5));
+  C tau = C(P.tau);
+  if (P.visc_var) tau = (ph * C(P.nu_l - P.nu_g) + C(P.nu_g)) * inv_cs2 + C(0.5);
+  const C itau = C(1) / tau;
   const C ffac = C(1) - C(0.5) * itau;
   const C pc = M.p * inv_cs2;
   const C uu15 = C(0.5) * inv_cs2 * M.uu;
