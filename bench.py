@@ -96,9 +96,9 @@ def parse():
     ap.add_argument("--appendix-a-marks", type=lambda v: [int(x) for x in v.split(",")],
                     default=[100000, 300000, 1000000, 3000000, 6000000])
     ap.add_argument("--theta0-max-steps", type=int, default=4000000,
-                    help="step cap of the thetacheck section for configs[0]")
+                    help="step cap of the thetacheck section for the 128x64 FP64 case")
     ap.add_argument("--theta1-max-steps", type=int, default=1000000,
-                    help="step cap of the thetacheck section for configs[1]")
+                    help="step cap of the thetacheck section for the 1024x512 FP32 cases")
     ap.add_argument("--incline3d-slopes", default="1,0.5,0.25")
     ap.add_argument("--incline3d-start", default="paper", help="paper or cap")
     ap.add_argument("--sphere-start", default="paper", help="paper or cap")
@@ -467,7 +467,7 @@ def _angle_sweep(torch, P, cases, max_steps, chunk=100000, label="sweep"):
 
 
 def theta_check(a, torch, P, workloads):
-    """configs[0] (128x64 FP64, theta 60) and configs[1] (1024x512 FP32, theta
+    """The 128x64 FP64 flat-wall case (theta 60) and the 1024x512 FP32 ones (theta
     30..150) against their prescribed contact angles, each case started two
     ways: as specified (a circle centred on the wall plane, i.e. at 90 deg) and
     as the cap of the same radius that meets the wall at theta.  Each set runs
@@ -475,8 +475,8 @@ def theta_check(a, torch, P, workloads):
     polls (100k steps apart) or the step cap; theta is reported at the
     specified step count (5000 and 50k) and along the way."""
     out = {}
-    sets = (("configs0", "f64", [(128, 64, 20.0, 60.0, 4.0)], 5000, a.theta0_max_steps),
-            ("configs1", "f32", [(1024, 512, 80.0, th, 5.0) for th in (30.0, 60.0, 90.0, 120.0, 150.0)],
+    sets = (("flat_128x64_fp64", "f64", [(128, 64, 20.0, 60.0, 4.0)], 5000, a.theta0_max_steps),
+            ("flat_1024x512_fp32", "f32", [(1024, 512, 80.0, th, 5.0) for th in (30.0, 60.0, 90.0, 120.0, 150.0)],
              50000, a.theta1_max_steps))
     for name, st, specs, at, cap in sets:
         cases, labels = [], []
@@ -526,8 +526,8 @@ def theta_check(a, torch, P, workloads):
         g.close()
         out[name] = {"storage": st, "steps": steps, "wall_s": round(time.perf_counter() - t0, 1),
                      "converged": steps < cap, "angles": rows, "theta_history": marks}
-    out["workload"] = ("configs[0]: 128x64 D2Q9 FP64, R = 20, theta 60, W = 4; configs[1]: 1024x512 "
-                       "D2Q9 FP32, R = 80, theta 30..150, W = 5; sigma 1e-3, M 0.1, rho 10/1, tau 0.8")
+    out["workload"] = ("128x64 D2Q9 FP64, R = 20, theta 60, W = 4; 1024x512 D2Q9 FP32, R = 80, "
+                       "theta 30..150, W = 5; sigma 1e-3, M 0.1, rho 10/1, tau 0.8")
     return out
 
 
