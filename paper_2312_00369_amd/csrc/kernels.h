@@ -396,6 +396,61 @@ __device__ inline C ghost_from(const uint32_t* __restrict__ nodes, const C* __re
   return den > 0 ? ghost_value(num / C(den), chi_a) : C(0);
 }
 
+// ghost_from for a node of the padding face x = 0 or x = PX - 1 of a walled x
+// axis: of its 3^D block only the column at x = 1 (x = PX - 2) lies inside the
+// domain, so only those 3^(D-1) entries are read (the others are padding or
+// outside, never zeta = 1).  They are summed in ghost_from's order, so the
+// value is the same to the bit.
+template <class L, class C>
+__device__ inline C ghost_face(const uint32_t* __restrict__ nodes, const C* __restrict__ phi,
+                               const Geo& G, int x, int y, int z, C chi_a) {
+  constexpr int NZ = (L::D == 3) ? 3 : 1, NB = 3 * NZ;
+  const int P3[3] = {G.PX, G.PY, G.PZ}, c3[3] = {x, y, z};
+  const int xi = x == 0 ? 1 : G.PX - 2;
+  const nidx self = G.idx(x, y, z);
+  int qq[3][3];
+  bool vv[3][3];
+#pragma unroll
+  for (int d = 1; d < 3; ++d) {
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      int q = c3[d] + s - 1;
+      if (d == 2 && L::D == 2) q = c3[d];
+      if (G.per[d]) {
+        q += (q < 0) ? P3[d] : 0;
+        q -= (q >= P3[d]) ? P3[d] : 0;
+        vv[d][s] = true;
+      } else {
+        vv[d][s] = q >= 1 && q < P3[d] - 1;
+      }
+      qq[d][s] = q;
+    }
+  }
+  nidx at[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const int sy = k % 3, sz = (L::D == 3) ? k / 3 : 1;
+    at[k] = (vv[1][sy] && vv[2][sz]) ? G.idx(xi, qq[1][sy], qq[2][sz]) : self;
+  }
+  uint32_t w[NB];
+  C v[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    w[k] = nodes[at[k]];
+    v[k] = phi[at[k]];
+  }
+  C num = C(0);
+  int den = 0;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    if (w[k] & kZeta) {
+      num += v[k];
+      ++den;
+    }
+  }
+  return den > 0 ? ghost_value(num / C(den), chi_a) : C(0);
+}
+
 // mu of Eq. (chemical_potencial2) at a zeta = 1 entry: isotropic Laplacian
 // (Eq. Laplace) of phi and a_v = |grad eps| (Eq. avvv) from the neighbours.
 // Wall coefficient sqrt(2 kappa beta) cos(theta) of Eq. (chemical_potencial2) at
@@ -1058,7 +1113,7 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(const uint32_t* __restr
     if (row >= G.PY * G.PZ) return;
     const int x = (i & 1) ? G.PX - 1 : 0, y = row % G.PY, z = row / G.PY;
     const nidx n = G.idx(x, y, z);
-    if (nodes[n] & kGhost) phi[n] = ghost_from<L, C>(nodes, phi, G, x, y, z, chi_a);
+    if (nodes[n] & kGhost) phi[n] = ghost_face<L, C>(nodes, phi, G, x, y, z, chi_a);
     return;
   }
   const int lane = threadIdx.x % 64;
