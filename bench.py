@@ -39,11 +39,11 @@ def parse():
     ap.add_argument("--ny", type=int, default=512)
     ap.add_argument("--chunk", type=int, default=100, help="steps per captured HIP graph")
     ap.add_argument("--profile-steps", type=int, default=200)
-    ap.add_argument("--variant", default="tuned",
+    ap.add_argument("--variant", default="1",
                     help="2D step launch shape for the bench line: 'variant' or "
-                         "'variant:xcd_order', or 'tuned' for the autotuner's choice of "
-                         "variant on the shape (XCD order 0)")
-    ap.add_argument("--variant-twin", default="tuned",
+                         "'variant:xcd_order' (default: the library's default variant 1), or "
+                         "'tuned' for the autotuner's choice of variant on the shape (XCD order 0)")
+    ap.add_argument("--variant-twin", default="1",
                     help="the same for the 8192x4096 twin")
     ap.add_argument("--sections", default="main,twin,3d,precision,batched,serve,cpu",
                     help="comma list of: main (the 1024x512 line), twin (8192x4096), 3d "
